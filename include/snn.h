@@ -1,0 +1,212 @@
+/*
+ * snn.h -- C ABI of the MI355X (gfx950) minibatched spiking-network library.
+ *
+ * The library advances a batch of B independent clock-driven simulations of
+ * one network for T steps (Saunders et al., "Minibatch Processing in Spiking
+ * Neural Networks", AAAI-20, Implementation section): per-sample state is
+ * duplicated B times, weights and adaptive thresholds exist once and receive
+ * batch-reduced updates.  One step is: Poisson input encoding, the
+ * feed-forward synaptic contraction, recurrent inhibition, the fused
+ * adaptive-LIF / LIF update, STDP traces, the batch-reduced weight change with
+ * clamp and per-column normalisation, and the threshold update.
+ *
+ * Conventions
+ *  - Every call returns an snn_status; on failure snn_last_error() returns a
+ *    message (thread-local, valid until the next call on the same thread).
+ *  - Pointers named *_host are host memory, *_dev are device memory of the
+ *    device the handle was created on.  The caller owns every pointer passed
+ *    in; the library copies what it keeps.  The handle owns all simulation
+ *    state (weights, thresholds, voltages, traces).
+ *  - snn_run is stream-ordered and asynchronous on the handle's stream;
+ *    outputs are valid after snn_sync() or after the stream is synchronised.
+ *  - Handles are not thread-safe, except that snn_serve_submit and
+ *    snn_serve_poll may be called from any thread.
+ *  - No call allocates device memory except snn_create, snn_run when the batch
+ *    size grows beyond what was allocated, and snn_serve_create.
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNN_ABI_VERSION 1u
+
+typedef struct snn_net snn_net;       /* opaque network + state handle */
+typedef struct snn_server snn_server; /* opaque serving loop handle    */
+
+typedef enum {
+    SNN_OK = 0,
+    SNN_EINVAL = -1,    /* invalid argument or configuration                */
+    SNN_ENOMEM = -2,    /* batch above max_batch or above the HBM budget    */
+    SNN_EDEVICE = -3,   /* a HIP call failed; the message names it          */
+    SNN_EAGAIN = -4,    /* serving: request not finished yet                */
+    SNN_ENOTFOUND = -5, /* serving: unknown or already returned request id  */
+    SNN_ESTATE = -6     /* call not valid in the handle's current state     */
+} snn_status;
+
+/* Batch reduction of per-sample parameter updates (Reduction methods
+ * section: averaging by default, summation, per-synapse maximum per step as
+ * in the unsupervised-learning experiment). */
+typedef enum { SNN_REDUCE_SUM = 0, SNN_REDUCE_MEAN = 1, SNN_REDUCE_MAX = 2 } snn_reduce;
+
+/* Operand type of the synaptic contraction.  Weights are always kept as an
+ * FP32 master copy; BF16 / FP8(e4m3) are contraction copies of it. */
+typedef enum { SNN_FP32 = 0, SNN_BF16 = 1, SNN_FP8_E4M3 = 2 } snn_precision;
+
+/* How the T-step loop is executed.
+ *   PLAIN      one launch per kernel per step (encoder, contraction, neuron
+ *              update, plasticity), the straightforward per-step path;
+ *   FUSED      one column-partitioned launch per step carrying contraction,
+ *              neuron update and plasticity, encoder hoisted over all T;
+ *   PERSISTENT one cooperative launch for all T steps, state kept on chip;
+ *   AUTO       chosen by the library's autotuner for (batch, T). */
+typedef enum { SNN_PATH_PLAIN = 0, SNN_PATH_FUSED = 1, SNN_PATH_PERSISTENT = 2, SNN_PATH_AUTO = 3 } snn_path;
+
+/* One LIF population (Scaling and Unsupervised Learning sections).
+ * Voltages in mV, times in ms.  adaptive != 0 adds the shared threshold
+ * offset theta (+theta_plus per spike, decays with tau_theta_ms). */
+typedef struct {
+    double v_rest, v_reset, v_thresh, tau_ms;
+    int32_t refrac_steps, adaptive;
+    double theta_plus, tau_theta_ms;
+} snn_lif;
+
+typedef struct {
+    uint32_t abi_version;          /* must be SNN_ABI_VERSION                      */
+    uint32_t n_in, n_exc, n_inh;   /* n_inh = 0: no inhibitory layer; else = n_exc */
+    int32_t uniform_rate;          /* 1: every input fires at max_rate_hz          */
+    int32_t learn;                 /* 1: STDP, normalisation and theta active      */
+    int32_t trace_additive;        /* 0: trace set to 1 on a spike; 1: += 1        */
+    int32_t reduce;                /* snn_reduce                                   */
+    int32_t precision;             /* snn_precision                                */
+    int32_t path;                  /* snn_path                                     */
+    double dt_ms, max_rate_hz;     /* pixel p fires at p/255 * max_rate_hz          */
+    snn_lif exc, inh;
+    double w_ei;                   /* exc -> inh, one-to-one                        */
+    double w_ie;                   /* inh -> exc, to all but the partner            */
+    double nu_pre, nu_post;        /* depression on pre spike, potentiation on post */
+    double tau_pre_ms, tau_post_ms;
+    double w_min, w_max;           /* clamp after every update                      */
+    double norm;                   /* column sum target; <= 0 disables              */
+    uint64_t seed;                 /* Philox key of the Poisson encoder             */
+    uint32_t max_batch;            /* largest batch snn_run will accept             */
+    uint32_t reserved0;
+    uint64_t hbm_budget_bytes;     /* 0: no limit                                   */
+} snn_config;
+
+/* Device outputs of snn_run; any NULL pointer is skipped.
+ * Bit rasters hold bit (k % 32) of word k / 32 for neuron / input k.
+ *   counts     batch x n_exc u32, exc spike counts of this call (overwritten)
+ *   raster_in  T x batch x ceil(n_in/32) u32 input spikes
+ *   raster_exc T x batch x ceil(n_exc/32) u32, raster_inh likewise
+ *   v_exc      T x batch x n_exc f32 voltage after each step, v_inh likewise */
+typedef struct {
+    uint32_t *counts;
+    uint32_t *raster_in;
+    uint32_t *raster_exc;
+    uint32_t *raster_inh;
+    float *v_exc;
+    float *v_inh;
+} snn_outputs;
+
+#define SNN_RUN_RESET 1u /* episodic: reset per-sample state before step 0
+                            (Episodic vs. continuing simulation section) */
+
+/* Library ABI version (SNN_ABI_VERSION of the build). */
+uint32_t snn_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *snn_last_error(void);
+
+/* Create a network on the current HIP device.  `stream` is a hipStream_t
+ * (NULL = the default stream) on which all work is ordered.  Weights start
+ * at zero and theta at zero; call snn_set_weights before running.
+ * Errors: SNN_EINVAL (bad config or ABI version), SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_create(const snn_config *cfg, void *stream, snn_net **out);
+
+/* Wait for outstanding work and release every resource of the handle. */
+void snn_destroy(snn_net *net);
+
+/* Change the stream later work is ordered on. */
+snn_status snn_set_stream(snn_net *net, void *stream);
+
+/* Weights, host memory, row-major n_in x n_exc f32 (n = n_in * n_exc).
+ * The FP32 master copy is replaced; contraction copies are refreshed. */
+snn_status snn_set_weights(snn_net *net, const float *w_host, size_t n);
+snn_status snn_get_weights(snn_net *net, float *w_host, size_t n);
+
+/* Shared adaptive thresholds, host memory, n_exc f64 (kept in FP64). */
+snn_status snn_set_theta(snn_net *net, const double *theta_host, size_t n);
+snn_status snn_get_theta(snn_net *net, double *theta_host, size_t n);
+
+/* Select the batch reduction of weight and threshold updates (Reduction
+ * methods section).  Takes effect at the next step. */
+snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
+
+/* Select the execution path (snn_path) and contraction precision. */
+snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision);
+
+/* Advance `batch` samples by T steps (Implementation section).
+ *   images_dev batch x n_in u8 pixels (ignored when uniform_rate)
+ *   ids_dev    batch u64 sample ids; the encoder is keyed by (seed, id,
+ *              local step), never by the batch slot
+ *   flags      SNN_RUN_RESET for an episodic trial; a batch size different
+ *              from the previous call re-initialises state as well (Dynamic
+ *              minibatch size section)
+ * Errors: SNN_EINVAL (T = 0, batch = 0, NULL images without uniform_rate),
+ *         SNN_ENOMEM (batch > max_batch or over the HBM budget; nothing runs),
+ *         SNN_EDEVICE. */
+snn_status snn_run(snn_net *net, const uint8_t *images_dev, const uint64_t *ids_dev,
+                   uint32_t batch, uint32_t T, uint32_t flags, const snn_outputs *out);
+
+/* As snn_run, with the input spikes given instead of the Poisson encoder:
+ * in_bits_dev is T x batch x ceil(n_in/32) u32 (bit layout of raster_in). */
+snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, uint32_t batch, uint32_t T,
+                          uint32_t flags, const snn_outputs *out);
+
+/* Block until all work queued on the handle's stream has finished. */
+snn_status snn_sync(snn_net *net);
+
+/* Device bytes the handle would hold for `batch` samples (state, weights,
+ * scratch), the quantity compared with hbm_budget_bytes. */
+size_t snn_state_bytes(const snn_config *cfg, uint32_t batch);
+
+/* Continuous-batching inference server over a frozen network (learn must be
+ * 0).  Single-sample requests (Dynamic minibatch size section: queries one at
+ * a time) are admitted into free slots of a device-resident batch while
+ * slots and the HBM budget allow, advanced chunk_steps steps per launch, and
+ * retired when their own T is reached.  A request's result does not depend on
+ * which other requests share the batch.
+ *   max_slots   largest device batch; hbm_budget 0 = no limit
+ * snn_serve_create takes the network's weights at call time. */
+snn_status snn_serve_create(snn_net *frozen, uint32_t max_slots, uint64_t hbm_budget,
+                            uint32_t chunk_steps, snn_server **out);
+
+/* Queue one request: image_host n_in u8 (copied), T steps, sample id `id`.
+ * Returns its request id.  SNN_ENOMEM if one slot does not fit the budget. */
+snn_status snn_serve_submit(snn_server *srv, const uint8_t *image_host, uint64_t id, uint32_t T,
+                            uint64_t *req_id);
+
+/* Result of a finished request: counts_host n_exc u32 spike counts and the
+ * submit-to-completion latency in seconds.  SNN_EAGAIN while queued or
+ * running; SNN_ENOTFOUND for an unknown id or one already returned. */
+snn_status snn_serve_poll(snn_server *srv, uint64_t req_id, uint32_t *counts_host, double *latency_s);
+
+/* Serving statistics: requests completed, slot-steps executed, peak active
+ * slots, and the device time spent in launches (seconds). */
+snn_status snn_serve_stats(snn_server *srv, uint64_t *completed, uint64_t *slot_steps,
+                           uint32_t *peak_active, double *busy_s);
+
+/* Drain queued and running requests, then stop; later polls are invalid. */
+snn_status snn_serve_destroy(snn_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNN_H */

@@ -1,0 +1,60 @@
+// snn_dev.h -- shared definitions of the gfx950 kernels and the host runtime.
+//
+// Data layout in HBM (one network, batch B):
+//   columns j are grouped in blocks of JB consecutive post-synaptic neurons,
+//   g = j / JB, jj = j % JB; every per-neuron array and the weight matrix are
+//   block-major, so one column block (the unit a fused or plasticity
+//   workgroup owns) is one contiguous span:
+//     state(b, j)  at (g * B + b) * JB + jj        (v_exc, v_inh, x_post, rf)
+//     W(i, j)      at (g * n_in_pad + i) * JB + jj (FP32 master)
+//   inputs are padded to n_in_pad = 32 * in_words; pad inputs never spike
+//   and their weights stay 0.
+//   input spikes of step t: bits[t][b][w] (bit i % 32 of word i / 32) and the
+//   transpose bitsT[t][i][bw] (bit b % 32 of word b / 32).
+//   presynaptic traces x_pre[t & 1][b][i]; inhibitory spike counts per sample
+//   C[t % 3][b].
+#pragma once
+#include <stdint.h>
+
+namespace snn {
+
+struct LifP {
+    float v_rest, v_reset, v_th, alpha;  // alpha = exp(-dt / tau), rounded to f32
+    int refrac;                          // refractory steps (<= 127)
+};
+
+struct Params {
+    int n_in, n_in_pad, in_words;
+    int n_exc, n_pad, jb, nblk;
+    int has_inh;
+    int B, bwords;            // batch, ceil(B / 32)
+    int learn, adaptive, trace_add, reduce;
+    int uniform_rate;
+    uint32_t thr_uniform;
+    LifP exc, inh;
+    float w_ei, w_ie;
+    float lam_pre, lam_post, nu_pre, nu_post, w_min, w_max;
+    float inv_B;
+    double norm, beta, theta_plus, inv_Bd;
+    uint64_t seed;
+};
+
+// Per-neuron packed flags (u16): low byte excitatory, high byte inhibitory;
+// in each byte bits 0..6 hold the refractory count, bit 7 the spike of the
+// previous step.
+constexpr uint32_t RF_SPIKE = 0x80u;
+constexpr uint32_t RF_COUNT = 0x7Fu;
+
+// Output pointers of one run (device; nullptr = not recorded).
+struct Outs {
+    uint32_t *counts;      // B x n_exc
+    uint32_t *raster_in;   // T x B x in_words
+    uint32_t *raster_exc;  // T x B x exc_words
+    uint32_t *raster_inh;  // T x B x exc_words
+    float *v_exc;          // T x B x n_exc
+    float *v_inh;          // T x B x n_exc
+};
+
+enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2 };
+
+}  // namespace snn

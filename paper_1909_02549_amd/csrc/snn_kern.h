@@ -1,0 +1,166 @@
+// snn_kern.h -- device helpers shared by the plain, fused and persistent
+// kernels (one definition of each arithmetic step of the method).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "snn_dev.h"
+
+namespace snn {
+
+__host__ __device__ constexpr size_t align16(size_t n) { return (n + 15) & ~(size_t)15; }
+
+// Philox4x64-10: ten rounds; per round two 64x64->128-bit products of the
+// counter words 0 and 2 with the round multipliers, mixed with words 1 and 3
+// and the key, the key advanced by the two Weyl increments between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4])
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Nearest-spike (or additive) trace: decay by lam, then 1 (or +1) on a spike.
+__device__ __forceinline__ float trace_step(float x, float lam, uint32_t spike, int additive)
+{
+    x *= lam;
+    if (spike) x = additive ? x + 1.f : 1.f;
+    return x;
+}
+
+// Batch reduction step of one term (terms are non-negative traces, the
+// accumulator starts at 0, so max over the spiking samples equals the max
+// over all B terms).
+__device__ __forceinline__ float reduce2(int mode, float acc, float x)
+{
+    return mode == RED_MAX ? fmaxf(acc, x) : acc + x;
+}
+
+// W <- clamp(W + nu_post P - nu_pre D); mean divides the sums by B.
+__device__ __forceinline__ float stdp_apply(const Params &p, float w, float P, float D)
+{
+    if (p.reduce == RED_MEAN) {
+        P *= p.inv_B;
+        D *= p.inv_B;
+    }
+    w = w + p.nu_post * P - p.nu_pre * D;
+    return fminf(fmaxf(w, p.w_min), p.w_max);
+}
+
+// Threshold offset seen by the excitatory neurons this step: theta decays by
+// beta at the start of every learning step; frozen when not learning.
+__device__ __forceinline__ float theta_offset(const Params &p, double theta)
+{
+    if (!p.adaptive) return 0.f;
+    return (float)(p.learn ? theta * p.beta : theta);
+}
+
+// theta <- theta * beta + theta_plus * R_b(s_exc[b, j]) from the column's
+// spike count (sum: count, mean: count / B, max: any).
+__device__ __forceinline__ double theta_step(const Params &p, double theta, int count)
+{
+    double r = (double)count;
+    if (p.reduce == RED_MEAN) r = (double)count / (double)p.B;
+    else if (p.reduce == RED_MAX) r = count > 0 ? 1.0 : 0.0;
+    return theta * p.beta + p.theta_plus * r;
+}
+
+struct NeuronState {
+    float ve, vi;
+    uint32_t rf;
+    float xpost;
+};
+
+// One step of the excitatory adaptive-LIF neuron j and its inhibitory
+// partner for one sample:
+//   I_exc = I_ff + w_ie * (C_inh(t-1) - s_inh(t-1)[j])   (all-but-self)
+//   I_inh = w_ei * s_exc(t-1)[j]                          (one-to-one)
+//   v <- v_rest + (v - v_rest) * alpha; if refractory: count down, input
+//   discarded; else v += I, spike when v >= v_th (+ theta), then v_reset and
+//   refrac steps.  Post trace decays and is set on an exc spike.
+__device__ __forceinline__ void neuron_update(const Params &p, float I_ff, uint32_t Cprev, float th_off,
+                                              NeuronState &st, bool &se, bool &si)
+{
+    const uint32_t re = st.rf & 0xFFu, ri = (st.rf >> 8) & 0xFFu;
+    const bool se_prev = (re & RF_SPIKE) != 0u;
+    const bool si_prev = (ri & RF_SPIKE) != 0u;
+    uint32_t ce = re & RF_COUNT, ci = ri & RF_COUNT;
+    float Ie = I_ff;
+    if (p.has_inh) Ie += p.w_ie * (float)((int)Cprev - (int)si_prev);
+    st.ve = p.exc.v_rest + (st.ve - p.exc.v_rest) * p.exc.alpha;
+    se = false;
+    if (ce > 0u) {
+        ce -= 1u;
+    } else {
+        st.ve += Ie;
+        if (st.ve >= p.exc.v_th + th_off) {
+            se = true;
+            st.ve = p.exc.v_reset;
+            ce = (uint32_t)p.exc.refrac;
+        }
+    }
+    si = false;
+    if (p.has_inh) {
+        const float Ii = se_prev ? p.w_ei : 0.f;
+        st.vi = p.inh.v_rest + (st.vi - p.inh.v_rest) * p.inh.alpha;
+        if (ci > 0u) {
+            ci -= 1u;
+        } else {
+            st.vi += Ii;
+            if (st.vi >= p.inh.v_th) {
+                si = true;
+                st.vi = p.inh.v_reset;
+                ci = (uint32_t)p.inh.refrac;
+            }
+        }
+    }
+    if (p.learn) st.xpost = trace_step(st.xpost, p.lam_post, se, p.trace_add);
+    st.rf = (ce | (se ? RF_SPIKE : 0u)) | ((ci | (si ? RF_SPIKE : 0u)) << 8);
+}
+
+// Optional per-call outputs of neuron (b, j) at step k of the call.
+__device__ __forceinline__ void write_outputs(const Params &p, const Outs &o, int k, int b, int j, bool se,
+                                              bool si, float ve, float vi)
+{
+    const int words = (p.n_exc + 31) >> 5;
+    if (o.counts && se) o.counts[(size_t)b * p.n_exc + j] += 1u;
+    if (o.raster_exc && se)
+        atomicOr(&o.raster_exc[((size_t)k * p.B + b) * words + (j >> 5)], 1u << (j & 31));
+    if (o.raster_inh && si)
+        atomicOr(&o.raster_inh[((size_t)k * p.B + b) * words + (j >> 5)], 1u << (j & 31));
+    if (o.v_exc) o.v_exc[((size_t)k * p.B + b) * p.n_exc + j] = ve;
+    if (o.v_inh && p.has_inh) o.v_inh[((size_t)k * p.B + b) * p.n_exc + j] = vi;
+}
+
+// kernels (snn_kernels.hip)
+__global__ void k_encode(Params p, const uint8_t *img, const uint64_t *ids, const uint32_t *thr_lut,
+                         const uint32_t *tl, uint64_t tbase, const uint32_t *forced, uint32_t *bits,
+                         uint32_t *bitsT, uint32_t *raster_in, int raster_k0);
+__global__ void k_xpre(Params p, const uint32_t *bits_t, const float *xprev, float *xcur);
+__global__ void k_contract(Params p, const float *W, const uint32_t *bits_t, float *I);
+__global__ void k_neuron(Params p, const float *I, const double *theta, const uint32_t *Cprev, uint32_t *Ccur,
+                         uint32_t *Cnext, float *v_exc, float *v_inh, uint16_t *rf, float *x_post, int k, Outs o);
+__global__ void k_plastic(Params p, float *W, double *theta, const uint16_t *rf, const float *x_post,
+                          const float *x_pre, const uint32_t *bitsT_t);
+__global__ void k_reset(Params p, float *v_exc, float *v_inh, uint16_t *rf, float *x_post, float *x_pre,
+                        uint32_t *C, const uint8_t *mask);
+__global__ void k_fill_u32(uint32_t *dst, uint32_t value, size_t n);
+
+}  // namespace snn

@@ -1,0 +1,272 @@
+// snn_kernels.hip -- gfx950 kernels of one minibatched SNN timestep.
+//
+// One step (Implementation and Unsupervised Learning sections of Saunders et
+// al., AAAI-20): Poisson input encoding; feed-forward current from the
+// input spikes and the shared weights; recurrent inhibition from the previous
+// step's inhibitory spikes; the excitatory adaptive-LIF and inhibitory LIF
+// updates; STDP traces; the batch-reduced weight change with clamp and
+// column normalisation; the shared threshold update.
+//
+// This file holds the building blocks and the plain per-step kernels.  The
+// fused and persistent step kernels live in snn_fused.hip.
+#include <hip/hip_runtime.h>
+
+#include "snn_dev.h"
+#include "snn_kern.h"
+
+namespace snn {
+
+// ---------------------------------------------------------------------------
+// Encoder: Philox4x64-10 counter-based generator (Salmon et al., SC'11).
+// Counter (i / 8, t, id, 0), key (seed, 0); the four 64-bit outputs give eight
+// 32-bit uniforms, low half first; input i spikes when its uniform is below
+// the rate threshold thr[pixel] (thr / 2^32 = rate * dt).
+// One 64-lane wave encodes one 32-input word for 64 consecutive samples and
+// transposes the 32x64 bit tile with ballots for the per-input layout.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_encode(Params p, const uint8_t *__restrict__ img,
+                                               const uint64_t *__restrict__ ids,
+                                               const uint32_t *__restrict__ thr_lut,
+                                               const uint32_t *__restrict__ tl, uint64_t tbase,
+                                               const uint32_t *__restrict__ forced,
+                                               uint32_t *__restrict__ bits, uint32_t *__restrict__ bitsT,
+                                               uint32_t *__restrict__ raster_in, int raster_k0)
+{
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x * 64 + lane;
+    const int w = blockIdx.y;
+    const int k = blockIdx.z;
+    uint32_t word = 0;
+    if (b < p.B) {
+        const int i_base = 32 * w;
+        if (forced) {
+            word = forced[((size_t)k * p.B + b) * p.in_words + w];
+        } else {
+            const uint64_t t = tbase + (uint64_t)k + (tl ? (uint64_t)tl[b] : 0ull);
+            const uint64_t id = ids[b];
+            for (int q = 0; q < 4; ++q) {
+                const int i0 = i_base + 8 * q;
+                if (i0 >= p.n_in) break;
+                uint64_t r[4];
+                philox4x64_10((uint64_t)(i0 >> 3), t, id, 0ull, p.seed, 0ull, r);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int i = i0 + e;
+                    if (i < p.n_in) {
+                        const uint32_t u = (e & 1) ? (uint32_t)(r[e >> 1] >> 32) : (uint32_t)r[e >> 1];
+                        const uint32_t thr = p.uniform_rate ? p.thr_uniform : thr_lut[img[(size_t)b * p.n_in + i]];
+                        word |= (uint32_t)(u < thr) << (8 * q + e);
+                    }
+                }
+            }
+        }
+        const int valid = p.n_in - i_base;
+        if (valid < 32) word &= valid <= 0 ? 0u : ((1u << valid) - 1u);
+        bits[((size_t)k * p.B + b) * p.in_words + w] = word;
+        if (raster_in) raster_in[((size_t)(raster_k0 + k) * p.B + b) * p.in_words + w] = word;
+    }
+    uint64_t mine = 0;
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+        const uint64_t m = __ballot((word >> e) & 1u);
+        if (lane == e) mine = m;
+    }
+    if (lane < 32) {
+        const size_t base = ((size_t)k * p.n_in_pad + (size_t)(32 * w + lane)) * p.bwords + 2 * blockIdx.x;
+        bitsT[base] = (uint32_t)mine;
+        if (2 * (int)blockIdx.x + 1 < p.bwords) bitsT[base + 1] = (uint32_t)(mine >> 32);
+    }
+}
+
+// Presynaptic traces of one step: x <- lam * x, then 1 (or x + 1) on a spike.
+__global__ void k_xpre(Params p, const uint32_t *__restrict__ bits_t, const float *__restrict__ xprev,
+                       float *__restrict__ xcur)
+{
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (size_t)p.B * p.n_in_pad) return;
+    const int b = (int)(n / p.n_in_pad), i = (int)(n % p.n_in_pad);
+    const uint32_t s = (bits_t[(size_t)b * p.in_words + (i >> 5)] >> (i & 31)) & 1u;
+    xcur[n] = trace_step(xprev[n], p.lam_pre, s, p.trace_add);
+}
+
+// Plain feed-forward contraction: I[b, j] = sum over inputs i that spiked in
+// sample b of W[i, j], summed in increasing i.  One thread per (b, j).
+__global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t *__restrict__ bits_t,
+                           float *__restrict__ I)
+{
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)p.nblk * p.B * p.jb;
+    if (n >= total) return;
+    const int jj = (int)(n % p.jb);
+    const size_t gb = n / p.jb;
+    const int b = (int)(gb % p.B);
+    const int g = (int)(gb / p.B);
+    const float *Wg = W + (size_t)g * p.n_in_pad * p.jb + jj;
+    const uint32_t *sb = bits_t + (size_t)b * p.in_words;
+    float acc = 0.f;
+    for (int w = 0; w < p.in_words; ++w) {
+        uint32_t m = sb[w];
+        while (m) {
+            const int i = 32 * w + __builtin_ctz(m);
+            m &= m - 1;
+            acc += Wg[(size_t)i * p.jb];
+        }
+    }
+    I[n] = acc;
+}
+
+// Plain neuron update, one thread per (b, j): recurrent currents, both
+// layers, post trace, spike outputs.
+__global__ void k_neuron(Params p, const float *__restrict__ I, const double *__restrict__ theta,
+                         const uint32_t *__restrict__ Cprev, uint32_t *__restrict__ Ccur,
+                         uint32_t *__restrict__ Cnext, float *__restrict__ v_exc, float *__restrict__ v_inh,
+                         uint16_t *__restrict__ rf, float *__restrict__ x_post, int k, Outs o)
+{
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)p.nblk * p.B * p.jb;
+    if (n >= total) return;
+    const int jj = (int)(n % p.jb);
+    const size_t gb = n / p.jb;
+    const int b = (int)(gb % p.B);
+    const int g = (int)(gb / p.B);
+    const int j = g * p.jb + jj;
+    if (j == 0 && Cnext) Cnext[b] = 0u;
+    if (j >= p.n_exc) return;
+    NeuronState st{v_exc[n], p.has_inh ? v_inh[n] : 0.f, (uint32_t)rf[n], p.learn ? x_post[n] : 0.f};
+    const float th_off = theta_offset(p, theta[j]);
+    bool se, si;
+    neuron_update(p, I[n], p.has_inh ? Cprev[b] : 0u, th_off, st, se, si);
+    v_exc[n] = st.ve;
+    if (p.has_inh) v_inh[n] = st.vi;
+    rf[n] = (uint16_t)st.rf;
+    if (p.learn) x_post[n] = st.xpost;
+    if (si) atomicAdd(&Ccur[b], 1u);
+    write_outputs(p, o, k, b, j, se, si, st.ve, st.vi);
+}
+
+// Plain plasticity, one workgroup per column block:
+//   P[i, j] = R_b x_pre[b, i] s_exc[b, j]   (potentiation on a post spike)
+//   D[i, j] = R_b s_in[b, i] x_post[b, j]   (depression on a pre spike)
+//   W <- clamp(W + nu_post P - nu_pre D), column sums in FP64, W[:, j] *=
+//   norm / c_j; theta <- theta * beta + theta_plus * R_b s_exc[b, j].
+// R is sum, mean (sum / B) or max, applied to P and D separately.
+__global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W, double *__restrict__ theta,
+                                                 const uint16_t *__restrict__ rf,
+                                                 const float *__restrict__ x_post,
+                                                 const float *__restrict__ x_pre,
+                                                 const uint32_t *__restrict__ bitsT_t)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = blockIdx.x;
+    const int JB = p.jb;
+    const int tid = threadIdx.x;
+    uint32_t *spk = reinterpret_cast<uint32_t *>(smem);                      // JB * bwords
+    double *part = reinterpret_cast<double *>(smem + align16((size_t)JB * p.bwords * 4)); // R * JB
+    double *scale = part + (size_t)(blockDim.x / JB) * JB;                  // JB
+
+    for (int q = tid; q < JB * p.bwords; q += blockDim.x) spk[q] = 0u;
+    __syncthreads();
+    const size_t sbase = (size_t)g * p.B * JB;
+    for (int q = tid; q < p.B * JB; q += blockDim.x) {
+        if (rf[sbase + q] & RF_SPIKE) {
+            const int b = q / JB, jj = q % JB;
+            atomicOr(&spk[jj * p.bwords + (b >> 5)], 1u << (b & 31));
+        }
+    }
+    __syncthreads();
+
+    const int R = blockDim.x / JB;
+    const int jj = tid % JB;
+    const int r0 = tid / JB;
+    const int j = g * JB + jj;
+    const bool col_ok = r0 < R && j < p.n_exc;
+    float *Wg = W + (size_t)g * p.n_in_pad * JB;
+    double cs = 0.0;
+    if (col_ok) {
+        for (int i = r0; i < p.n_in; i += R) {
+            float D = 0.f, P = 0.f;
+            const uint32_t *bt = bitsT_t + (size_t)i * p.bwords;
+            for (int bw = 0; bw < p.bwords; ++bw) {
+                uint32_t m = bt[bw];
+                while (m) {
+                    const int b = 32 * bw + __builtin_ctz(m);
+                    m &= m - 1;
+                    D = reduce2(p.reduce, D, x_post[sbase + (size_t)b * JB + jj]);
+                }
+            }
+            const uint32_t *sp = spk + jj * p.bwords;
+            for (int bw = 0; bw < p.bwords; ++bw) {
+                uint32_t m = sp[bw];
+                while (m) {
+                    const int b = 32 * bw + __builtin_ctz(m);
+                    m &= m - 1;
+                    P = reduce2(p.reduce, P, x_pre[(size_t)b * p.n_in_pad + i]);
+                }
+            }
+            const float w = stdp_apply(p, Wg[(size_t)i * JB + jj], P, D);
+            Wg[(size_t)i * JB + jj] = w;
+            cs += (double)w;
+        }
+    }
+    if (r0 < R) part[r0 * JB + jj] = cs;
+    __syncthreads();
+    if (r0 == 0) {
+        double c = 0.0;
+        for (int q = 0; q < R; ++q) c += part[q * JB + jj];
+        scale[jj] = (p.norm > 0.0 && c > 0.0) ? p.norm / c : 1.0;
+        if (j < p.n_exc && p.adaptive) {
+            int cnt = 0;
+            for (int bw = 0; bw < p.bwords; ++bw) cnt += __builtin_popcount(spk[jj * p.bwords + bw]);
+            theta[j] = theta_step(p, theta[j], cnt);
+        }
+    }
+    __syncthreads();
+    if (col_ok && p.norm > 0.0) {
+        const double s = scale[jj];
+        for (int i = r0; i < p.n_in; i += R) {
+            const size_t q = (size_t)i * JB + jj;
+            Wg[q] = (float)((double)Wg[q] * s);
+        }
+    }
+}
+
+// Episodic reset of per-sample state (all samples, or those with mask[b]).
+__global__ void k_reset(Params p, float *__restrict__ v_exc, float *__restrict__ v_inh, uint16_t *__restrict__ rf,
+                        float *__restrict__ x_post, float *__restrict__ x_pre, uint32_t *__restrict__ C,
+                        const uint8_t *__restrict__ mask)
+{
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t ns = (size_t)p.nblk * p.B * p.jb;
+    if (n < ns) {
+        const int b = (int)((n / p.jb) % p.B);
+        if (!mask || mask[b]) {
+            v_exc[n] = p.exc.v_rest;
+            v_inh[n] = p.inh.v_rest;
+            rf[n] = 0;
+            x_post[n] = 0.f;
+        }
+    }
+    const size_t nx = (size_t)p.B * p.n_in_pad;
+    if (n < nx) {
+        const int b = (int)(n / p.n_in_pad);
+        if (!mask || mask[b]) {
+            x_pre[n] = 0.f;
+            x_pre[nx + n] = 0.f;
+        }
+    }
+    if (n < (size_t)p.B) {
+        if (!mask || mask[n]) {
+            C[n] = 0u;
+            C[p.B + n] = 0u;
+            C[2 * p.B + n] = 0u;
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ dst, uint32_t value, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        dst[q] = value;
+}
+
+}  // namespace snn

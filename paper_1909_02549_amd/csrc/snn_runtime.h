@@ -1,0 +1,54 @@
+// snn_runtime.h -- the network handle behind the opaque snn_net of snn.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/snn.h"
+#include "snn_dev.h"
+
+// Steps encoded per encoder launch (bounds the input-spike buffers).
+constexpr uint32_t kChunk = 256;
+
+struct snn_net {
+    snn_config cfg{};
+    snn::Params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cus = 256;
+    int path = 0;
+    int precision = 0;
+
+    // shared parameters
+    float *W = nullptr;          // FP32 master, block layout
+    void *Wq = nullptr;          // BF16 / FP8 contraction copy (MFMA path)
+    double *theta = nullptr;     // n_pad, FP64
+    uint32_t *thr_lut = nullptr; // 256 spike thresholds
+
+    // per-sample state, capacity cap_B
+    uint32_t cap_B = 0, cur_B = 0;
+    float *v_exc = nullptr, *v_inh = nullptr, *x_post = nullptr, *I = nullptr;
+    uint16_t *rf = nullptr;
+    float *x_pre = nullptr;      // 2 x B x n_in_pad
+    uint32_t *C = nullptr;       // 3 x B
+    uint32_t *bits = nullptr;    // kChunk x B x in_words
+    uint32_t *bitsT = nullptr;   // kChunk x n_in_pad x bwords
+    uint8_t *flags_mask = nullptr;
+
+    uint64_t gstep = 0;  // steps since the state was initialised
+    uint64_t tloc = 0;   // local step of the current samples (encoder counter)
+
+    ~snn_net();
+    void free_state();
+    snn_status ensure_state(uint32_t B);
+    void set_batch(uint32_t B);
+    snn_status reset_state(const uint8_t *mask_dev);
+    snn_status refresh_weight_copies();
+    void graphs_invalidate();
+    snn_status encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase, int steps,
+                            const uint32_t *forced, uint32_t *raster_in, int raster_k0);
+    snn_status plain_step(int kk, int k, const snn::Outs &o);
+    snn_status run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch, uint32_t T,
+                   uint32_t flags, const snn_outputs *out);
+    snn_status run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t T,
+                         const snn::Outs &o);
+    int choose_path(uint32_t batch, uint32_t T);
+};

@@ -1,0 +1,537 @@
+// snn_runtime.hip -- host side of the C ABI declared in include/snn.h:
+// handle, device buffers, batch (re)initialisation, the T-step drivers of the
+// plain, fused and persistent paths, weights / theta transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+#include "snn_dev.h"
+#include "snn_kern.h"
+#include "snn_runtime.h"
+
+using namespace snn;
+
+static thread_local std::string g_err;
+
+static snn_status fail(snn_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(call)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail(SNN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+extern "C" uint32_t snn_abi_version(void) { return SNN_ABI_VERSION; }
+extern "C" const char *snn_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+
+static int device_cu_count()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    return cus;
+}
+
+// Column block width: enough blocks to give every CU one block when the
+// layer is large, at least 16 columns per block otherwise.
+static int choose_jb(uint32_t n_exc, int cus)
+{
+    int jb = (int)((n_exc + (uint32_t)cus - 1) / (uint32_t)cus);
+    if (jb < 16) jb = 16;
+    if (jb > 64) jb = 64;
+    return jb;
+}
+
+static void fill_dims(Params &p, const snn_config &c, int jb)
+{
+    p.n_in = (int)c.n_in;
+    p.in_words = (int)((c.n_in + 31) / 32);
+    p.n_in_pad = 32 * p.in_words;
+    p.n_exc = (int)c.n_exc;
+    p.jb = jb;
+    p.nblk = (int)((c.n_exc + jb - 1) / jb);
+    p.n_pad = p.nblk * jb;
+    p.has_inh = c.n_inh > 0;
+}
+
+static size_t state_bytes(const Params &p, uint32_t B, uint32_t chunk)
+{
+    const size_t ns = (size_t)p.n_pad * B;
+    const size_t bw = (B + 31) / 32;
+    size_t s = 0;
+    s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
+    s += 2 * (size_t)B * p.n_in_pad * 4;            // x_pre
+    s += 3 * (size_t)B * 4;                         // C
+    s += (size_t)chunk * B * p.in_words * 4;        // bits
+    s += (size_t)chunk * p.n_in_pad * bw * 4;       // bitsT
+    return s;
+}
+
+static size_t param_bytes(const Params &p)
+{
+    return (size_t)p.n_in_pad * p.n_pad * (4 + 2 + 1) + (size_t)p.n_pad * 8 + 1024;
+}
+
+static snn_status validate(const snn_config *c)
+{
+    if (!c) return fail(SNN_EINVAL, "snn_config is NULL");
+    if (c->abi_version != SNN_ABI_VERSION) return fail(SNN_EINVAL, "abi_version mismatch");
+    if (c->n_in == 0 || c->n_exc == 0) return fail(SNN_EINVAL, "n_in and n_exc must be > 0");
+    if (c->n_in > (1u << 20) || c->n_exc > (1u << 22)) return fail(SNN_EINVAL, "layer size too large");
+    if (c->n_inh != 0 && c->n_inh != c->n_exc)
+        return fail(SNN_EINVAL, "n_inh must be 0 or equal to n_exc (one-to-one exc->inh)");
+    if (!(c->dt_ms > 0) || !(c->exc.tau_ms > 0) || (c->n_inh && !(c->inh.tau_ms > 0)))
+        return fail(SNN_EINVAL, "dt and time constants must be > 0");
+    if (c->exc.refrac_steps < 0 || c->exc.refrac_steps > 127 || c->inh.refrac_steps < 0 ||
+        c->inh.refrac_steps > 127)
+        return fail(SNN_EINVAL, "refrac_steps must be in [0, 127]");
+    if (c->reduce < 0 || c->reduce > 2) return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean) or 2 (max)");
+    if (c->precision < 0 || c->precision > 2) return fail(SNN_EINVAL, "precision must be 0, 1 or 2");
+    if (c->path < 0 || c->path > 3) return fail(SNN_EINVAL, "path must be 0..3");
+    if (c->learn && (!(c->tau_pre_ms > 0) || !(c->tau_post_ms > 0)))
+        return fail(SNN_EINVAL, "trace time constants must be > 0");
+    if (c->learn && c->exc.adaptive && !(c->exc.tau_theta_ms > 0))
+        return fail(SNN_EINVAL, "tau_theta_ms must be > 0");
+    if (c->w_min > c->w_max) return fail(SNN_EINVAL, "w_min > w_max");
+    if (c->max_batch == 0) return fail(SNN_EINVAL, "max_batch must be > 0");
+    double prob = c->max_rate_hz * c->dt_ms / 1000.0;
+    if (!(prob >= 0.0) || prob > 1.0) return fail(SNN_EINVAL, "max_rate_hz * dt must be a probability");
+    return SNN_OK;
+}
+
+// Spike threshold of pixel value `pixel`: floor(rate * dt * 2^32) with
+// rate = pixel / 255 * max_rate (or max_rate for uniform inputs).
+static uint32_t rate_threshold(const snn_config &c, int pixel, bool uniform)
+{
+    const double prob = uniform ? c.max_rate_hz * c.dt_ms / 1000.0
+                                : (double)pixel * c.max_rate_hz * c.dt_ms / (255.0 * 1000.0);
+    double thr = std::floor(prob * 4294967296.0);
+    thr = std::min(std::max(thr, 0.0), 4294967295.0);
+    return (uint32_t)thr;
+}
+
+static void fill_params(Params &p, const snn_config &c)
+{
+    auto lif = [&](const snn_lif &l) {
+        LifP q;
+        q.v_rest = (float)l.v_rest;
+        q.v_reset = (float)l.v_reset;
+        q.v_th = (float)l.v_thresh;
+        q.alpha = (float)std::exp(-c.dt_ms / l.tau_ms);
+        q.refrac = l.refrac_steps;
+        return q;
+    };
+    p.exc = lif(c.exc);
+    p.inh = c.n_inh ? lif(c.inh) : LifP{0.f, 0.f, 0.f, 0.f, 0};
+    p.learn = c.learn != 0;
+    p.adaptive = c.exc.adaptive != 0;
+    p.trace_add = c.trace_additive != 0;
+    p.reduce = c.reduce;
+    p.uniform_rate = c.uniform_rate != 0;
+    p.thr_uniform = rate_threshold(c, 0, true);
+    p.w_ei = (float)c.w_ei;
+    p.w_ie = (float)c.w_ie;
+    p.lam_pre = c.learn ? (float)std::exp(-c.dt_ms / c.tau_pre_ms) : 0.f;
+    p.lam_post = c.learn ? (float)std::exp(-c.dt_ms / c.tau_post_ms) : 0.f;
+    p.nu_pre = (float)c.nu_pre;
+    p.nu_post = (float)c.nu_post;
+    p.w_min = (float)c.w_min;
+    p.w_max = (float)c.w_max;
+    p.norm = c.norm;
+    p.beta = (c.learn && c.exc.adaptive) ? std::exp(-c.dt_ms / c.exc.tau_theta_ms) : 1.0;
+    p.theta_plus = c.exc.theta_plus;
+    p.seed = c.seed;
+    p.B = 0;
+    p.bwords = 0;
+    p.inv_B = 0.f;
+    p.inv_Bd = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// handle lifetime
+// ---------------------------------------------------------------------------
+
+snn_net::~snn_net()
+{
+    free_state();
+    (void)hipFree(W);
+    (void)hipFree(theta);
+    (void)hipFree(thr_lut);
+    (void)hipFree(Wq);
+}
+
+void snn_net::free_state()
+{
+    for (void *q : {(void *)v_exc, (void *)v_inh, (void *)x_post, (void *)I, (void *)rf, (void *)x_pre, (void *)C,
+                    (void *)bits, (void *)bitsT, (void *)flags_mask})
+        if (q) (void)hipFree(q);
+    v_exc = v_inh = x_post = I = x_pre = nullptr;
+    rf = nullptr;
+    C = bits = bitsT = nullptr;
+    flags_mask = nullptr;
+    cap_B = 0;
+    cur_B = 0;
+}
+
+extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **out)
+{
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    snn_status st = validate(cfg);
+    if (st != SNN_OK) return st;
+    snn_net *n = new (std::nothrow) snn_net();
+    if (!n) return fail(SNN_ENOMEM, "host allocation failed");
+    n->cfg = *cfg;
+    n->stream = (hipStream_t)stream;
+    HIP_TRY(hipGetDevice(&n->device));
+    n->cus = device_cu_count();
+    fill_dims(n->p, *cfg, choose_jb(cfg->n_exc, n->cus));
+    fill_params(n->p, *cfg);
+    n->path = cfg->path;
+    n->precision = cfg->precision;
+    if (cfg->hbm_budget_bytes && param_bytes(n->p) > cfg->hbm_budget_bytes) {
+        delete n;
+        return fail(SNN_ENOMEM, "weights alone exceed hbm_budget_bytes");
+    }
+    const size_t nw = (size_t)n->p.n_in_pad * n->p.n_pad;
+    hipError_t e = hipMalloc(&n->W, nw * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&n->theta, (size_t)n->p.n_pad * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&n->thr_lut, 256 * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete n;
+        return fail(SNN_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    std::vector<uint32_t> lut(256);
+    for (int q = 0; q < 256; ++q) lut[q] = rate_threshold(*cfg, q, false);
+    e = hipMemcpy(n->thr_lut, lut.data(), 256 * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->W, 0, nw * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(n->theta, 0, (size_t)n->p.n_pad * sizeof(double));
+    if (e != hipSuccess) {
+        delete n;
+        return fail(SNN_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = n;
+    return SNN_OK;
+}
+
+extern "C" void snn_destroy(snn_net *net)
+{
+    if (!net) return;
+    if (net->stream) (void)hipStreamSynchronize(net->stream);
+    else (void)hipDeviceSynchronize();
+    delete net;
+}
+
+extern "C" snn_status snn_set_stream(snn_net *net, void *stream)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    net->stream = (hipStream_t)stream;
+    net->graphs_invalidate();
+    return SNN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// weights and thresholds
+// ---------------------------------------------------------------------------
+
+extern "C" snn_status snn_set_weights(snn_net *net, const float *w, size_t n)
+{
+    if (!net || !w) return fail(SNN_EINVAL, "NULL argument");
+    const Params &p = net->p;
+    if (n != (size_t)p.n_in * p.n_exc) return fail(SNN_EINVAL, "n must equal n_in * n_exc");
+    std::vector<float> blk((size_t)p.n_in_pad * p.n_pad, 0.f);
+    for (int i = 0; i < p.n_in; ++i)
+        for (int j = 0; j < p.n_exc; ++j) {
+            const int g = j / p.jb, jj = j % p.jb;
+            blk[((size_t)g * p.n_in_pad + i) * p.jb + jj] = w[(size_t)i * p.n_exc + j];
+        }
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(hipMemcpy(net->W, blk.data(), blk.size() * sizeof(float), hipMemcpyHostToDevice));
+    return net->refresh_weight_copies();
+}
+
+extern "C" snn_status snn_get_weights(snn_net *net, float *w, size_t n)
+{
+    if (!net || !w) return fail(SNN_EINVAL, "NULL argument");
+    const Params &p = net->p;
+    if (n != (size_t)p.n_in * p.n_exc) return fail(SNN_EINVAL, "n must equal n_in * n_exc");
+    std::vector<float> blk((size_t)p.n_in_pad * p.n_pad);
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(hipMemcpy(blk.data(), net->W, blk.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int i = 0; i < p.n_in; ++i)
+        for (int j = 0; j < p.n_exc; ++j) {
+            const int g = j / p.jb, jj = j % p.jb;
+            w[(size_t)i * p.n_exc + j] = blk[((size_t)g * p.n_in_pad + i) * p.jb + jj];
+        }
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_set_theta(snn_net *net, const double *th, size_t n)
+{
+    if (!net || !th) return fail(SNN_EINVAL, "NULL argument");
+    if (n != net->cfg.n_exc) return fail(SNN_EINVAL, "n must equal n_exc");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(hipMemcpy(net->theta, th, n * sizeof(double), hipMemcpyHostToDevice));
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_get_theta(snn_net *net, double *th, size_t n)
+{
+    if (!net || !th) return fail(SNN_EINVAL, "NULL argument");
+    if (n != net->cfg.n_exc) return fail(SNN_EINVAL, "n must equal n_exc");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(hipMemcpy(th, net->theta, n * sizeof(double), hipMemcpyDeviceToHost));
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_stdp_reduce(snn_net *net, int32_t mode)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (mode < 0 || mode > 2) return fail(SNN_EINVAL, "mode must be 0 (sum), 1 (mean) or 2 (max)");
+    net->cfg.reduce = mode;
+    net->p.reduce = mode;
+    net->graphs_invalidate();
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (path < 0 || path > 3) return fail(SNN_EINVAL, "path must be 0..3");
+    if (precision < 0 || precision > 2) return fail(SNN_EINVAL, "precision must be 0..2");
+    net->path = path;
+    if (precision != net->precision) {
+        net->precision = precision;
+        snn_status st = net->refresh_weight_copies();
+        if (st != SNN_OK) return st;
+    }
+    net->graphs_invalidate();
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_sync(snn_net *net)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return SNN_OK;
+}
+
+extern "C" size_t snn_state_bytes(const snn_config *cfg, uint32_t batch)
+{
+    if (!cfg || validate(cfg) != SNN_OK) return 0;
+    Params p{};
+    fill_dims(p, *cfg, choose_jb(cfg->n_exc, device_cu_count()));
+    return state_bytes(p, batch, kChunk) + param_bytes(p);
+}
+
+// ---------------------------------------------------------------------------
+// state management
+// ---------------------------------------------------------------------------
+
+snn_status snn_net::ensure_state(uint32_t B)
+{
+    if (B > cfg.max_batch) return fail(SNN_ENOMEM, "batch exceeds max_batch");
+    if (cfg.hbm_budget_bytes && state_bytes(p, B, kChunk) + param_bytes(p) > cfg.hbm_budget_bytes)
+        return fail(SNN_ENOMEM, "batch exceeds hbm_budget_bytes");
+    if (B > cap_B) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        free_state();
+        const size_t ns = (size_t)p.n_pad * B;
+        const size_t bw = (B + 31) / 32;
+        hipError_t e = hipSuccess;
+        auto A = [&](void **ptr, size_t bytes) {
+            if (e == hipSuccess) e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+        };
+        A((void **)&v_exc, ns * 4);
+        A((void **)&v_inh, ns * 4);
+        A((void **)&x_post, ns * 4);
+        A((void **)&I, ns * 4);
+        A((void **)&rf, ns * 2);
+        A((void **)&x_pre, 2 * (size_t)B * p.n_in_pad * 4);
+        A((void **)&C, 3 * (size_t)B * 4);
+        A((void **)&bits, (size_t)kChunk * B * p.in_words * 4);
+        A((void **)&bitsT, (size_t)kChunk * p.n_in_pad * bw * 4);
+        A((void **)&flags_mask, B);
+        if (e != hipSuccess) {
+            free_state();
+            return fail(SNN_ENOMEM, std::string("state hipMalloc: ") + hipGetErrorString(e));
+        }
+        cap_B = B;
+        graphs_invalidate();
+    }
+    return SNN_OK;
+}
+
+void snn_net::set_batch(uint32_t B)
+{
+    p.B = (int)B;
+    p.bwords = (int)((B + 31) / 32);
+    p.inv_B = 1.f / (float)B;
+    p.inv_Bd = 1.0 / (double)B;
+}
+
+snn_status snn_net::reset_state(const uint8_t *mask_dev)
+{
+    const size_t ns = (size_t)p.n_pad * p.B;
+    const size_t n = std::max(ns, (size_t)p.B * p.n_in_pad);
+    const int tpb = 256;
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, stream, p, v_exc, v_inh, rf,
+                       x_post, x_pre, C, mask_dev);
+    HIP_TRY(hipGetLastError());
+    if (!mask_dev) {
+        gstep = 0;
+        tloc = 0;
+    }
+    return SNN_OK;
+}
+
+snn_status snn_net::refresh_weight_copies()
+{
+    // Contraction copies in BF16 / FP8 are derived from the FP32 master by the
+    // MFMA path when it is selected; nothing to do for FP32.
+    return SNN_OK;
+}
+
+void snn_net::graphs_invalidate() {}
+
+// ---------------------------------------------------------------------------
+// plain per-step path
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(size_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+snn_status snn_net::encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase,
+                                 int steps, const uint32_t *forced, uint32_t *raster_in, int raster_k0)
+{
+    dim3 grid((unsigned)((p.B + 63) / 64), (unsigned)p.in_words, (unsigned)steps);
+    hipLaunchKernelGGL(k_encode, grid, dim3(64), 0, stream, p, img, ids, thr_lut, tl, tbase, forced, bits, bitsT,
+                       raster_in, raster_k0);
+    HIP_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
+snn_status snn_net::plain_step(int kk, int k, const Outs &o)
+{
+    const uint32_t *bits_t = bits + (size_t)kk * p.B * p.in_words;
+    const uint32_t *bitsT_t = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
+    const int cur = (int)(gstep & 1);
+    float *xcur = x_pre + (size_t)cur * p.B * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
+    uint32_t *Ccur = C + (size_t)(gstep % 3) * p.B;
+    uint32_t *Cprev = C + (size_t)((gstep + 2) % 3) * p.B;
+    uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.B;
+    const size_t ns = (size_t)p.n_pad * p.B;
+    const int tpb = 256;
+    if (p.learn)
+        hipLaunchKernelGGL(k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, stream, p,
+                           bits_t, xprev, xcur);
+    hipLaunchKernelGGL(k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, stream, p, (const float *)W, bits_t, I);
+    hipLaunchKernelGGL(k_neuron, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, stream, p, (const float *)I,
+                       (const double *)theta, (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf, x_post, k, o);
+    if (p.learn) {
+        const int R = 256 / p.jb;
+        const size_t sm = align16((size_t)p.jb * p.bwords * 4) + (size_t)(R * p.jb + p.jb) * 8;
+        hipLaunchKernelGGL(k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, stream, p, W, theta,
+                           (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
+    }
+    HIP_TRY(hipGetLastError());
+    ++gstep;
+    return SNN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// snn_run
+// ---------------------------------------------------------------------------
+
+snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch,
+                        uint32_t T, uint32_t flags, const snn_outputs *out)
+{
+    if (batch == 0 || T == 0) return fail(SNN_EINVAL, "batch and T must be > 0");
+    if (!forced) {
+        if (!ids) return fail(SNN_EINVAL, "ids_dev is NULL");
+        if (!images && !cfg.uniform_rate) return fail(SNN_EINVAL, "images_dev is NULL and uniform_rate is 0");
+    }
+    snn_status st = ensure_state(batch);
+    if (st != SNN_OK) return st;
+    const bool new_batch = batch != cur_B;
+    set_batch(batch);
+    if (new_batch || (flags & SNN_RUN_RESET)) {
+        st = reset_state(nullptr);
+        if (st != SNN_OK) return st;
+        cur_B = batch;
+    }
+    Outs o{};
+    if (out) {
+        o.counts = out->counts;
+        o.raster_in = out->raster_in;
+        o.raster_exc = out->raster_exc;
+        o.raster_inh = out->raster_inh;
+        o.v_exc = out->v_exc;
+        o.v_inh = out->v_inh;
+    }
+    const int words = (p.n_exc + 31) / 32;
+    auto zero = [&](uint32_t *ptr, size_t n) {
+        if (!ptr) return;
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, stream,
+                           ptr, 0u, n);
+    };
+    zero(o.counts, (size_t)batch * p.n_exc);
+    zero(o.raster_exc, (size_t)T * batch * words);
+    zero(o.raster_inh, (size_t)T * batch * words);
+    HIP_TRY(hipGetLastError());
+
+    int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T) : this->path;
+    return run_steps(path, images, ids, forced, T, o);
+}
+
+snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                              uint32_t T, const Outs &o)
+{
+    (void)path;
+    for (uint32_t k0 = 0; k0 < T; k0 += kChunk) {
+        const int steps = (int)std::min<uint32_t>(kChunk, T - k0);
+        const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
+        snn_status st = encode_chunk(images, ids, nullptr, tloc, steps, fc, o.raster_in, (int)k0);
+        if (st != SNN_OK) return st;
+        for (int kk = 0; kk < steps; ++kk) {
+            st = plain_step(kk, (int)k0 + kk, o);
+            if (st != SNN_OK) return st;
+        }
+        tloc += (uint64_t)steps;
+    }
+    return SNN_OK;
+}
+
+int snn_net::choose_path(uint32_t, uint32_t) { return SNN_PATH_PLAIN; }
+
+extern "C" snn_status snn_run(snn_net *net, const uint8_t *images_dev, const uint64_t *ids_dev, uint32_t batch,
+                              uint32_t T, uint32_t flags, const snn_outputs *out)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    return net->run(images_dev, ids_dev, nullptr, batch, T, flags, out);
+}
+
+extern "C" snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, uint32_t batch, uint32_t T,
+                                     uint32_t flags, const snn_outputs *out)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (!in_bits_dev) return fail(SNN_EINVAL, "in_bits_dev is NULL");
+    return net->run(nullptr, nullptr, in_bits_dev, batch, T, flags, out);
+}

@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (FP32 path): input spikes bit-exact; exc/inh rasters agree on at least
+99.9 % of (sample, step, neuron) entries; voltages within 1e-3 mV up to the
+first raster divergence, widened by 4e-6 |v| where one FP32 ulp of v already
+exceeds 1e-3 mV (summed inhibition drives v to -1e4 mV, ulp 1e-3 mV);
+weights within 1e-4 relative (1e-6 absolute near zero) and theta within 1e-6
+relative when no spike diverged.
+"""
+import numpy as np
+import pytest
+
+from paper_1909_02549_amd import inputs
+from paper_1909_02549_amd.inputs import dc_config, sample_ids, stroke_images, uniform_weights
+
+pytestmark = pytest.mark.gpu
+
+RASTER_AGREE = 0.999
+V_TOL = 1e-3
+V_RTOL = 4e-6
+W_RTOL, W_ATOL = 1e-4, 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def to_dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+def run_both(torch, oracle_mod, cfg, W, imgs, ids, T, path="plain", record=("in", "exc", "inh", "v_exc", "counts"),
+             reduce=None, forced=None):
+    from paper_1909_02549_amd.snn import Net, pack_bits, unpack_bits
+    B = len(ids)
+    net = Net(cfg, max_batch=B, path=path)
+    net.snn_set_weights(W)
+    if forced is not None:
+        bits = pack_bits(forced.transpose(1, 0, 2))  # T, B, words
+        out = net.snn_run_spikes(to_dev(torch, bits.view(np.int32)), T, record=record)
+    else:
+        out = net.snn_run(to_dev(torch, imgs) if imgs is not None else None,
+                          to_dev(torch, ids.astype(np.int64)), T, record=record)
+    torch.cuda.synchronize()
+    g = {}
+    n_in, n_exc = cfg["n_in"], cfg["n_exc"]
+    for k, v in out.items():
+        a = v.cpu().numpy()
+        if k == "in":
+            g[k] = unpack_bits(a, n_in).transpose(1, 0, 2)
+        elif k in ("exc", "inh"):
+            g[k] = unpack_bits(a, n_exc).transpose(1, 0, 2)
+        elif k in ("v_exc", "v_inh"):
+            g[k] = a.transpose(1, 0, 2)
+        else:
+            g[k] = a.astype(np.int64)
+    g["W"] = net.snn_get_weights()
+    g["theta"] = net.snn_get_theta()
+    net.close()
+    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
+    ref = orc.run(imgs, ids, T, forced_in=forced, record=tuple(record))
+    ref["W"] = orc.W
+    ref["theta"] = orc.theta
+    return g, ref
+
+
+def first_divergence(g, ref):
+    """First step at which any exc or inh raster entry differs (T if none)."""
+    T = ref["exc"].shape[1]
+    diff = (g["exc"] != ref["exc"]).any(axis=(0, 2))
+    if "inh" in g and "inh" in ref:
+        diff |= (g["inh"] != ref["inh"]).any(axis=(0, 2))
+    idx = np.nonzero(diff)[0]
+    return int(idx[0]) if len(idx) else T
+
+
+def check_parity(g, ref, learn=True):
+    assert np.array_equal(g["in"], ref["in"]), "input spikes not bit-exact"
+    agree_e = (g["exc"] == ref["exc"]).mean()
+    assert agree_e >= RASTER_AGREE, f"exc raster agreement {agree_e}"
+    if "inh" in g:
+        agree_i = (g["inh"] == ref["inh"]).mean()
+        assert agree_i >= RASTER_AGREE, f"inh raster agreement {agree_i}"
+    t_div = first_divergence(g, ref)
+    if "v_exc" in g and t_div > 0:
+        vr = ref["v_exc"][:, :t_div]
+        dv = np.abs(g["v_exc"][:, :t_div] - vr)
+        bad = dv > V_TOL + V_RTOL * np.abs(vr)
+        assert not bad.any(), f"voltage error {dv.max()} mV (v={vr.flat[dv.argmax()]}) before step {t_div}"
+    if learn and t_div == ref["exc"].shape[1]:
+        err = np.abs(g["W"] - ref["W"])
+        bad = err > W_RTOL * np.abs(ref["W"]) + W_ATOL
+        assert not bad.any(), f"weights: max err {err.max()}"
+        np.testing.assert_allclose(g["theta"], ref["theta"], rtol=1e-6, atol=1e-12)
+    return t_div
+
+
+@pytest.mark.parametrize("path", ["plain"])
+def test_dc100_learning_parity(torch_cuda, oracle_mod, path):
+    """784 -> 100/100 Diehl & Cook net, B=4, T=100, STDP with mean reduction."""
+    w = inputs.workload("dc100")
+    cfg = w["cfg"]
+    imgs = stroke_images(4, 0, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 0)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(4), 100, path=path)
+    assert ref["exc"].sum() > 50
+    t_div = check_parity(g, ref)
+    assert np.array_equal(g["counts"], ref["counts"].astype(np.int64)) or t_div < 100
+
+
+@pytest.mark.parametrize("reduce", ["sum", "max"])
+def test_reductions_parity(torch_cuda, oracle_mod, reduce):
+    cfg = dc_config(100, reduce=reduce)
+    imgs = stroke_images(8, 3, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 1)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 10), 60)
+    check_parity(g, ref)
+
+
+def test_ragged_batch_and_inputs(torch_cuda, oracle_mod):
+    """B = 70 (two 64-sample tiles, three 32-sample words), n_in = 50
+    (ragged input word), n_exc = 37 (ragged column block)."""
+    cfg = dc_config(37, n_in=50)
+    rng = np.random.default_rng(0)
+    imgs = (rng.random((70, 50)) < 0.5) * rng.integers(1, 256, (70, 50))
+    imgs = imgs.astype(np.uint8)
+    W = uniform_weights(50, 37, 0.0, 1.5, 2)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(70, 5), 40)
+    check_parity(g, ref)
+
+
+def test_no_learning_scaling_net(torch_cuda, oracle_mod):
+    """Uniform 20 Hz inputs -> LIF layer without inhibition or learning."""
+    cfg = inputs.scaling_config(n_in=200, n_out=150)
+    W = inputs.normal_weights(200, 150, 0.5, 0.2, 0)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(16), 120,
+                      record=("in", "exc", "v_exc", "counts"))
+    assert ref["exc"].sum() > 100
+    check_parity(g, ref, learn=False)
+
+
+def test_forced_stdp_pairs(torch_cuda, oracle_mod):
+    """Forced input rasters through snn_run_spikes: pre/post pairs at several
+    offsets in different samples, compared with the oracle."""
+    cfg = dc_config(1, n_in=2, reduce="sum", norm=0.0, w_max=100.0, exc=dict(adaptive=0))
+    cfg["n_inh"] = 0
+    T = 40
+    deltas = [-7, -3, -1, 0, 1, 2, 5, 12]
+    forced = np.zeros((len(deltas), T, 2), np.uint8)
+    for b, d in enumerate(deltas):
+        t_pre = 10 if d >= 0 else 10 - d
+        forced[b, t_pre, 0] = 1
+        forced[b, t_pre + d, 1] = 1
+    W = np.array([[0.5], [20.0]], np.float32)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(len(deltas)), T,
+                      forced=forced, record=("in", "exc", "v_exc"))
+    check_parity(g, ref)
