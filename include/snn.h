@@ -172,6 +172,16 @@ snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, uint32_t ba
 /* Block until all work queued on the handle's stream has finished. */
 snn_status snn_sync(snn_net *net);
 
+/* Per-kernel timing: with profiling on, every kernel launch of the handle is
+ * bracketed by two HIP events recorded on the handle's stream, and elapsed
+ * times are accumulated per kernel name (cleared when profiling is turned
+ * on).  snn_profile_get returns entry idx (SNN_ENOTFOUND past the last one):
+ * its name (copied into name[name_len]), launch count and total milliseconds.
+ * Reading synchronises the stream. */
+snn_status snn_profile_enable(snn_net *net, int32_t on);
+snn_status snn_profile_get(snn_net *net, uint32_t idx, char *name, size_t name_len, uint64_t *launches,
+                           double *total_ms);
+
 /* Device bytes the handle would hold for `batch` samples (state, weights,
  * scratch), the quantity compared with hbm_budget_bytes. */
 size_t snn_state_bytes(const snn_config *cfg, uint32_t batch);

@@ -2,11 +2,18 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+#include <utility>
+#include <vector>
+
 #include "../../include/snn.h"
 #include "snn_dev.h"
 
-// Steps encoded per encoder launch (bounds the input-spike buffers).
+// Steps encoded per encoder launch (bounds the input-spike buffers; one extra
+// step is encoded so the last step of a chunk sees its successor's inputs).
 constexpr uint32_t kChunk = 256;
+// LDS a workgroup may use on gfx950 (160 KiB per CU).
+constexpr size_t kMaxLds = 160 * 1024;
 
 struct snn_net {
     snn_config cfg{};
@@ -33,6 +40,21 @@ struct snn_net {
     uint32_t *bitsT = nullptr;   // kChunk x n_in_pad x bwords
     uint8_t *flags_mask = nullptr;
 
+    // optional per-kernel timing with HIP events on the handle's stream
+    struct KStat {
+        std::string name;
+        uint64_t launches = 0;
+        double total_ms = 0.0;
+    };
+    bool prof = false;
+    std::vector<KStat> kstats;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
+    int kstat_id(const char *name);
+    std::pair<hipEvent_t, hipEvent_t> prof_begin();
+    void prof_end(int id, std::pair<hipEvent_t, hipEvent_t> ev);
+    snn_status prof_flush();
+
     uint64_t gstep = 0;  // steps since the state was initialised
     uint64_t tloc = 0;   // local step of the current samples (encoder counter)
 
@@ -46,6 +68,10 @@ struct snn_net {
     snn_status encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase, int steps,
                             const uint32_t *forced, uint32_t *raster_in, int raster_k0);
     snn_status plain_step(int kk, int k, const snn::Outs &o);
+    snn_status xpre_first(const uint32_t *bits_t);
+    bool fused_ok() const;
+    size_t fused_attr_bytes = 64 * 1024;
+    snn_status fused_step(int kk, int k, bool has_next, const snn::Outs &o);
     snn_status run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch, uint32_t T,
                    uint32_t flags, const snn_outputs *out);
     snn_status run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t T,

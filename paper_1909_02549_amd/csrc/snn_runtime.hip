@@ -12,6 +12,7 @@
 
 #include "../../include/snn.h"
 #include "snn_dev.h"
+#include "snn_fused.h"
 #include "snn_kern.h"
 #include "snn_runtime.h"
 
@@ -30,6 +31,22 @@ static snn_status fail(snn_status st, const std::string &msg)
         hipError_t e_ = (call);                                                                         \
         if (e_ != hipSuccess)                                                                           \
             return fail(SNN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+// Launch a kernel on the handle's stream; with profiling on, bracket it with
+// a pair of HIP events on the same stream and account it under `name`.
+#define SNN_LAUNCH(kname_, kern, grid, block, shmem, ...)                                                  \
+    do {                                                                                                \
+        if (this->prof) {                                                                               \
+            static thread_local int kid_ = -1;                                                          \
+            if (kid_ < 0 || kid_ >= (int)this->kstats.size() || this->kstats[kid_].name != (kname_))      \
+                kid_ = this->kstat_id(kname_);                                                            \
+            auto ev_ = this->prof_begin();                                                              \
+            hipLaunchKernelGGL(kern, grid, block, shmem, this->stream, __VA_ARGS__);                    \
+            this->prof_end(kid_, ev_);                                                                  \
+        } else {                                                                                        \
+            hipLaunchKernelGGL(kern, grid, block, shmem, this->stream, __VA_ARGS__);                    \
+        }                                                                                               \
     } while (0)
 
 extern "C" uint32_t snn_abi_version(void) { return SNN_ABI_VERSION; }
@@ -79,8 +96,8 @@ static size_t state_bytes(const Params &p, uint32_t B, uint32_t chunk)
     s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
     s += 2 * (size_t)B * p.n_in_pad * 4;            // x_pre
     s += 3 * (size_t)B * 4;                         // C
-    s += (size_t)chunk * B * p.in_words * 4;        // bits
-    s += (size_t)chunk * p.n_in_pad * bw * 4;       // bitsT
+    s += (size_t)(chunk + 1) * B * p.in_words * 4;  // bits
+    s += (size_t)(chunk + 1) * p.n_in_pad * bw * 4; // bitsT
     return s;
 }
 
@@ -168,8 +185,63 @@ static void fill_params(Params &p, const snn_config &c)
 // handle lifetime
 // ---------------------------------------------------------------------------
 
+int snn_net::kstat_id(const char *name)
+{
+    for (size_t q = 0; q < kstats.size(); ++q)
+        if (kstats[q].name == name) return (int)q;
+    kstats.push_back(KStat{name, 0, 0.0});
+    return (int)kstats.size() - 1;
+}
+
+std::pair<hipEvent_t, hipEvent_t> snn_net::prof_begin()
+{
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (!evpool.empty()) {
+        ev = evpool.back();
+        evpool.pop_back();
+    } else {
+        if (pending.size() >= 4096) prof_flush();
+        if (!evpool.empty()) {
+            ev = evpool.back();
+            evpool.pop_back();
+        } else {
+            (void)hipEventCreate(&ev.first);
+            (void)hipEventCreate(&ev.second);
+        }
+    }
+    (void)hipEventRecord(ev.first, stream);
+    return ev;
+}
+
+void snn_net::prof_end(int id, std::pair<hipEvent_t, hipEvent_t> ev)
+{
+    (void)hipEventRecord(ev.second, stream);
+    pending.push_back({id, ev});
+}
+
+snn_status snn_net::prof_flush()
+{
+    if (pending.empty()) return SNN_OK;
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (auto &pe : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+            kstats[pe.first].launches += 1;
+            kstats[pe.first].total_ms += ms;
+        }
+        evpool.push_back(pe.second);
+    }
+    pending.clear();
+    return SNN_OK;
+}
+
 snn_net::~snn_net()
 {
+    prof_flush();
+    for (auto &e : evpool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     free_state();
     (void)hipFree(W);
     (void)hipFree(theta);
@@ -366,8 +438,8 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&rf, ns * 2);
         A((void **)&x_pre, 2 * (size_t)B * p.n_in_pad * 4);
         A((void **)&C, 3 * (size_t)B * 4);
-        A((void **)&bits, (size_t)kChunk * B * p.in_words * 4);
-        A((void **)&bitsT, (size_t)kChunk * p.n_in_pad * bw * 4);
+        A((void **)&bits, (size_t)(kChunk + 1) * B * p.in_words * 4);
+        A((void **)&bitsT, (size_t)(kChunk + 1) * p.n_in_pad * bw * 4);
         A((void **)&flags_mask, B);
         if (e != hipSuccess) {
             free_state();
@@ -392,8 +464,8 @@ snn_status snn_net::reset_state(const uint8_t *mask_dev)
     const size_t ns = (size_t)p.n_pad * p.B;
     const size_t n = std::max(ns, (size_t)p.B * p.n_in_pad);
     const int tpb = 256;
-    hipLaunchKernelGGL(k_reset, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, stream, p, v_exc, v_inh, rf,
-                       x_post, x_pre, C, mask_dev);
+    SNN_LAUNCH("reset", k_reset, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, p, v_exc, v_inh, rf, x_post,
+               x_pre, C, mask_dev);
     HIP_TRY(hipGetLastError());
     if (!mask_dev) {
         gstep = 0;
@@ -421,8 +493,8 @@ snn_status snn_net::encode_chunk(const uint8_t *img, const uint64_t *ids, const 
                                  int steps, const uint32_t *forced, uint32_t *raster_in, int raster_k0)
 {
     dim3 grid((unsigned)((p.B + 63) / 64), (unsigned)p.in_words, (unsigned)steps);
-    hipLaunchKernelGGL(k_encode, grid, dim3(64), 0, stream, p, img, ids, thr_lut, tl, tbase, forced, bits, bitsT,
-                       raster_in, raster_k0);
+    SNN_LAUNCH("encode", k_encode, grid, dim3(64), 0, p, img, ids, (const uint32_t *)thr_lut, tl, tbase, forced,
+               bits, bitsT, raster_in, raster_k0);
     HIP_TRY(hipGetLastError());
     return SNN_OK;
 }
@@ -440,16 +512,16 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o)
     const size_t ns = (size_t)p.n_pad * p.B;
     const int tpb = 256;
     if (p.learn)
-        hipLaunchKernelGGL(k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, stream, p,
-                           bits_t, xprev, xcur);
-    hipLaunchKernelGGL(k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, stream, p, (const float *)W, bits_t, I);
-    hipLaunchKernelGGL(k_neuron, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, stream, p, (const float *)I,
-                       (const double *)theta, (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf, x_post, k, o);
+        SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, p, bits_t, xprev,
+                   xcur);
+    SNN_LAUNCH("contract", k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)W, bits_t, I);
+    SNN_LAUNCH("neuron", k_neuron, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)I, (const double *)theta,
+               (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf, x_post, k, o);
     if (p.learn) {
         const int R = 256 / p.jb;
         const size_t sm = align16((size_t)p.jb * p.bwords * 4) + (size_t)(R * p.jb + p.jb) * 8;
-        hipLaunchKernelGGL(k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, stream, p, W, theta,
-                           (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
+        SNN_LAUNCH("plastic", k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, p, W, theta, (const uint16_t *)rf,
+                   (const float *)x_post, (const float *)xcur, bitsT_t);
     }
     HIP_TRY(hipGetLastError());
     ++gstep;
@@ -489,8 +561,8 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     const int words = (p.n_exc + 31) / 32;
     auto zero = [&](uint32_t *ptr, size_t n) {
         if (!ptr) return;
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, stream,
-                           ptr, 0u, n);
+        SNN_LAUNCH("fill", k_fill_u32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, ptr, 0u,
+                   n);
     };
     zero(o.counts, (size_t)batch * p.n_exc);
     zero(o.raster_exc, (size_t)T * batch * words);
@@ -501,18 +573,72 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     return run_steps(path, images, ids, forced, T, o);
 }
 
+snn_status snn_net::xpre_first(const uint32_t *bits_t)
+{
+    const int cur = (int)(gstep & 1);
+    float *xcur = x_pre + (size_t)cur * p.B * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
+    SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, 256)), dim3(256), 0, p, bits_t, xprev, xcur);
+    HIP_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
+bool snn_net::fused_ok() const
+{
+    return p.jb <= 32 && fused_lds_bytes(p) <= kMaxLds;
+}
+
+snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
+{
+    const int cur = (int)(gstep & 1);
+    StepPtrs s;
+    s.bits = bits + (size_t)kk * p.B * p.in_words;
+    s.bitsT = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
+    s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.B * p.in_words : nullptr;
+    s.xpre = x_pre + (size_t)cur * p.B * p.n_in_pad;
+    s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
+    s.Ccur = C + (size_t)(gstep % 3) * p.B;
+    s.Cprev = C + (size_t)((gstep + 2) % 3) * p.B;
+    s.Cnext = C + (size_t)((gstep + 1) % 3) * p.B;
+    s.k = k;
+    FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
+    const size_t lds = fused_lds_bytes(p);
+    if (lds > fused_attr_bytes) {
+        HIP_TRY(hipFuncSetAttribute((const void *)k_fused_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        fused_attr_bytes = lds;
+    }
+    SNN_LAUNCH("fused_step", k_fused_step, dim3((unsigned)p.nblk), dim3(kFusedThreads), lds, p, a, s);
+    HIP_TRY(hipGetLastError());
+    ++gstep;
+    return SNN_OK;
+}
+
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o)
 {
-    (void)path;
+    if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
     for (uint32_t k0 = 0; k0 < T; k0 += kChunk) {
         const int steps = (int)std::min<uint32_t>(kChunk, T - k0);
+        const bool more = k0 + (uint32_t)steps < T;
+        const int enc_steps = steps + (more ? 1 : 0);
         const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
-        snn_status st = encode_chunk(images, ids, nullptr, tloc, steps, fc, o.raster_in, (int)k0);
+        snn_status st = encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
         if (st != SNN_OK) return st;
-        for (int kk = 0; kk < steps; ++kk) {
-            st = plain_step(kk, (int)k0 + kk, o);
-            if (st != SNN_OK) return st;
+        if (path == SNN_PATH_FUSED) {
+            if (k0 == 0 && p.learn) {
+                st = xpre_first(bits);
+                if (st != SNN_OK) return st;
+            }
+            for (int kk = 0; kk < steps; ++kk) {
+                const bool has_next = (kk + 1 < enc_steps);
+                st = fused_step(kk, (int)k0 + kk, has_next, o);
+                if (st != SNN_OK) return st;
+            }
+        } else {
+            for (int kk = 0; kk < steps; ++kk) {
+                st = plain_step(kk, (int)k0 + kk, o);
+                if (st != SNN_OK) return st;
+            }
         }
         tloc += (uint64_t)steps;
     }
@@ -534,4 +660,35 @@ extern "C" snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, 
     if (!net) return fail(SNN_EINVAL, "net is NULL");
     if (!in_bits_dev) return fail(SNN_EINVAL, "in_bits_dev is NULL");
     return net->run(nullptr, nullptr, in_bits_dev, batch, T, flags, out);
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing (HIP events on the handle's stream)
+// ---------------------------------------------------------------------------
+
+extern "C" snn_status snn_profile_enable(snn_net *net, int32_t on)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    snn_status st = net->prof_flush();
+    if (st != SNN_OK) return st;
+    net->prof = on != 0;
+    if (on) net->kstats.clear();
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_profile_get(snn_net *net, uint32_t idx, char *name, size_t name_len, uint64_t *launches,
+                                      double *total_ms)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    snn_status st = net->prof_flush();
+    if (st != SNN_OK) return st;
+    if (idx >= net->kstats.size()) return fail(SNN_ENOTFOUND, "no such kernel entry");
+    const auto &k = net->kstats[idx];
+    if (name && name_len) {
+        std::strncpy(name, k.name.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (launches) *launches = k.launches;
+    if (total_ms) *total_ms = k.total_ms;
+    return SNN_OK;
 }

@@ -27,6 +27,7 @@ STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4
 EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "snn_set_stream",
             "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce",
             "snn_set_path", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
+            "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
             "snn_serve_destroy"]
 
@@ -89,6 +90,8 @@ def load_library():
         "snn_run_spikes": ([VP, VP, U32, U32, U32, P(snn_outputs)], I32),
         "snn_sync": ([VP], I32),
         "snn_state_bytes": ([P(snn_config), U32], SZ),
+        "snn_profile_enable": ([VP, I32], I32),
+        "snn_profile_get": ([VP, U32, C.c_char_p, SZ, P(U64), P(C.c_double)], I32),
         "snn_serve_create": ([VP, U32, U64, U32, P(VP)], I32),
         "snn_serve_submit": ([VP, VP, U64, U32, P(U64)], I32),
         "snn_serve_poll": ([VP, U64, VP, P(C.c_double)], I32),
@@ -203,6 +206,23 @@ class Net:
 
     def snn_sync(self):
         _check(self.lib.snn_sync(self.h))
+
+    def snn_profile_enable(self, on: bool = True):
+        _check(self.lib.snn_profile_enable(self.h, 1 if on else 0))
+
+    def snn_profile_get(self) -> dict:
+        """{kernel name: (launches, total_ms)} accumulated since profiling on."""
+        res, idx = {}, 0
+        name = C.create_string_buffer(64)
+        while True:
+            n, ms = C.c_uint64(), C.c_double()
+            st = self.lib.snn_profile_get(self.h, idx, name, 64, C.byref(n), C.byref(ms))
+            if st == -5:
+                break
+            _check(st)
+            res[name.value.decode()] = (int(n.value), float(ms.value))
+            idx += 1
+        return res
 
     # -- running --------------------------------------------------------------
     def _outputs(self, B, T, record):

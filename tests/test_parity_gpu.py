@@ -102,7 +102,10 @@ def check_parity(g, ref, learn=True):
     return t_div
 
 
-@pytest.mark.parametrize("path", ["plain"])
+PATHS = ["plain", "fused"]
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_dc100_learning_parity(torch_cuda, oracle_mod, path):
     """784 -> 100/100 Diehl & Cook net, B=4, T=100, STDP with mean reduction."""
     w = inputs.workload("dc100")
@@ -115,16 +118,18 @@ def test_dc100_learning_parity(torch_cuda, oracle_mod, path):
     assert np.array_equal(g["counts"], ref["counts"].astype(np.int64)) or t_div < 100
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("reduce", ["sum", "max"])
-def test_reductions_parity(torch_cuda, oracle_mod, reduce):
+def test_reductions_parity(torch_cuda, oracle_mod, reduce, path):
     cfg = dc_config(100, reduce=reduce)
     imgs = stroke_images(8, 3, 0.19)
     W = uniform_weights(784, 100, 0.0, 0.3, 1)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 10), 60)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 10), 60, path=path)
     check_parity(g, ref)
 
 
-def test_ragged_batch_and_inputs(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", PATHS)
+def test_ragged_batch_and_inputs(torch_cuda, oracle_mod, path):
     """B = 70 (two 64-sample tiles, three 32-sample words), n_in = 50
     (ragged input word), n_exc = 37 (ragged column block)."""
     cfg = dc_config(37, n_in=50)
@@ -132,21 +137,23 @@ def test_ragged_batch_and_inputs(torch_cuda, oracle_mod):
     imgs = (rng.random((70, 50)) < 0.5) * rng.integers(1, 256, (70, 50))
     imgs = imgs.astype(np.uint8)
     W = uniform_weights(50, 37, 0.0, 1.5, 2)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(70, 5), 40)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(70, 5), 40, path=path)
     check_parity(g, ref)
 
 
-def test_no_learning_scaling_net(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", PATHS)
+def test_no_learning_scaling_net(torch_cuda, oracle_mod, path):
     """Uniform 20 Hz inputs -> LIF layer without inhibition or learning."""
     cfg = inputs.scaling_config(n_in=200, n_out=150)
     W = inputs.normal_weights(200, 150, 0.5, 0.2, 0)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(16), 120,
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(16), 120, path=path,
                       record=("in", "exc", "v_exc", "counts"))
     assert ref["exc"].sum() > 100
     check_parity(g, ref, learn=False)
 
 
-def test_forced_stdp_pairs(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", PATHS)
+def test_forced_stdp_pairs(torch_cuda, oracle_mod, path):
     """Forced input rasters through snn_run_spikes: pre/post pairs at several
     offsets in different samples, compared with the oracle."""
     cfg = dc_config(1, n_in=2, reduce="sum", norm=0.0, w_max=100.0, exc=dict(adaptive=0))
@@ -159,6 +166,17 @@ def test_forced_stdp_pairs(torch_cuda, oracle_mod):
         forced[b, t_pre, 0] = 1
         forced[b, t_pre + d, 1] = 1
     W = np.array([[0.5], [20.0]], np.float32)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(len(deltas)), T,
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(len(deltas)), T, path=path,
                       forced=forced, record=("in", "exc", "v_exc"))
+    check_parity(g, ref)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_long_run_crosses_encoder_chunks(torch_cuda, oracle_mod, path):
+    """T = 300 > 256 steps per encoder chunk: the chunk boundary (next-step
+    inputs for the presynaptic traces) is seamless."""
+    cfg = dc_config(40)
+    imgs = stroke_images(3, 21, 0.25)
+    W = uniform_weights(784, 40, 0.0, 0.3, 4)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(3, 77), 300, path=path)
     check_parity(g, ref)
