@@ -9,8 +9,9 @@
 //     W(i, j)      at (g * n_in_pad + i) * JB + jj (FP32 master)
 //   inputs are padded to n_in_pad = 32 * in_words; pad inputs never spike
 //   and their weights stay 0.
-//   input spikes of step t: bits[t][b][w] (bit i % 32 of word i / 32) and the
-//   transpose bitsT[t][i][bw] (bit b % 32 of word b / 32).
+//   input spikes of step t: bits[t * bits_stride + b * in_words + w] (bit
+//   i % 32 of word i / 32) and the transpose bitsT[t][i][bw] (bit b % 32 of
+//   word b / 32).
 //   presynaptic traces x_pre[t & 1][b][i]; inhibitory spike counts per sample
 //   C[t % 3][b].
 #pragma once
@@ -28,6 +29,8 @@ struct Params {
     int n_exc, n_pad, jb, nblk;
     int has_inh;
     int B, bwords;            // batch, ceil(B / 32)
+    int bits_stride;          // words per step of the per-sample input spikes
+                              // (B * in_words rounded up to 4: 16-byte rows)
     int learn, adaptive, trace_add, reduce;
     int uniform_rate;
     uint32_t thr_uniform;

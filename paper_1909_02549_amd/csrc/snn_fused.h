@@ -6,7 +6,7 @@
 
 namespace snn {
 
-constexpr int kFusedThreads = 512;  // 8 waves; two samples per wave per round
+constexpr int kFusedThreads = 1024;  // 16 waves; two samples per wave per round
 
 // Per-network pointers (state and parameters owned by the handle).
 struct FusedArgs {

@@ -29,11 +29,9 @@
 
 namespace snn {
 
-__device__ __forceinline__ uint32_t lds_words(size_t bytes) { return (uint32_t)(bytes / 4); }
-
 // LDS carve-up shared by host (size) and device (offsets).
 struct FusedLds {
-    size_t w, xpost, cprev, cinh, spk, part, scale, theta, total;
+    size_t w, xpost, bits, cprev, cinh, spk, part, scale, theta, total;
     __host__ __device__ FusedLds(const Params &p, int nthreads)
     {
         size_t o = 0;
@@ -41,6 +39,14 @@ struct FusedLds {
         o += align16((size_t)p.n_in_pad * p.jb * 4);
         xpost = o;
         o += p.learn ? align16((size_t)p.B * p.jb * 4) : 0;
+        // input spikes of the step: B x in_words for the contraction, then
+        // reused for the transpose n_in_pad x bwords during plasticity
+        bits = o;
+        {
+            const size_t a1 = (size_t)p.B * p.in_words * 4;
+            const size_t a2 = p.learn ? (size_t)p.n_in_pad * p.bwords * 4 : 0;
+            o += align16(a1 > a2 ? a1 : a2);
+        }
         cprev = o;
         o += align16((size_t)p.B * 4);
         cinh = o;
@@ -59,28 +65,63 @@ struct FusedLds {
 
 size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads).total; }
 
-__device__ __forceinline__ void copy_to_lds(float *dst, const float *__restrict__ src, size_t n, int tid, int nt)
+// Bulk copy with four 16-byte loads in flight per thread (all four loads
+// are issued before the first store).
+__device__ __forceinline__ void copy_u4(void *dst_, const void *__restrict__ src_, size_t n_words, int tid, int nt)
 {
-    const size_t n4 = n / 4;
-    const float4 *s4 = reinterpret_cast<const float4 *>(src);
-    float4 *d4 = reinterpret_cast<float4 *>(dst);
-    for (size_t q = tid; q < n4; q += nt) d4[q] = s4[q];
-    for (size_t q = n4 * 4 + tid; q < n; q += nt) dst[q] = src[q];
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src_);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst_);
+    const size_t n4 = n_words / 4;
+    const size_t st = (size_t)nt;
+    size_t q = tid;
+    for (; q + 3 * st < n4; q += 4 * st) {
+        const uint4 r0 = s4[q], r1 = s4[q + st], r2 = s4[q + 2 * st], r3 = s4[q + 3 * st];
+        d4[q] = r0;
+        d4[q + st] = r1;
+        d4[q + 2 * st] = r2;
+        d4[q + 3 * st] = r3;
+    }
+    for (; q < n4; q += st) d4[q] = s4[q];
+    const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src_);
+    uint32_t *d1 = reinterpret_cast<uint32_t *>(dst_);
+    for (size_t e = n4 * 4 + tid; e < n_words; e += st) d1[e] = s1[e];
 }
 
-__device__ __forceinline__ void copy_from_lds(float *__restrict__ dst, const float *src, size_t n, int tid, int nt)
+// R over the set bits k (in increasing order) of words[0..nwords) of
+// src[k * stride]; words are fetched four at a time and the next element's
+// load is issued before the previous one is accumulated.
+__device__ __forceinline__ float gather_bits(const uint32_t *words, int nwords, const float *src, int stride,
+                                             int mode)
 {
-    const size_t n4 = n / 4;
-    const float4 *s4 = reinterpret_cast<const float4 *>(src);
-    float4 *d4 = reinterpret_cast<float4 *>(dst);
-    for (size_t q = tid; q < n4; q += nt) d4[q] = s4[q];
-    for (size_t q = n4 * 4 + tid; q < n; q += nt) dst[q] = src[q];
+    float acc = 0.f, pend = 0.f;
+    bool hp = false;
+    auto word = [&](uint32_t mm, int base) {
+        while (mm) {
+            const int k = base + __builtin_ctz(mm);
+            mm &= mm - 1;
+            const float v = src[k * stride];
+            if (hp) acc = reduce2(mode, acc, pend);
+            pend = v;
+            hp = true;
+        }
+    };
+    int w0 = 0;
+    for (; w0 + 4 <= nwords; w0 += 4) {
+        const uint32_t m0 = words[w0], m1 = words[w0 + 1], m2 = words[w0 + 2], m3 = words[w0 + 3];
+        word(m0, 32 * w0);
+        word(m1, 32 * w0 + 32);
+        word(m2, 32 * w0 + 64);
+        word(m3, 32 * w0 + 96);
+    }
+    for (; w0 < nwords; ++w0) word(words[w0], 32 * w0);
+    if (hp) acc = reduce2(mode, acc, pend);
+    return acc;
 }
 
 // One step of workgroup g.  W_lds holds the column block on entry (and the
 // updated block on exit when learning).
-__device__ void fused_step_body(const Params &p, const FusedArgs &a, const StepPtrs &s, int g, unsigned char *smem,
-                                const FusedLds &L)
+__device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs &a, const StepPtrs &s, int g,
+                                                unsigned char *smem, const FusedLds &L)
 {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
@@ -95,6 +136,7 @@ __device__ void fused_step_body(const Params &p, const FusedArgs &a, const StepP
 
     float *W_lds = reinterpret_cast<float *>(smem + L.w);
     float *xpost_lds = reinterpret_cast<float *>(smem + L.xpost);
+    uint32_t *bits_lds = reinterpret_cast<uint32_t *>(smem + L.bits);
     uint32_t *cprev_lds = reinterpret_cast<uint32_t *>(smem + L.cprev);
     uint32_t *cinh_lds = reinterpret_cast<uint32_t *>(smem + L.cinh);
     uint32_t *spk = reinterpret_cast<uint32_t *>(smem + L.spk);
@@ -102,7 +144,8 @@ __device__ void fused_step_body(const Params &p, const FusedArgs &a, const StepP
     double *scale = reinterpret_cast<double *>(smem + L.scale);
     float *th_lds = reinterpret_cast<float *>(smem + L.theta);
 
-    // A: per-step small inputs
+    // A: per-step inputs
+    copy_u4(bits_lds, s.bits, (size_t)p.B * p.in_words, tid, nt);
     for (int b = tid; b < p.B; b += nt) {
         cprev_lds[b] = p.has_inh ? s.Cprev[b] : 0u;
         cinh_lds[b] = 0u;
@@ -128,16 +171,8 @@ __device__ void fused_step_body(const Params &p, const FusedArgs &a, const StepP
                 st.rf = a.rf[n];
                 st.xpost = p.learn ? a.x_post[n] : 0.f;
             }
-            float acc = 0.f;
-            const uint32_t *sb = s.bits + (size_t)b * p.in_words;
-            for (int w = 0; w < p.in_words; ++w) {
-                uint32_t m = sb[w];
-                while (m) {
-                    const int i = 32 * w + __builtin_ctz(m);
-                    m &= m - 1;
-                    if (jj < JB) acc += W_lds[i * JB + jj];
-                }
-            }
+            const float acc = gather_bits(bits_lds + b * p.in_words, p.in_words, W_lds + (jj < JB ? jj : 0), JB,
+                                          RED_SUM);
             if (col_ok) {
                 bool se, si;
                 neuron_update(p, acc, cprev_lds[b], th_lds[jj], st, se, si);
@@ -161,33 +196,35 @@ __device__ void fused_step_body(const Params &p, const FusedArgs &a, const StepP
         if (g == 0 && s.Cnext) s.Cnext[b] = 0u;
     }
     if (!p.learn) return;
+    // the transposed input spikes replace the per-sample ones in LDS
+    copy_u4(bits_lds, s.bitsT, (size_t)p.n_in_pad * p.bwords, tid, nt);
 
-    // C: plasticity on the LDS block
+    // C1: potentiation.  For every column with post spikes this step, all
+    // threads sweep the rows: P[i] = R over the spiking samples b of
+    // x_pre[b, i] (coalesced over i), then W[i, j] += nu_post * P.
+    for (int c = 0; c < JB; ++c) {
+        const uint32_t *sp = spk + c * p.bwords;
+        uint32_t any = 0u;
+        for (int bw = 0; bw < p.bwords; ++bw) any |= sp[bw];
+        if (!any) continue;
+        for (int i = tid; i < p.n_in; i += nt) {
+            float P = gather_bits(sp, p.bwords, s.xpre + i, p.n_in_pad, p.reduce);
+            if (p.reduce == RED_MEAN) P *= p.inv_B;
+            W_lds[i * JB + c] = W_lds[i * JB + c] + p.nu_post * P;
+        }
+    }
+    __syncthreads();
+
+    // C2: depression, clamp and column partial sums.  D[i, j] = R over the
+    // samples b in which input i spiked of x_post[b, j] (LDS gather).
     const int rg = tid >> 5;
     const int nrg = nt >> 5;
     double cs = 0.0;
     if (col_ok) {
-        const uint32_t *sp = spk + jj * p.bwords;
         for (int i = rg; i < p.n_in; i += nrg) {
-            float D = 0.f, P = 0.f;
-            const uint32_t *bt = s.bitsT + (size_t)i * p.bwords;
-            for (int bw = 0; bw < p.bwords; ++bw) {
-                uint32_t m = bt[bw];
-                while (m) {
-                    const int b = 32 * bw + __builtin_ctz(m);
-                    m &= m - 1;
-                    D = reduce2(p.reduce, D, xpost_lds[b * JB + jj]);
-                }
-            }
-            for (int bw = 0; bw < p.bwords; ++bw) {
-                uint32_t m = sp[bw];
-                while (m) {
-                    const int b = 32 * bw + __builtin_ctz(m);
-                    m &= m - 1;
-                    P = reduce2(p.reduce, P, s.xpre[(size_t)b * p.n_in_pad + i]);
-                }
-            }
-            const float w = stdp_apply(p, W_lds[i * JB + jj], P, D);
+            float D = gather_bits(bits_lds + i * p.bwords, p.bwords, xpost_lds + jj, JB, p.reduce);
+            if (p.reduce == RED_MEAN) D *= p.inv_B;
+            const float w = fminf(fmaxf(W_lds[i * JB + jj] - p.nu_pre * D, p.w_min), p.w_max);
             W_lds[i * JB + jj] = w;
             cs += (double)w;
         }
@@ -232,10 +269,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     float *W_lds = reinterpret_cast<float *>(smem + L.w);
     float *Wg = a.W + (size_t)g * p.n_in_pad * p.jb;
     const size_t nw = (size_t)p.n_in_pad * p.jb;
-    copy_to_lds(W_lds, Wg, nw, threadIdx.x, blockDim.x);
+    copy_u4(W_lds, Wg, nw, threadIdx.x, blockDim.x);
     __syncthreads();
     fused_step_body(p, a, s, g, smem, L);
-    if (p.learn) copy_from_lds(Wg, W_lds, nw, threadIdx.x, blockDim.x);
+    if (p.learn) copy_u4(Wg, W_lds, nw, threadIdx.x, blockDim.x);
 }
 
 }  // namespace snn

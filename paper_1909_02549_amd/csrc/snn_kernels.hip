@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64) void k_encode(Params p, const uint8_t *__restri
         }
         const int valid = p.n_in - i_base;
         if (valid < 32) word &= valid <= 0 ? 0u : ((1u << valid) - 1u);
-        bits[((size_t)k * p.B + b) * p.in_words + w] = word;
+        bits[(size_t)k * p.bits_stride + (size_t)b * p.in_words + w] = word;
         if (raster_in) raster_in[((size_t)(raster_k0 + k) * p.B + b) * p.in_words + w] = word;
     }
     uint64_t mine = 0;

@@ -96,7 +96,7 @@ static size_t state_bytes(const Params &p, uint32_t B, uint32_t chunk)
     s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
     s += 2 * (size_t)B * p.n_in_pad * 4;            // x_pre
     s += 3 * (size_t)B * 4;                         // C
-    s += (size_t)(chunk + 1) * B * p.in_words * 4;  // bits
+    s += (size_t)(chunk + 1) * (B * p.in_words + 3) * 4;  // bits
     s += (size_t)(chunk + 1) * p.n_in_pad * bw * 4; // bitsT
     return s;
 }
@@ -438,7 +438,7 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&rf, ns * 2);
         A((void **)&x_pre, 2 * (size_t)B * p.n_in_pad * 4);
         A((void **)&C, 3 * (size_t)B * 4);
-        A((void **)&bits, (size_t)(kChunk + 1) * B * p.in_words * 4);
+        A((void **)&bits, (size_t)(kChunk + 1) * ((size_t)B * p.in_words + 3) * 4);
         A((void **)&bitsT, (size_t)(kChunk + 1) * p.n_in_pad * bw * 4);
         A((void **)&flags_mask, B);
         if (e != hipSuccess) {
@@ -457,6 +457,7 @@ void snn_net::set_batch(uint32_t B)
     p.bwords = (int)((B + 31) / 32);
     p.inv_B = 1.f / (float)B;
     p.inv_Bd = 1.0 / (double)B;
+    p.bits_stride = (int)((((size_t)B * p.in_words) + 3) & ~(size_t)3);
 }
 
 snn_status snn_net::reset_state(const uint8_t *mask_dev)
@@ -501,7 +502,7 @@ snn_status snn_net::encode_chunk(const uint8_t *img, const uint64_t *ids, const 
 
 snn_status snn_net::plain_step(int kk, int k, const Outs &o)
 {
-    const uint32_t *bits_t = bits + (size_t)kk * p.B * p.in_words;
+    const uint32_t *bits_t = bits + (size_t)kk * p.bits_stride;
     const uint32_t *bitsT_t = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
     const int cur = (int)(gstep & 1);
     float *xcur = x_pre + (size_t)cur * p.B * p.n_in_pad;
@@ -592,9 +593,9 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
 {
     const int cur = (int)(gstep & 1);
     StepPtrs s;
-    s.bits = bits + (size_t)kk * p.B * p.in_words;
+    s.bits = bits + (size_t)kk * p.bits_stride;
     s.bitsT = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
-    s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.B * p.in_words : nullptr;
+    s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.bits_stride : nullptr;
     s.xpre = x_pre + (size_t)cur * p.B * p.n_in_pad;
     s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
     s.Ccur = C + (size_t)(gstep % 3) * p.B;
