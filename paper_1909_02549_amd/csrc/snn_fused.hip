@@ -1,26 +1,30 @@
-// snn_fused.hip -- one column-partitioned launch per SNN step, and the same
-// step body run for all T steps by one cooperative (persistent) launch.
+// snn_fused.hip -- one column-partitioned launch per SNN step.
 //
 // Workgroup g owns the JB post-synaptic columns [g*JB, g*JB+JB) for every
 // sample of the batch: their weight block W[:, cols] (staged in LDS), their
-// neuron state, their adaptive thresholds.  Everything the method couples
-// across columns is small: the per-sample inhibitory spike count C[b] (all-
-// but-self inhibition) and the presynaptic traces x_pre (shared by all
-// columns); both are exchanged through global memory between steps.
+// neuron state and their adaptive thresholds.  What the method couples across
+// columns is small: the per-sample inhibitory spike count C[b] (all-but-self
+// inhibition) and the presynaptic traces x_pre (read by every column); both
+// are exchanged through global memory between steps.
+//
+// In LDS the block is stored with JBP = JB rounded up to 8 columns per row
+// plus one all-zero row, so a thread owning 8 consecutive columns reads a row
+// with two 16-byte loads, and padding slots of an index list point at the
+// zero row (adding +0 leaves a sum unchanged).
 //
 // Step t in workgroup g:
-//   A  stage W block in LDS, thresholds and C(t-1) in LDS
-//   B  per (b, j): I = sum of W[i, j] over inputs i that spiked in sample b
-//      (gather from LDS), recurrent currents, exc adaptive-LIF + inh LIF
-//      update, post trace; exc spikes -> per-column sample masks in LDS,
-//      inh spikes -> per-sample counts -> C(t)
-//   C  (learning) per (i, j): D = R_b over samples where input i spiked of
-//      x_post[b, j]; P = R_b over samples where j spiked of x_pre[b, i];
-//      W = clamp(W + nu_post P - nu_pre D); FP64 column sums; scale to norm;
-//      theta update; W block back to HBM
+//   A  stage the weight block, thresholds and C(t-1)
+//   B  task (b, 8 columns): I = sum over the inputs i in sample b's spike
+//      list (increasing i) of W[i, cols]; recurrent currents; exc
+//      adaptive-LIF and inh LIF update; post trace.  Exc spikes set per-column
+//      sample masks, inh spikes add to C(t)
+//   C1 (learning) potentiation: for each column with post spikes, all
+//      threads sweep the rows with P = R over its spiking samples of x_pre
+//   C2 (learning) task (i, 8 columns): D = R over the samples in input i's
+//      spike list of x_post[b, cols]; W = clamp(W + nu_post P - nu_pre D)
+//   C3 (learning) FP64 column sums, scale to the target sum, theta update,
+//      block written back scaled
 //   E  (learning) x_pre(t+1) for this workgroup's share of the samples
-// Thread mapping: lane = (bs, jj), bs = lane / 32 picks one of two samples a
-// wave handles per round, jj = lane % 32 the column (JB <= 32).
 #include <hip/hip_runtime.h>
 
 #include "snn_dev.h"
@@ -31,22 +35,14 @@ namespace snn {
 
 // LDS carve-up shared by host (size) and device (offsets).
 struct FusedLds {
-    size_t w, xpost, bits, cprev, cinh, spk, part, scale, theta, total;
+    size_t w, xpost, cprev, cinh, spk, part, scale, theta, total;
     __host__ __device__ FusedLds(const Params &p, int nthreads)
     {
         size_t o = 0;
         w = o;
-        o += align16((size_t)p.n_in_pad * p.jb * 4);
+        o += align16((size_t)(p.n_in_pad + 1) * p.jbp * 4);
         xpost = o;
-        o += p.learn ? align16((size_t)p.B * p.jb * 4) : 0;
-        // input spikes of the step: B x in_words for the contraction, then
-        // reused for the transpose n_in_pad x bwords during plasticity
-        bits = o;
-        {
-            const size_t a1 = (size_t)p.B * p.in_words * 4;
-            const size_t a2 = p.learn ? (size_t)p.n_in_pad * p.bwords * 4 : 0;
-            o += align16(a1 > a2 ? a1 : a2);
-        }
+        o += p.learn ? align16((size_t)(p.B + 1) * p.jbp * 4) : 0;
         cprev = o;
         o += align16((size_t)p.B * 4);
         cinh = o;
@@ -65,87 +61,101 @@ struct FusedLds {
 
 size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads).total; }
 
-// Bulk copy with four 16-byte loads in flight per thread (all four loads
-// are issued before the first store).
-__device__ __forceinline__ void copy_u4(void *dst_, const void *__restrict__ src_, size_t n_words, int tid, int nt)
+__device__ __forceinline__ void add4(float *acc, const float4 v)
 {
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(src_);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst_);
-    const size_t n4 = n_words / 4;
-    const size_t st = (size_t)nt;
-    size_t q = tid;
-    for (; q + 3 * st < n4; q += 4 * st) {
-        const uint4 r0 = s4[q], r1 = s4[q + st], r2 = s4[q + 2 * st], r3 = s4[q + 3 * st];
-        d4[q] = r0;
-        d4[q + st] = r1;
-        d4[q + 2 * st] = r2;
-        d4[q + 3 * st] = r3;
-    }
-    for (; q < n4; q += st) d4[q] = s4[q];
-    const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src_);
-    uint32_t *d1 = reinterpret_cast<uint32_t *>(dst_);
-    for (size_t e = n4 * 4 + tid; e < n_words; e += st) d1[e] = s1[e];
+    acc[0] += v.x;
+    acc[1] += v.y;
+    acc[2] += v.z;
+    acc[3] += v.w;
 }
 
-// R over the set bits k (in increasing order) of words[0..nwords) of
-// src[k * stride]; words are fetched four at a time and the next element's
-// load is issued before the previous one is accumulated.
-__device__ __forceinline__ float gather_bits(const uint32_t *words, int nwords, const float *src, int stride,
-                                             int mode)
+__device__ __forceinline__ void red4(int mode, float *acc, const float4 v)
 {
-    float acc = 0.f, pend = 0.f;
-    bool hp = false;
-    auto word = [&](uint32_t mm, int base) {
-        while (mm) {
-            const int k = base + __builtin_ctz(mm);
-            mm &= mm - 1;
-            const float v = src[k * stride];
-            if (hp) acc = reduce2(mode, acc, pend);
-            pend = v;
-            hp = true;
+    acc[0] = reduce2(mode, acc[0], v.x);
+    acc[1] = reduce2(mode, acc[1], v.y);
+    acc[2] = reduce2(mode, acc[2], v.z);
+    acc[3] = reduce2(mode, acc[3], v.w);
+}
+
+// acc[0..8) = R over the first `cnt` entries of `list` (u16 row indices, in
+// list order) of rows[idx * jbp + c0 .. + 8), four rows in flight at a time;
+// slots past cnt read row `zero_row` (all zeros).
+__device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int cnt, const float *rows, int jbp,
+                                        int c0, int zero_row, int mode, float *acc)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
+    for (int k0 = 0; k0 < cnt; k0 += 4) {
+        const uint2 q = l4[k0 >> 2];
+        const int i0 = (int)(q.x & 0xFFFFu);
+        const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
+        const int i2 = k0 + 2 < cnt ? (int)(q.y & 0xFFFFu) : zero_row;
+        const int i3 = k0 + 3 < cnt ? (int)(q.y >> 16) : zero_row;
+        const float4 *r0 = reinterpret_cast<const float4 *>(rows + i0 * jbp + c0);
+        const float4 *r1 = reinterpret_cast<const float4 *>(rows + i1 * jbp + c0);
+        const float4 *r2 = reinterpret_cast<const float4 *>(rows + i2 * jbp + c0);
+        const float4 *r3 = reinterpret_cast<const float4 *>(rows + i3 * jbp + c0);
+        const float4 a0 = r0[0], b0 = r0[1], a1 = r1[0], b1 = r1[1];
+        const float4 a2 = r2[0], b2 = r2[1], a3 = r3[0], b3 = r3[1];
+        if (mode == RED_MAX) {
+            red4(mode, acc, a0), red4(mode, acc + 4, b0);
+            red4(mode, acc, a1), red4(mode, acc + 4, b1);
+            red4(mode, acc, a2), red4(mode, acc + 4, b2);
+            red4(mode, acc, a3), red4(mode, acc + 4, b3);
+        } else {
+            add4(acc, a0), add4(acc + 4, b0);
+            add4(acc, a1), add4(acc + 4, b1);
+            add4(acc, a2), add4(acc + 4, b2);
+            add4(acc, a3), add4(acc + 4, b3);
         }
-    };
-    int w0 = 0;
-    for (; w0 + 4 <= nwords; w0 += 4) {
-        const uint32_t m0 = words[w0], m1 = words[w0 + 1], m2 = words[w0 + 2], m3 = words[w0 + 3];
-        word(m0, 32 * w0);
-        word(m1, 32 * w0 + 32);
-        word(m2, 32 * w0 + 64);
-        word(m3, 32 * w0 + 96);
     }
-    for (; w0 < nwords; ++w0) word(words[w0], 32 * w0);
-    if (hp) acc = reduce2(mode, acc, pend);
-    return acc;
 }
 
-// One step of workgroup g.  W_lds holds the column block on entry (and the
-// updated block on exit when learning).
-__device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs &a, const StepPtrs &s, int g,
-                                                unsigned char *smem, const FusedLds &L)
+__global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const FusedLds L(p, blockDim.x);
+    const int g = blockIdx.x;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int nwaves = nt >> 6;
-    const int JB = p.jb;
-    const int jj = lane & 31;
-    const int bs = lane >> 5;
-    const int j = g * JB + jj;
-    const bool col_ok = jj < JB && j < p.n_exc;
+    const int JB = p.jb, JBP = p.jbp, ncg = p.jbp >> 3;
+    const int jj = tid & 31;
+    const int rg = tid >> 5;
+    const int nrg = nt >> 5;
 
     float *W_lds = reinterpret_cast<float *>(smem + L.w);
     float *xpost_lds = reinterpret_cast<float *>(smem + L.xpost);
-    uint32_t *bits_lds = reinterpret_cast<uint32_t *>(smem + L.bits);
     uint32_t *cprev_lds = reinterpret_cast<uint32_t *>(smem + L.cprev);
     uint32_t *cinh_lds = reinterpret_cast<uint32_t *>(smem + L.cinh);
     uint32_t *spk = reinterpret_cast<uint32_t *>(smem + L.spk);
     double *part = reinterpret_cast<double *>(smem + L.part);
     double *scale = reinterpret_cast<double *>(smem + L.scale);
     float *th_lds = reinterpret_cast<float *>(smem + L.theta);
+    float *Wg = a.W + (size_t)g * p.n_in_pad * JB;
 
-    // A: per-step inputs
-    copy_u4(bits_lds, s.bits, (size_t)p.B * p.in_words, tid, nt);
+    // A: weight block (row-padded to JBP, plus the zero row), small inputs
+    if (jj < JBP) {
+        int i = rg;
+        for (; i + 3 * nrg < p.n_in_pad; i += 4 * nrg) {
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+            if (jj < JB) {
+                v0 = Wg[(size_t)i * JB + jj];
+                v1 = Wg[(size_t)(i + nrg) * JB + jj];
+                v2 = Wg[(size_t)(i + 2 * nrg) * JB + jj];
+                v3 = Wg[(size_t)(i + 3 * nrg) * JB + jj];
+            }
+            W_lds[i * JBP + jj] = v0;
+            W_lds[(i + nrg) * JBP + jj] = v1;
+            W_lds[(i + 2 * nrg) * JBP + jj] = v2;
+            W_lds[(i + 3 * nrg) * JBP + jj] = v3;
+        }
+        for (; i < p.n_in_pad; i += nrg) W_lds[i * JBP + jj] = jj < JB ? Wg[(size_t)i * JB + jj] : 0.f;
+        if (rg == 0) {
+            W_lds[p.n_in_pad * JBP + jj] = 0.f;
+            if (p.learn) xpost_lds[p.B * JBP + jj] = 0.f;
+        }
+    }
     for (int b = tid; b < p.B; b += nt) {
         cprev_lds[b] = p.has_inh ? s.Cprev[b] : 0u;
         cinh_lds[b] = 0u;
@@ -157,37 +167,50 @@ __device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs
     }
     __syncthreads();
 
-    // B: contraction + neuron update, two samples per wave per round
-    const int spr = 2 * nwaves;
+    // B: contraction + neuron update, task (b, column group)
     const size_t sbase = (size_t)g * p.B * JB;
-    for (int b0 = 0; b0 < p.B; b0 += spr) {
-        const int b = b0 + 2 * wave + bs;
-        if (b < p.B) {
-            const size_t n = sbase + (size_t)b * JB + jj;
-            NeuronState st{0.f, 0.f, 0u, 0.f};
-            if (col_ok) {
-                st.ve = a.v_exc[n];
-                st.vi = p.has_inh ? a.v_inh[n] : 0.f;
-                st.rf = a.rf[n];
-                st.xpost = p.learn ? a.x_post[n] : 0.f;
-            }
-            const float acc = gather_bits(bits_lds + b * p.in_words, p.in_words, W_lds + (jj < JB ? jj : 0), JB,
-                                          RED_SUM);
-            if (col_ok) {
-                bool se, si;
-                neuron_update(p, acc, cprev_lds[b], th_lds[jj], st, se, si);
-                a.v_exc[n] = st.ve;
-                if (p.has_inh) a.v_inh[n] = st.vi;
-                a.rf[n] = (uint16_t)st.rf;
-                if (p.learn) {
-                    a.x_post[n] = st.xpost;
-                    xpost_lds[b * JB + jj] = st.xpost;
-                    if (se) atomicOr(&spk[jj * p.bwords + (b >> 5)], 1u << (b & 31));
-                }
-                if (si) atomicAdd(&cinh_lds[b], 1u);
-                write_outputs(p, a.o, s.k, b, j, se, si, st.ve, st.vi);
+    for (int q = tid; q < p.B * ncg; q += nt) {
+        const int b = q / ncg;
+        const int c0 = 8 * (q - b * ncg);
+        NeuronState st[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int jl = c0 + c;
+            st[c] = NeuronState{0.f, 0.f, 0u, 0.f};
+            if (jl < JB && g * JB + jl < p.n_exc) {
+                const size_t n = sbase + (size_t)b * JB + jl;
+                st[c].ve = a.v_exc[n];
+                st[c].vi = p.has_inh ? a.v_inh[n] : 0.f;
+                st[c].rf = a.rf[n];
+                st[c].xpost = p.learn ? a.x_post[n] : 0.f;
             }
         }
+        float acc[8];
+        gather8(s.lin + (size_t)b * p.n_in_pad, (int)s.cin[b], W_lds, JBP, c0, p.n_in_pad, RED_SUM, acc);
+        uint32_t cnt_inh = 0u;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int jl = c0 + c;
+            const int j = g * JB + jl;
+            if (jl < JB && j < p.n_exc) {
+                const size_t n = sbase + (size_t)b * JB + jl;
+                bool se, si;
+                neuron_update(p, acc[c], cprev_lds[b], th_lds[jl], st[c], se, si);
+                a.v_exc[n] = st[c].ve;
+                if (p.has_inh) a.v_inh[n] = st[c].vi;
+                a.rf[n] = (uint16_t)st[c].rf;
+                if (p.learn) {
+                    a.x_post[n] = st[c].xpost;
+                    xpost_lds[b * JBP + jl] = st[c].xpost;
+                    if (se) atomicOr(&spk[jl * p.bwords + (b >> 5)], 1u << (b & 31));
+                }
+                cnt_inh += si ? 1u : 0u;
+                write_outputs(p, a.o, s.k, b, j, se, si, st[c].ve, st[c].vi);
+            } else if (p.learn && jl < JBP) {
+                xpost_lds[b * JBP + jl] = 0.f;
+            }
+        }
+        if (cnt_inh) atomicAdd(&cinh_lds[b], cnt_inh);
     }
     __syncthreads();
     for (int b = tid; b < p.B; b += nt) {
@@ -196,44 +219,58 @@ __device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs
         if (g == 0 && s.Cnext) s.Cnext[b] = 0u;
     }
     if (!p.learn) return;
-    // the transposed input spikes replace the per-sample ones in LDS
-    copy_u4(bits_lds, s.bitsT, (size_t)p.n_in_pad * p.bwords, tid, nt);
 
-    // C1: potentiation.  For every column with post spikes this step, all
-    // threads sweep the rows: P[i] = R over the spiking samples b of
-    // x_pre[b, i] (coalesced over i), then W[i, j] += nu_post * P.
+    // C1: potentiation, W[i, c] += nu_post * R_{b spiking in c} x_pre[b, i]
     for (int c = 0; c < JB; ++c) {
         const uint32_t *sp = spk + c * p.bwords;
         uint32_t any = 0u;
         for (int bw = 0; bw < p.bwords; ++bw) any |= sp[bw];
         if (!any) continue;
         for (int i = tid; i < p.n_in; i += nt) {
-            float P = gather_bits(sp, p.bwords, s.xpre + i, p.n_in_pad, p.reduce);
+            float P = 0.f;
+            for (int bw = 0; bw < p.bwords; ++bw) {
+                uint32_t m = sp[bw];
+                while (m) {
+                    const int b = 32 * bw + __builtin_ctz(m);
+                    m &= m - 1;
+                    P = reduce2(p.reduce, P, s.xpre[(size_t)b * p.n_in_pad + i]);
+                }
+            }
             if (p.reduce == RED_MEAN) P *= p.inv_B;
-            W_lds[i * JB + c] = W_lds[i * JB + c] + p.nu_post * P;
+            W_lds[i * JBP + c] = W_lds[i * JBP + c] + p.nu_post * P;
         }
     }
     __syncthreads();
 
-    // C2: depression, clamp and column partial sums.  D[i, j] = R over the
-    // samples b in which input i spiked of x_post[b, j] (LDS gather).
-    const int rg = tid >> 5;
-    const int nrg = nt >> 5;
-    double cs = 0.0;
-    if (col_ok) {
-        for (int i = rg; i < p.n_in; i += nrg) {
-            float D = gather_bits(bits_lds + i * p.bwords, p.bwords, xpost_lds + jj, JB, p.reduce);
-            if (p.reduce == RED_MEAN) D *= p.inv_B;
-            const float w = fminf(fmaxf(W_lds[i * JB + jj] - p.nu_pre * D, p.w_min), p.w_max);
-            W_lds[i * JB + jj] = w;
-            cs += (double)w;
+    // C2: depression and clamp, task (i, column group)
+    for (int q = tid; q < p.n_in * ncg; q += nt) {
+        const int i = q / ncg;
+        const int c0 = 8 * (q - i * ncg);
+        float D[8];
+        gather8(s.lt + (size_t)i * p.lt_stride, (int)s.ct[i], xpost_lds, JBP, c0, p.B, p.reduce, D);
+        float4 *wr = reinterpret_cast<float4 *>(W_lds + i * JBP + c0);
+        const float4 w0 = wr[0], w1 = wr[1];
+        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float d = D[c];
+            if (p.reduce == RED_MEAN) d *= p.inv_B;
+            w[c] = fminf(fmaxf(w[c] - p.nu_pre * d, p.w_min), p.w_max);
         }
+        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
     }
+    __syncthreads();
+
+    // C3: column sums (FP64), normalisation factor, theta, write-back
+    double cs = 0.0;
+    if (jj < JB)
+        for (int i = rg; i < p.n_in; i += nrg) cs += (double)W_lds[i * JBP + jj];
     part[rg * 32 + jj] = cs;
     __syncthreads();
     if (tid < 32) {
         double c = 0.0;
-        for (int q = 0; q < nrg; ++q) c += part[q * 32 + tid];
+        for (int r = 0; r < nrg; ++r) c += part[r * 32 + tid];
         scale[tid] = (p.norm > 0.0 && c > 0.0) ? p.norm / c : 1.0;
         const int jt = g * JB + tid;
         if (tid < JB && jt < p.n_exc && p.adaptive) {
@@ -241,11 +278,6 @@ __device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs
             for (int bw = 0; bw < p.bwords; ++bw) cnt += __builtin_popcount(spk[tid * p.bwords + bw]);
             a.theta[jt] = theta_step(p, a.theta[jt], cnt);
         }
-    }
-    __syncthreads();
-    if (p.norm > 0.0 && col_ok) {
-        const double sc = scale[jj];
-        for (int i = rg; i < p.n_in; i += nrg) W_lds[i * JB + jj] = (float)((double)W_lds[i * JB + jj] * sc);
     }
 
     // E: presynaptic traces of the next step for this workgroup's samples
@@ -259,20 +291,52 @@ __device__ __forceinline__ void fused_step_body(const Params &p, const FusedArgs
         }
     }
     __syncthreads();
+    if (jj < JB) {
+        const bool do_scale = p.norm > 0.0;
+        const double sc = scale[jj];
+        for (int i = rg; i < p.n_in_pad; i += nrg) {
+            float w = W_lds[i * JBP + jj];
+            if (do_scale && i < p.n_in) w = (float)((double)w * sc);
+            Wg[(size_t)i * JB + jj] = w;
+        }
+    }
 }
 
-__global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
+// Sparse index lists of one chunk of encoded steps:
+//   lin[t][b][0 .. cin[t][b])  inputs that spiked in sample b (increasing)
+//   lt [t][i][0 .. ct[t][i])   samples in which input i spiked (increasing)
+__global__ void k_lists(Params p, const uint32_t *__restrict__ bits, const uint32_t *__restrict__ bitsT,
+                        uint16_t *__restrict__ lin, uint32_t *__restrict__ cin, uint16_t *__restrict__ lt,
+                        uint32_t *__restrict__ ct, int with_t)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const FusedLds L(p, blockDim.x);
-    const int g = blockIdx.x;
-    float *W_lds = reinterpret_cast<float *>(smem + L.w);
-    float *Wg = a.W + (size_t)g * p.n_in_pad * p.jb;
-    const size_t nw = (size_t)p.n_in_pad * p.jb;
-    copy_u4(W_lds, Wg, nw, threadIdx.x, blockDim.x);
-    __syncthreads();
-    fused_step_body(p, a, s, g, smem, L);
-    if (p.learn) copy_u4(Wg, W_lds, nw, threadIdx.x, blockDim.x);
+    const int t = blockIdx.y;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < p.B) {
+        const uint32_t *w = bits + (size_t)t * p.bits_stride + (size_t)q * p.in_words;
+        uint16_t *out = lin + ((size_t)t * p.B + q) * p.n_in_pad;
+        uint32_t n = 0;
+        for (int k = 0; k < p.in_words; ++k) {
+            uint32_t m = w[k];
+            while (m) {
+                out[n++] = (uint16_t)(32 * k + __builtin_ctz(m));
+                m &= m - 1;
+            }
+        }
+        cin[(size_t)t * p.B + q] = n;
+    }
+    if (with_t && q < p.n_in_pad) {
+        const uint32_t *w = bitsT + ((size_t)t * p.n_in_pad + q) * p.bwords;
+        uint16_t *out = lt + ((size_t)t * p.n_in_pad + q) * p.lt_stride;
+        uint32_t n = 0;
+        for (int k = 0; k < p.bwords; ++k) {
+            uint32_t m = w[k];
+            while (m) {
+                out[n++] = (uint16_t)(32 * k + __builtin_ctz(m));
+                m &= m - 1;
+            }
+        }
+        ct[(size_t)t * p.n_in_pad + q] = n;
+    }
 }
 
 }  // namespace snn

@@ -36,8 +36,14 @@ struct snn_net {
     uint16_t *rf = nullptr;
     float *x_pre = nullptr;      // 2 x B x n_in_pad
     uint32_t *C = nullptr;       // 3 x B
-    uint32_t *bits = nullptr;    // kChunk x B x in_words
-    uint32_t *bitsT = nullptr;   // kChunk x n_in_pad x bwords
+    uint32_t *bits = nullptr;    // (chunk + 1) steps of input spikes, per sample
+    uint32_t *bitsT = nullptr;   //   and per input
+    uint16_t *lin = nullptr;     // (chunk + 1) x B x n_in_pad input spike lists
+    uint32_t *cin = nullptr;
+    uint16_t *lt = nullptr;      // (chunk + 1) x n_in_pad x lt_stride sample lists
+    uint32_t *ct = nullptr;
+    uint32_t chunk = kChunk;     // steps per encoder launch for the current batch
+    uint32_t cap_chunk = kChunk; // steps the buffers hold at capacity
     uint8_t *flags_mask = nullptr;
 
     // optional per-kernel timing with HIP events on the handle's stream

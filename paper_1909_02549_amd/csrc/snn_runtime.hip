@@ -66,14 +66,24 @@ static int device_cu_count()
     return cus;
 }
 
-// Column block width: enough blocks to give every CU one block when the
-// layer is large, at least 16 columns per block otherwise.
+// Column block width: one block per CU when the layer is large (at most 32
+// columns, the fused kernel's limit), at least 8 columns otherwise.
 static int choose_jb(uint32_t n_exc, int cus)
 {
     int jb = (int)((n_exc + (uint32_t)cus - 1) / (uint32_t)cus);
-    if (jb < 16) jb = 16;
-    if (jb > 64) jb = 64;
+    if (jb < 8) jb = 8;
+    if (jb > 32) jb = 32;
     return jb;
+}
+
+// Steps per encoder chunk: the sparse lists take B * n_in_pad and
+// n_in_pad * round8(B) u16 per step; keep one chunk under 256 MiB.
+static uint32_t chunk_steps(const Params &p, uint32_t B)
+{
+    const size_t per = ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2 + 16 * (size_t)B;
+    size_t c = ((size_t)256 << 20) / std::max<size_t>(per, 1);
+    c = std::min<size_t>(std::max<size_t>(c, 8), kChunk);
+    return (uint32_t)c;
 }
 
 static void fill_dims(Params &p, const snn_config &c, int jb)
@@ -83,16 +93,20 @@ static void fill_dims(Params &p, const snn_config &c, int jb)
     p.n_in_pad = 32 * p.in_words;
     p.n_exc = (int)c.n_exc;
     p.jb = jb;
+    p.jbp = (jb + 7) & ~7;
     p.nblk = (int)((c.n_exc + jb - 1) / jb);
     p.n_pad = p.nblk * jb;
     p.has_inh = c.n_inh > 0;
 }
 
-static size_t state_bytes(const Params &p, uint32_t B, uint32_t chunk)
+static size_t state_bytes(const Params &p, uint32_t B)
 {
+    const uint32_t chunk = chunk_steps(p, B);
     const size_t ns = (size_t)p.n_pad * B;
     const size_t bw = (B + 31) / 32;
     size_t s = 0;
+    s += (size_t)(chunk + 1) * ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2;  // lists
+    s += (size_t)(chunk + 1) * ((size_t)B + p.n_in_pad) * 4;                                       // lengths
     s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
     s += 2 * (size_t)B * p.n_in_pad * 4;            // x_pre
     s += 3 * (size_t)B * 4;                         // C
@@ -252,11 +266,12 @@ snn_net::~snn_net()
 void snn_net::free_state()
 {
     for (void *q : {(void *)v_exc, (void *)v_inh, (void *)x_post, (void *)I, (void *)rf, (void *)x_pre, (void *)C,
-                    (void *)bits, (void *)bitsT, (void *)flags_mask})
+                    (void *)bits, (void *)bitsT, (void *)flags_mask, (void *)lin, (void *)cin, (void *)lt, (void *)ct})
         if (q) (void)hipFree(q);
     v_exc = v_inh = x_post = I = x_pre = nullptr;
     rf = nullptr;
-    C = bits = bitsT = nullptr;
+    lin = lt = nullptr;
+    C = bits = bitsT = cin = ct = nullptr;
     flags_mask = nullptr;
     cap_B = 0;
     cur_B = 0;
@@ -410,7 +425,7 @@ extern "C" size_t snn_state_bytes(const snn_config *cfg, uint32_t batch)
     if (!cfg || validate(cfg) != SNN_OK) return 0;
     Params p{};
     fill_dims(p, *cfg, choose_jb(cfg->n_exc, device_cu_count()));
-    return state_bytes(p, batch, kChunk) + param_bytes(p);
+    return state_bytes(p, batch) + param_bytes(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,7 +435,7 @@ extern "C" size_t snn_state_bytes(const snn_config *cfg, uint32_t batch)
 snn_status snn_net::ensure_state(uint32_t B)
 {
     if (B > cfg.max_batch) return fail(SNN_ENOMEM, "batch exceeds max_batch");
-    if (cfg.hbm_budget_bytes && state_bytes(p, B, kChunk) + param_bytes(p) > cfg.hbm_budget_bytes)
+    if (cfg.hbm_budget_bytes && state_bytes(p, B) + param_bytes(p) > cfg.hbm_budget_bytes)
         return fail(SNN_ENOMEM, "batch exceeds hbm_budget_bytes");
     if (B > cap_B) {
         HIP_TRY(hipStreamSynchronize(stream));
@@ -438,14 +453,22 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&rf, ns * 2);
         A((void **)&x_pre, 2 * (size_t)B * p.n_in_pad * 4);
         A((void **)&C, 3 * (size_t)B * 4);
-        A((void **)&bits, (size_t)(kChunk + 1) * ((size_t)B * p.in_words + 3) * 4);
-        A((void **)&bitsT, (size_t)(kChunk + 1) * p.n_in_pad * bw * 4);
+        const uint32_t ch = chunk_steps(p, B);
+        const size_t lts = (B + 7) & ~7u;
+        A((void **)&bits, (size_t)(ch + 1) * ((size_t)B * p.in_words + 3) * 4);
+        A((void **)&bitsT, (size_t)(ch + 1) * p.n_in_pad * bw * 4);
+        A((void **)&lin, (size_t)(ch + 1) * B * p.n_in_pad * 2);
+        A((void **)&cin, (size_t)(ch + 1) * B * 4);
+        A((void **)&lt, (size_t)(ch + 1) * p.n_in_pad * lts * 2);
+        A((void **)&ct, (size_t)(ch + 1) * p.n_in_pad * 4);
         A((void **)&flags_mask, B);
         if (e != hipSuccess) {
             free_state();
             return fail(SNN_ENOMEM, std::string("state hipMalloc: ") + hipGetErrorString(e));
         }
         cap_B = B;
+        cap_chunk = ch;
+        chunk = ch;
         graphs_invalidate();
     }
     return SNN_OK;
@@ -458,6 +481,9 @@ void snn_net::set_batch(uint32_t B)
     p.inv_B = 1.f / (float)B;
     p.inv_Bd = 1.0 / (double)B;
     p.bits_stride = (int)((((size_t)B * p.in_words) + 3) & ~(size_t)3);
+    p.lt_stride = (int)((B + 7) & ~7u);
+    // never more steps than the buffers were sized for at capacity
+    chunk = std::min(chunk_steps(p, B), cap_chunk);
 }
 
 snn_status snn_net::reset_state(const uint8_t *mask_dev)
@@ -586,7 +612,7 @@ snn_status snn_net::xpre_first(const uint32_t *bits_t)
 
 bool snn_net::fused_ok() const
 {
-    return p.jb <= 32 && fused_lds_bytes(p) <= kMaxLds;
+    return p.jb <= 32 && p.n_in_pad < 65535 && p.B < 65535 && fused_lds_bytes(p) <= kMaxLds;
 }
 
 snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
@@ -596,6 +622,10 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.bits = bits + (size_t)kk * p.bits_stride;
     s.bitsT = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
     s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.bits_stride : nullptr;
+    s.lin = lin + (size_t)kk * p.B * p.n_in_pad;
+    s.cin = cin + (size_t)kk * p.B;
+    s.lt = lt + (size_t)kk * p.n_in_pad * p.lt_stride;
+    s.ct = ct + (size_t)kk * p.n_in_pad;
     s.xpre = x_pre + (size_t)cur * p.B * p.n_in_pad;
     s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
     s.Ccur = C + (size_t)(gstep % 3) * p.B;
@@ -618,14 +648,18 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
                               uint32_t T, const Outs &o)
 {
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
-    for (uint32_t k0 = 0; k0 < T; k0 += kChunk) {
-        const int steps = (int)std::min<uint32_t>(kChunk, T - k0);
+    for (uint32_t k0 = 0; k0 < T; k0 += chunk) {
+        const int steps = (int)std::min<uint32_t>(chunk, T - k0);
         const bool more = k0 + (uint32_t)steps < T;
         const int enc_steps = steps + (more ? 1 : 0);
         const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
         snn_status st = encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
         if (st != SNN_OK) return st;
         if (path == SNN_PATH_FUSED) {
+            const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
+            SNN_LAUNCH("lists", k_lists, dim3((unsigned)((nq + 255) / 256), (unsigned)enc_steps), dim3(256), 0, p,
+                       (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, p.learn);
+            HIP_TRY(hipGetLastError());
             if (k0 == 0 && p.learn) {
                 st = xpre_first(bits);
                 if (st != SNN_OK) return st;
