@@ -5,7 +5,8 @@
 //   g = j / JB, jj = j % JB; every per-neuron array and the weight matrix are
 //   block-major, so one column block (the unit a fused or plasticity
 //   workgroup owns) is one contiguous span:
-//     state(b, j)  at (g * B + b) * JB + jj        (v_exc, v_inh, x_post, rf)
+//     state(b, j)  at (g * B + b) * JBP + jj       (v_exc, v_inh, x_post, rf)
+//                  (JBP = JB rounded up to 8: 32-byte aligned 8-neuron groups)
 //     W(i, j)      at (g * n_in_pad + i) * JB + jj (FP32 master)
 //   inputs are padded to n_in_pad = 32 * in_words; pad inputs never spike
 //   and their weights stay 0.

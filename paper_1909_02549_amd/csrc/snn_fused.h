@@ -1,12 +1,31 @@
-// snn_fused.h -- argument blocks of the fused / persistent step kernels.
+// snn_fused.h -- the column-block step shared by the fused (one launch per
+// step) and persistent (one cooperative launch per chunk of steps) kernels.
+//
+// Workgroup g owns the JB post-synaptic columns [g*JB, g*JB+JB) for every
+// sample of the batch: their weight block W[:, cols] (in LDS), their neuron
+// state and their adaptive thresholds.  What the method couples across
+// columns is small: the per-sample inhibitory spike count C[b] (all-but-self
+// inhibition) and the presynaptic traces x_pre (read by every column).
+//
+// In LDS the weight block and the post traces are stored with JBP = JB
+// rounded up to 8 columns per row plus one all-zero row, so a thread owning 8
+// consecutive columns reads a row with two 16-byte loads, and the padding
+// slots of an index list point at the zero row (adding +0 changes no sum).
+//
+// Column normalisation is kept lazily: after a learning step the block holds
+// the clamped, not yet normalised weights and scale[c] = norm / sum_i W[i, c]
+// (FP64); the next step applies it (w <- float(w * scale)) when it updates
+// the weight, the contraction multiplies its column sum by it, and the block
+// is written back to HBM normalised.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "snn_dev.h"
+#include "snn_kern.h"
 
 namespace snn {
 
-constexpr int kFusedThreads = 1024;  // 16 waves; two samples per wave per round
+constexpr int kFusedThreads = 1024;  // 16 waves
 
 // Per-network pointers (state and parameters owned by the handle).
 struct FusedArgs {
@@ -20,7 +39,6 @@ struct FusedArgs {
 // Per-step pointers.
 struct StepPtrs {
     const uint32_t *bits;       // input spikes of step t, B x in_words
-    const uint32_t *bitsT;      // the same, n_in_pad x bwords
     const uint32_t *bits_next;  // input spikes of step t + 1 (nullptr: none)
     const uint16_t *lin;        // per-sample input spike lists of step t
     const uint32_t *cin;        //   and their lengths
@@ -34,9 +52,485 @@ struct StepPtrs {
     int k;                      // step index within the call (outputs)
 };
 
+// Pointers of one chunk of steps run by a persistent launch.
+struct ChunkPtrs {
+    const uint32_t *bits;  // input spikes of the chunk's steps (+1 if has_next)
+    const uint16_t *lin;
+    const uint32_t *cin;
+    const uint16_t *lt;
+    const uint32_t *ct;
+    float *xpre;           // 2 x B x n_in_pad, x_pre(s) in buffer s & 1
+    uint32_t *C;           // 3 x B, inhibitory counts of step s in slot s % 3
+    int steps;             // steps to run
+    int has_next;          // inputs of step `steps` are encoded (x_pre ahead)
+    int par0, mod0;        // (s & 1), (s % 3) of the first step
+    int k0;                // output index of the first step
+};
+
+// Cross-workgroup state of one persistent launch.
+struct PersistSync {
+    uint32_t *bar;  // arrival counter, zeroed before the launch
+    uint32_t *err;  // set to 1 if a barrier wait timed out
+};
+
+// Arguments of a persistent launch, read from device memory (kept out of
+// scalar registers: the kernel is register-bound).
+struct PersistArgs {
+    Params p;
+    FusedArgs a;
+    ChunkPtrs ch;
+    PersistSync sy;
+};
+
 size_t fused_lds_bytes(const Params &p);
+size_t persist_lds_bytes(const Params &p);
 __global__ void k_fused_step(Params p, FusedArgs a, StepPtrs s);
+__global__ void k_persist(const PersistArgs *args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
+
+// ---------------------------------------------------------------------------
+// device building blocks
+// ---------------------------------------------------------------------------
+
+// Accesses to data another workgroup of the same persistent launch writes
+// (next-step presynaptic traces, inhibitory counts) are agent-scope atomic
+// loads / stores: they are coherent across the XCDs' separate L2 caches, so
+// the grid barrier needs no cache write-back or invalidation and read-only
+// data stays cached.  The fused per-step kernel passes Coherent = false
+// (kernel boundaries order its exchanges).
+template <bool Coherent>
+__device__ __forceinline__ float ld_x(const float *ptr)
+{
+    if (Coherent) return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *ptr;
+}
+
+template <bool Coherent>
+__device__ __forceinline__ uint32_t ld_u(const uint32_t *ptr)
+{
+    if (Coherent) return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *ptr;
+}
+
+template <bool Coherent, typename T>
+__device__ __forceinline__ void st_x(T *ptr, T v)
+{
+    if (Coherent) __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *ptr = v;
+}
+
+// LDS carve-up shared by host (size) and device (offsets).
+struct FusedLds {
+    size_t w, xpost, cprev, cinh, spk, colmask, ulist, part, scale, theta, theta64, total;
+    __host__ __device__ FusedLds(const Params &p, int nthreads)
+    {
+        size_t o = 0;
+        w = o;
+        o += align16((size_t)(p.n_in_pad + 1) * p.jbp * 4);
+        xpost = o;
+        o += p.learn ? align16((size_t)(p.B + 1) * p.jbp * 4) : 0;
+        cprev = o;
+        o += align16((size_t)p.B * 4);
+        cinh = o;
+        o += align16((size_t)p.B * 4);
+        spk = o;
+        o += align16((size_t)p.jb * p.bwords * 4);
+        colmask = o;
+        o += align16((size_t)p.B * 4);
+        ulist = o;
+        o += align16((size_t)(p.B + 1) * 4);
+        part = o;
+        o += align16((size_t)(nthreads / 32) * 32 * 8);
+        scale = o;
+        o += 32 * 8;
+        theta = o;
+        o += 32 * 4;
+        theta64 = o;
+        o += 32 * 8;
+        total = o;
+    }
+};
+
+// Named views of the LDS regions.
+struct StepLds {
+    float *W, *xpost, *th;
+    uint32_t *cprev, *cinh, *spk, *colmask, *ulist;
+    double *part, *scale, *th64;
+    __device__ StepLds(unsigned char *smem, const FusedLds &L)
+        : W(reinterpret_cast<float *>(smem + L.w)), xpost(reinterpret_cast<float *>(smem + L.xpost)),
+          th(reinterpret_cast<float *>(smem + L.theta)), cprev(reinterpret_cast<uint32_t *>(smem + L.cprev)),
+          cinh(reinterpret_cast<uint32_t *>(smem + L.cinh)), spk(reinterpret_cast<uint32_t *>(smem + L.spk)),
+          colmask(reinterpret_cast<uint32_t *>(smem + L.colmask)),
+          ulist(reinterpret_cast<uint32_t *>(smem + L.ulist)), part(reinterpret_cast<double *>(smem + L.part)),
+          scale(reinterpret_cast<double *>(smem + L.scale)), th64(reinterpret_cast<double *>(smem + L.theta64))
+    {
+    }
+};
+
+__device__ __forceinline__ void add4(float *acc, const float4 v)
+{
+    acc[0] += v.x;
+    acc[1] += v.y;
+    acc[2] += v.z;
+    acc[3] += v.w;
+}
+
+__device__ __forceinline__ void red4(int mode, float *acc, const float4 v)
+{
+    acc[0] = reduce2(mode, acc[0], v.x);
+    acc[1] = reduce2(mode, acc[1], v.y);
+    acc[2] = reduce2(mode, acc[2], v.z);
+    acc[3] = reduce2(mode, acc[3], v.w);
+}
+
+// Four list entries (two u32 words of u16 indices) -> acc[0..8) R= rows.
+__device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const float *rows, int jbp, int c0, int zero_row,
+                                            int mode, float *acc)
+{
+    const int i0 = (int)(q.x & 0xFFFFu);
+    const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
+    const int i2 = k0 + 2 < cnt ? (int)(q.y & 0xFFFFu) : zero_row;
+    const int i3 = k0 + 3 < cnt ? (int)(q.y >> 16) : zero_row;
+    const float4 *r0 = reinterpret_cast<const float4 *>(rows + i0 * jbp + c0);
+    const float4 *r1 = reinterpret_cast<const float4 *>(rows + i1 * jbp + c0);
+    const float4 *r2 = reinterpret_cast<const float4 *>(rows + i2 * jbp + c0);
+    const float4 *r3 = reinterpret_cast<const float4 *>(rows + i3 * jbp + c0);
+    const float4 a0 = r0[0], b0 = r0[1], a1 = r1[0], b1 = r1[1];
+    const float4 a2 = r2[0], b2 = r2[1], a3 = r3[0], b3 = r3[1];
+    if (mode == RED_MAX) {
+        red4(mode, acc, a0), red4(mode, acc + 4, b0);
+        red4(mode, acc, a1), red4(mode, acc + 4, b1);
+        red4(mode, acc, a2), red4(mode, acc + 4, b2);
+        red4(mode, acc, a3), red4(mode, acc + 4, b3);
+    } else {
+        add4(acc, a0), add4(acc + 4, b0);
+        add4(acc, a1), add4(acc + 4, b1);
+        add4(acc, a2), add4(acc + 4, b2);
+        add4(acc, a3), add4(acc + 4, b3);
+    }
+}
+
+// acc[0..8) = R over the first `cnt` entries of `list` (u16 row indices, in
+// list order) of rows[idx * jbp + c0 .. + 8), four rows in flight at a time;
+// slots past cnt read row `zero_row` (all zeros).  The first `nhead` (4 or
+// 8) entries are passed in registers (head0, head1), loaded ahead of time.
+__device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int cnt, uint2 head0, uint2 head1,
+                                        int nhead, const float *rows, int jbp, int c0, int zero_row, int mode,
+                                        float *acc)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
+    for (int k0 = 0; k0 < cnt; k0 += 4) {
+        const uint2 q = k0 == 0 ? head0 : (k0 == 4 && nhead == 8) ? head1 : l4[k0 >> 2];
+        gather4rows(q, k0, cnt, rows, jbp, c0, zero_row, mode, acc);
+    }
+}
+
+// Step phase A: C(t-1) and per-step scratch in LDS, threshold offsets.
+// theta64 holds the workgroup's thresholds (FP64).
+template <bool Coherent>
+__device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, const uint32_t *Cprev, int tid, int nt)
+{
+    for (int q = tid; q < p.B; q += nt) {
+        S.cprev[q] = p.has_inh ? ld_u<Coherent>(Cprev + q) : 0u;
+        S.cinh[q] = 0u;
+        S.colmask[q] = 0u;
+    }
+    for (int q = tid; q < p.jb * p.bwords; q += nt) S.spk[q] = 0u;
+    if (tid < 32) S.th[tid] = theta_offset(p, S.th64[tid]);
+}
+
+// Step phase B for one task: 8 neurons j0+c of sample b (c < nv real).
+// acc: column sums of the sample's input spikes over the LDS block (raw,
+// before the pending scale).  Updates the register state, the post traces in
+// LDS, the spike masks and the inhibitory count; writes requested outputs.
+__device__ __forceinline__ void neuron_task(const Params &p, const StepLds &S, const Outs &o, int k, int b, int c0,
+                                            int j0, int nv, const float *acc, float *ve, float *vi, uint32_t *rw)
+{
+    float xp[8];
+    if (p.learn) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0);
+        const float4 x1 = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0 + 4);
+        xp[0] = x0.x, xp[1] = x0.y, xp[2] = x0.z, xp[3] = x0.w;
+        xp[4] = x1.x, xp[5] = x1.y, xp[6] = x1.z, xp[7] = x1.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xp[c] = 0.f;
+    }
+    uint32_t cm = 0u, se_m = 0u, si_m = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int jl = c0 + c;
+        if (c < nv) {
+            const float I = (float)((double)acc[c] * S.scale[jl]);
+            NeuronState st{ve[c], vi[c], (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu, xp[c]};
+            bool se, si;
+            neuron_update(p, I, S.cprev[b], S.th[jl], st, se, si);
+            ve[c] = st.ve;
+            vi[c] = st.vi;
+            xp[c] = st.xpost;
+            rw[c >> 1] = (rw[c >> 1] & ~(0xFFFFu << (16 * (c & 1)))) | (st.rf << (16 * (c & 1)));
+            se_m |= (se ? 1u : 0u) << c;
+            si_m |= (si ? 1u : 0u) << c;
+            if (p.learn && se) {
+                atomicOr(&S.spk[jl * p.bwords + (b >> 5)], 1u << (b & 31));
+                cm |= 1u << jl;
+            }
+        } else {
+            xp[c] = 0.f;
+        }
+    }
+    if (p.learn) {
+        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0) = make_float4(xp[0], xp[1], xp[2], xp[3]);
+        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0 + 4) = make_float4(xp[4], xp[5], xp[6], xp[7]);
+        if (cm) atomicOr(&S.colmask[b], cm);
+    }
+    if (si_m) atomicAdd(&S.cinh[b], (uint32_t)__builtin_popcount(si_m));
+    write_outputs8(p, o, k, b, j0, nv, se_m, si_m, ve, vi);
+}
+
+// After phase B: publish the inhibitory counts, clear the next step's slot
+// (workgroup 0), and list the samples with any post spike in this block in
+// increasing order (wave 0, ballots).  ulist[B] holds their number.
+template <bool Coherent>
+__device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, uint32_t *Ccur, uint32_t *Cnext, int g,
+                                             int tid, int nt)
+{
+    for (int q = tid; q < p.B; q += nt) {
+        const uint32_t c = S.cinh[q];
+        if (c) atomicAdd(&Ccur[q], c);
+        if (g == 0 && Cnext) st_x<Coherent>(Cnext + q, 0u);
+    }
+    if (p.learn && tid < 64) {
+        uint32_t base = 0;
+        for (int b0 = 0; b0 < p.B; b0 += 64) {
+            const int b = b0 + tid;
+            const bool hit = b < p.B && S.colmask[b] != 0u;
+            const uint64_t m = __ballot(hit);
+            if (hit) S.ulist[base + __popcll(m & ((1ull << tid) - 1ull))] = (uint32_t)b;
+            base += (uint32_t)__popcll(m);
+        }
+        if (tid == 0) S.ulist[p.B] = base;
+    }
+}
+
+// Step phase C for one task: input row i, columns c0 .. c0+7.
+//   P[c] = R over listed spiking samples b with neuron c fired of x_pre[b, i]
+//   D[c] = R over the samples in input i's spike list of x_post[b, c]
+//   w = clamp(float(w * scale[c]) + nu_post * P[c] - nu_pre * D[c])
+// The x_pre loads of up to eight samples are issued before the D gather.
+template <bool Coherent>
+__device__ __forceinline__ void plasticity_task(const Params &p, const StepLds &S, int i, int c0, int cnt, uint2 head,
+                                                const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany)
+{
+    float P[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) P[c] = 0.f;
+    const uint32_t grp = (colany >> c0) & 0xFFu;
+    if (grp) {
+        for (int u0 = 0; u0 < ucnt; u0 += 8) {
+            float x[8];
+            uint32_t cm[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                cm[v] = 0u;
+                x[v] = 0.f;
+                if (u0 + v < ucnt) {
+                    const int b = (int)S.ulist[u0 + v];
+                    cm[v] = (S.colmask[b] >> c0) & 0xFFu;
+                    if (cm[v]) x[v] = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((cm[v] >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+        }
+    }
+    float D[8];
+    gather8(ltrow, cnt, head, head, 4, S.xpost, p.jbp, c0, p.B, p.reduce, D);
+    float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.jbp + c0);
+    const float4 w0 = wr[0], w1 = wr[1];
+    float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float x = (float)((double)w[c] * S.scale[c0 + c]);
+        if ((grp >> c) & 1u) x = x + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
+        const float d = p.reduce == RED_MEAN ? D[c] * p.inv_B : D[c];
+        w[c] = fminf(fmaxf(x - p.nu_pre * d, p.w_min), p.w_max);
+    }
+    wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+    wr[1] = make_float4(w[4], w[5], w[6], w[7]);
+}
+
+// Phase C over all (row, column group) tasks of the block; each thread loads
+// the next task's list head before working on the current one.
+template <bool Coherent>
+__device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
+                                               const uint32_t *ct, const float *xpre, int tid, int nt)
+{
+    const int ncg = p.jbp >> 3;
+    const int ucnt = (int)S.ulist[p.B];
+    uint32_t colany = 0u;
+    for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
+    const int ntask = p.n_in * ncg;
+    int q = tid;
+    uint32_t cnt_n = 0u;
+    uint2 head_n = make_uint2(0u, 0u);
+    if (q < ntask) {
+        const int i = q / ncg;
+        cnt_n = ct[i];
+        head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)i * p.lt_stride);
+    }
+    while (q < ntask) {
+        const int i = q / ncg;
+        const int c0 = 8 * (q - i * ncg);
+        const uint32_t cnt = cnt_n;
+        const uint2 head = head_n;
+        const int qn = q + nt;
+        if (qn < ntask) {
+            const int inx = qn / ncg;
+            cnt_n = ct[inx];
+            head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)inx * p.lt_stride);
+        }
+        plasticity_task<Coherent>(p, S, i, c0, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany);
+        q = qn;
+    }
+}
+
+// Phase C3: FP64 column sums of the updated block, the pending
+// normalisation scale, the threshold update.  Two workgroup barriers.
+__device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, int tid, int nt)
+{
+    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
+    double cs = 0.0;
+    if (jj < p.jb)
+        for (int i = rg; i < p.n_in; i += nrg) cs += (double)S.W[i * p.jbp + jj];
+    S.part[rg * 32 + jj] = cs;
+    __syncthreads();
+    if (tid < 32) {
+        double c = 0.0;
+        for (int r = 0; r < nrg; ++r) c += S.part[r * 32 + tid];
+        S.scale[tid] = (p.norm > 0.0 && c > 0.0 && tid < p.jb) ? p.norm / c : 1.0;
+        if (p.adaptive && tid < p.jb) {
+            int cnt = 0;
+            for (int bw = 0; bw < p.bwords; ++bw) cnt += __builtin_popcount(S.spk[tid * p.bwords + bw]);
+            S.th64[tid] = theta_step(p, S.th64[tid], cnt);
+        }
+    }
+    __syncthreads();
+}
+
+// Phase E: x_pre(t+1) for this workgroup's share of the samples.
+template <bool Coherent>
+__device__ __forceinline__ void xpre_next(const Params &p, const uint32_t *bits_next, const float *xpre, float *xn_all,
+                                          int g, int ng, int tid, int nt)
+{
+    for (int b = g; b < p.B; b += ng) {
+        const uint32_t *sb = bits_next + (size_t)b * p.in_words;
+        const float *xc = xpre + (size_t)b * p.n_in_pad;
+        float *xn = xn_all + (size_t)b * p.n_in_pad;
+        for (int i = tid; i < p.n_in_pad; i += nt)
+            st_x<Coherent>(xn + i, trace_step(ld_x<Coherent>(xc + i), p.lam_pre, (sb[i >> 5] >> (i & 31)) & 1u,
+                                              p.trace_add));
+    }
+}
+
+// Prologue of both kernels: weight block (row-padded, zero row), thresholds,
+// pending scale 1.
+__device__ __forceinline__ void load_block(const Params &p, const StepLds &S, const float *Wg, const double *theta,
+                                           int g, int tid, int nt)
+{
+    const int JB = p.jb, JBP = p.jbp;
+    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
+    if (jj < JBP) {
+        int i = rg;
+        for (; i + 3 * nrg < p.n_in_pad; i += 4 * nrg) {
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+            if (jj < JB) {
+                v0 = Wg[(size_t)i * JB + jj];
+                v1 = Wg[(size_t)(i + nrg) * JB + jj];
+                v2 = Wg[(size_t)(i + 2 * nrg) * JB + jj];
+                v3 = Wg[(size_t)(i + 3 * nrg) * JB + jj];
+            }
+            S.W[i * JBP + jj] = v0;
+            S.W[(i + nrg) * JBP + jj] = v1;
+            S.W[(i + 2 * nrg) * JBP + jj] = v2;
+            S.W[(i + 3 * nrg) * JBP + jj] = v3;
+        }
+        for (; i < p.n_in_pad; i += nrg) S.W[i * JBP + jj] = jj < JB ? Wg[(size_t)i * JB + jj] : 0.f;
+        if (rg == 0) {
+            S.W[p.n_in_pad * JBP + jj] = 0.f;
+            if (p.learn) S.xpost[p.B * JBP + jj] = 0.f;
+        }
+    }
+    if (tid < 32) {
+        const int jt = g * JB + tid;
+        S.th64[tid] = (tid < JB && jt < p.n_exc) ? theta[jt] : 0.0;
+        S.scale[tid] = 1.0;
+    }
+}
+
+// Epilogue of a learning launch: the block, normalised, and the thresholds.
+__device__ __forceinline__ void store_block(const Params &p, const StepLds &S, float *Wg, double *theta, int g,
+                                            int tid, int nt)
+{
+    const int JB = p.jb, JBP = p.jbp;
+    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
+    if (jj < JB) {
+        const double sc = S.scale[jj];
+        for (int i = rg; i < p.n_in_pad; i += nrg) {
+            float w = S.W[i * JBP + jj];
+            if (i < p.n_in) w = (float)((double)w * sc);
+            Wg[(size_t)i * JB + jj] = w;
+        }
+    }
+    if (tid < JB && g * JB + tid < p.n_exc) theta[g * JB + tid] = S.th64[tid];
+}
+
+// State of the 8 neurons of task (b, c0): voltages, packed refractory words,
+// post traces (into LDS), from / to the HBM arrays.
+__device__ __forceinline__ void load_task_state(const Params &p, const StepLds &S, const FusedArgs &a, size_t n0, int b,
+                                                int c0, float *ve, float *vi, uint32_t *rw)
+{
+    const float4 e0 = *reinterpret_cast<const float4 *>(a.v_exc + n0);
+    const float4 e1 = *reinterpret_cast<const float4 *>(a.v_exc + n0 + 4);
+    ve[0] = e0.x, ve[1] = e0.y, ve[2] = e0.z, ve[3] = e0.w, ve[4] = e1.x, ve[5] = e1.y, ve[6] = e1.z, ve[7] = e1.w;
+    if (p.has_inh) {
+        const float4 i0 = *reinterpret_cast<const float4 *>(a.v_inh + n0);
+        const float4 i1 = *reinterpret_cast<const float4 *>(a.v_inh + n0 + 4);
+        vi[0] = i0.x, vi[1] = i0.y, vi[2] = i0.z, vi[3] = i0.w, vi[4] = i1.x, vi[5] = i1.y, vi[6] = i1.z, vi[7] = i1.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) vi[c] = 0.f;
+    }
+    if (p.learn) {
+        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0) = *reinterpret_cast<const float4 *>(a.x_post + n0);
+        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0 + 4) =
+            *reinterpret_cast<const float4 *>(a.x_post + n0 + 4);
+    }
+    const uint4 r = *reinterpret_cast<const uint4 *>(a.rf + n0);
+    rw[0] = r.x, rw[1] = r.y, rw[2] = r.z, rw[3] = r.w;
+}
+
+__device__ __forceinline__ void store_task_state(const Params &p, const StepLds &S, const FusedArgs &a, size_t n0,
+                                                 int b, int c0, const float *ve, const float *vi, const uint32_t *rw)
+{
+    *reinterpret_cast<float4 *>(a.v_exc + n0) = make_float4(ve[0], ve[1], ve[2], ve[3]);
+    *reinterpret_cast<float4 *>(a.v_exc + n0 + 4) = make_float4(ve[4], ve[5], ve[6], ve[7]);
+    if (p.has_inh) {
+        *reinterpret_cast<float4 *>(a.v_inh + n0) = make_float4(vi[0], vi[1], vi[2], vi[3]);
+        *reinterpret_cast<float4 *>(a.v_inh + n0 + 4) = make_float4(vi[4], vi[5], vi[6], vi[7]);
+    }
+    if (p.learn) {
+        *reinterpret_cast<float4 *>(a.x_post + n0) = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0);
+        *reinterpret_cast<float4 *>(a.x_post + n0 + 4) =
+            *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0 + 4);
+    }
+    *reinterpret_cast<uint4 *>(a.rf + n0) = make_uint4(rw[0], rw[1], rw[2], rw[3]);
+}
 
 }  // namespace snn

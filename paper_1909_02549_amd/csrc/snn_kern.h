@@ -149,6 +149,41 @@ __device__ __forceinline__ void write_outputs(const Params &p, const Outs &o, in
     if (o.v_inh && p.has_inh) o.v_inh[((size_t)k * p.B + b) * p.n_exc + j] = vi;
 }
 
+// Outputs of a group of 8 consecutive neurons j0 .. j0+7 of sample b at
+// step k; nv of them are real (the rest padding, never set in the masks).
+// se_m / si_m hold their exc / inh spikes as bits 0..7.
+__device__ __forceinline__ void write_outputs8(const Params &p, const Outs &o, int k, int b, int j0, int nv,
+                                               uint32_t se_m, uint32_t si_m, const float *ve, const float *vi)
+{
+    const int words = (p.n_exc + 31) >> 5;
+    const size_t row = (size_t)k * p.B + b;
+    if (o.counts && se_m) {
+        uint32_t *cnt = o.counts + (size_t)b * p.n_exc + j0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if ((se_m >> c) & 1u) cnt[c] += 1u;
+    }
+    const int w0 = j0 >> 5, sh = j0 & 31;
+    if (o.raster_exc && se_m) {
+        atomicOr(&o.raster_exc[row * words + w0], se_m << sh);
+        if (sh > 24 && (se_m >> (32 - sh))) atomicOr(&o.raster_exc[row * words + w0 + 1], se_m >> (32 - sh));
+    }
+    if (o.raster_inh && si_m) {
+        atomicOr(&o.raster_inh[row * words + w0], si_m << sh);
+        if (sh > 24 && (si_m >> (32 - sh))) atomicOr(&o.raster_inh[row * words + w0 + 1], si_m >> (32 - sh));
+    }
+    if (o.v_exc) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nv) o.v_exc[row * p.n_exc + j0 + c] = ve[c];
+    }
+    if (o.v_inh && p.has_inh) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nv) o.v_inh[row * p.n_exc + j0 + c] = vi[c];
+    }
+}
+
 // kernels (snn_kernels.hip)
 __global__ void k_encode(Params p, const uint8_t *img, const uint64_t *ids, const uint32_t *thr_lut,
                          const uint32_t *tl, uint64_t tbase, const uint32_t *forced, uint32_t *bits,

@@ -95,12 +95,16 @@ __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t
                            float *__restrict__ I)
 {
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)p.nblk * p.B * p.jb;
+    const size_t total = (size_t)p.nblk * p.B * p.jbp;
     if (n >= total) return;
-    const int jj = (int)(n % p.jb);
-    const size_t gb = n / p.jb;
+    const int jj = (int)(n % p.jbp);
+    const size_t gb = n / p.jbp;
     const int b = (int)(gb % p.B);
     const int g = (int)(gb / p.B);
+    if (jj >= p.jb) {
+        I[n] = 0.f;
+        return;
+    }
     const float *Wg = W + (size_t)g * p.n_in_pad * p.jb + jj;
     const uint32_t *sb = bits_t + (size_t)b * p.in_words;
     float acc = 0.f;
@@ -123,15 +127,15 @@ __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__
                          uint16_t *__restrict__ rf, float *__restrict__ x_post, int k, Outs o)
 {
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)p.nblk * p.B * p.jb;
+    const size_t total = (size_t)p.nblk * p.B * p.jbp;
     if (n >= total) return;
-    const int jj = (int)(n % p.jb);
-    const size_t gb = n / p.jb;
+    const int jj = (int)(n % p.jbp);
+    const size_t gb = n / p.jbp;
     const int b = (int)(gb % p.B);
     const int g = (int)(gb / p.B);
     const int j = g * p.jb + jj;
     if (j == 0 && Cnext) Cnext[b] = 0u;
-    if (j >= p.n_exc) return;
+    if (jj >= p.jb || j >= p.n_exc) return;
     NeuronState st{v_exc[n], p.has_inh ? v_inh[n] : 0.f, (uint32_t)rf[n], p.learn ? x_post[n] : 0.f};
     const float th_off = theta_offset(p, theta[j]);
     bool se, si;
@@ -166,12 +170,11 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
 
     for (int q = tid; q < JB * p.bwords; q += blockDim.x) spk[q] = 0u;
     __syncthreads();
-    const size_t sbase = (size_t)g * p.B * JB;
+    const size_t sbase = (size_t)g * p.B * p.jbp;
     for (int q = tid; q < p.B * JB; q += blockDim.x) {
-        if (rf[sbase + q] & RF_SPIKE) {
-            const int b = q / JB, jj = q % JB;
+        const int b = q / JB, jj = q % JB;
+        if (rf[sbase + (size_t)b * p.jbp + jj] & RF_SPIKE)
             atomicOr(&spk[jj * p.bwords + (b >> 5)], 1u << (b & 31));
-        }
     }
     __syncthreads();
 
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
                 while (m) {
                     const int b = 32 * bw + __builtin_ctz(m);
                     m &= m - 1;
-                    D = reduce2(p.reduce, D, x_post[sbase + (size_t)b * JB + jj]);
+                    D = reduce2(p.reduce, D, x_post[sbase + (size_t)b * p.jbp + jj]);
                 }
             }
             const uint32_t *sp = spk + jj * p.bwords;
@@ -236,9 +239,9 @@ __global__ void k_reset(Params p, float *__restrict__ v_exc, float *__restrict__
                         const uint8_t *__restrict__ mask)
 {
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t ns = (size_t)p.nblk * p.B * p.jb;
+    const size_t ns = (size_t)p.nblk * p.B * p.jbp;
     if (n < ns) {
-        const int b = (int)((n / p.jb) % p.B);
+        const int b = (int)((n / p.jbp) % p.B);
         if (!mask || mask[b]) {
             v_exc[n] = p.exc.v_rest;
             v_inh[n] = p.inh.v_rest;

@@ -78,6 +78,19 @@ struct snn_net {
     bool fused_ok() const;
     size_t fused_attr_bytes = 64 * 1024;
     snn_status fused_step(int kk, int k, bool has_next, const snn::Outs &o);
+
+    // persistent path: grid barrier counter / error flag, argument ring
+    static constexpr int kArgSlots = 16;
+    uint32_t *bar = nullptr, *err = nullptr;
+    void *pargs_dev = nullptr;           // kArgSlots x PersistArgs (device)
+    void *pargs_host = nullptr;          // kArgSlots x PersistArgs (pinned)
+    hipEvent_t pargs_ev[kArgSlots] = {};
+    int pargs_next = 0;
+    size_t persist_attr_bytes = 64 * 1024;
+    int coop_ok = -1;
+    bool persist_ok();
+    snn_status persist_chunk(int steps, bool has_next, int k0, const snn::Outs &o);
+    snn_status check_device_error();
     snn_status run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch, uint32_t T,
                    uint32_t flags, const snn_outputs *out);
     snn_status run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t T,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -102,7 +103,7 @@ static void fill_dims(Params &p, const snn_config &c, int jb)
 static size_t state_bytes(const Params &p, uint32_t B)
 {
     const uint32_t chunk = chunk_steps(p, B);
-    const size_t ns = (size_t)p.n_pad * B;
+    const size_t ns = (size_t)p.nblk * p.jbp * B;
     const size_t bw = (B + 31) / 32;
     size_t s = 0;
     s += (size_t)(chunk + 1) * ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2;  // lists
@@ -256,6 +257,12 @@ snn_net::~snn_net()
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (auto &e : pargs_ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipFree(bar);
+    (void)hipFree(err);
+    (void)hipFree(pargs_dev);
+    if (pargs_host) (void)hipHostFree(pargs_host);
     free_state();
     (void)hipFree(W);
     (void)hipFree(theta);
@@ -289,7 +296,12 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **
     n->stream = (hipStream_t)stream;
     HIP_TRY(hipGetDevice(&n->device));
     n->cus = device_cu_count();
-    fill_dims(n->p, *cfg, choose_jb(cfg->n_exc, n->cus));
+    int jb = choose_jb(cfg->n_exc, n->cus);
+    if (const char *e = std::getenv("SNN_JB")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 32) jb = v;
+    }
+    fill_dims(n->p, *cfg, jb);
     fill_params(n->p, *cfg);
     n->path = cfg->path;
     n->precision = cfg->precision;
@@ -301,6 +313,11 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **
     hipError_t e = hipMalloc(&n->W, nw * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&n->theta, (size_t)n->p.n_pad * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&n->thr_lut, 256 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&n->bar, 64);
+    if (e == hipSuccess) e = hipMalloc(&n->err, 64);
+    if (e == hipSuccess) e = hipMalloc(&n->pargs_dev, snn_net::kArgSlots * sizeof(PersistArgs));
+    if (e == hipSuccess) e = hipHostMalloc(&n->pargs_host, snn_net::kArgSlots * sizeof(PersistArgs), hipHostMallocDefault);
+    for (int q = 0; q < snn_net::kArgSlots && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&n->pargs_ev[q], hipEventDisableTiming);
     if (e != hipSuccess) {
         delete n;
         return fail(SNN_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -310,6 +327,7 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **
     e = hipMemcpy(n->thr_lut, lut.data(), 256 * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(n->W, 0, nw * sizeof(float));
     if (e == hipSuccess) e = hipMemset(n->theta, 0, (size_t)n->p.n_pad * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(n->err, 0, 64);
     if (e != hipSuccess) {
         delete n;
         return fail(SNN_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -413,11 +431,22 @@ extern "C" snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision
     return SNN_OK;
 }
 
+snn_status snn_net::check_device_error()
+{
+    uint32_t flag = 0;
+    HIP_TRY(hipMemcpy(&flag, err, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) {
+        HIP_TRY(hipMemset(err, 0, sizeof flag));
+        return fail(SNN_EDEVICE, "persistent kernel: grid barrier wait timed out (launch ended early)");
+    }
+    return SNN_OK;
+}
+
 extern "C" snn_status snn_sync(snn_net *net)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
     HIP_TRY(hipStreamSynchronize(net->stream));
-    return SNN_OK;
+    return net->check_device_error();
 }
 
 extern "C" size_t snn_state_bytes(const snn_config *cfg, uint32_t batch)
@@ -440,7 +469,7 @@ snn_status snn_net::ensure_state(uint32_t B)
     if (B > cap_B) {
         HIP_TRY(hipStreamSynchronize(stream));
         free_state();
-        const size_t ns = (size_t)p.n_pad * B;
+        const size_t ns = (size_t)p.nblk * p.jbp * B;
         const size_t bw = (B + 31) / 32;
         hipError_t e = hipSuccess;
         auto A = [&](void **ptr, size_t bytes) {
@@ -488,7 +517,7 @@ void snn_net::set_batch(uint32_t B)
 
 snn_status snn_net::reset_state(const uint8_t *mask_dev)
 {
-    const size_t ns = (size_t)p.n_pad * p.B;
+    const size_t ns = (size_t)p.nblk * p.jbp * p.B;
     const size_t n = std::max(ns, (size_t)p.B * p.n_in_pad);
     const int tpb = 256;
     SNN_LAUNCH("reset", k_reset, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, p, v_exc, v_inh, rf, x_post,
@@ -536,7 +565,7 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o)
     uint32_t *Ccur = C + (size_t)(gstep % 3) * p.B;
     uint32_t *Cprev = C + (size_t)((gstep + 2) % 3) * p.B;
     uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.B;
-    const size_t ns = (size_t)p.n_pad * p.B;
+    const size_t ns = (size_t)p.nblk * p.jbp * p.B;
     const int tpb = 256;
     if (p.learn)
         SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, p, bits_t, xprev,
@@ -620,7 +649,6 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     const int cur = (int)(gstep & 1);
     StepPtrs s;
     s.bits = bits + (size_t)kk * p.bits_stride;
-    s.bitsT = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
     s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.bits_stride : nullptr;
     s.lin = lin + (size_t)kk * p.B * p.n_in_pad;
     s.cin = cin + (size_t)kk * p.B;
@@ -644,9 +672,65 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     return SNN_OK;
 }
 
+bool snn_net::persist_ok()
+{
+    if (coop_ok < 0) {
+        int v = 0;
+        coop_ok = (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess && v) ? 1 : 0;
+    }
+    return coop_ok == 1 && p.jb <= 32 && p.B * (p.jbp / 8) <= kFusedThreads && p.nblk <= cus &&
+           p.n_in_pad < 65535 && p.B < 65535 && persist_lds_bytes(p) + 64 <= kMaxLds;
+}
+
+snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &o)
+{
+    const int slot = pargs_next;
+    pargs_next = (pargs_next + 1) % kArgSlots;
+    HIP_TRY(hipEventSynchronize(pargs_ev[slot]));
+    PersistArgs *h = reinterpret_cast<PersistArgs *>(pargs_host) + slot;
+    PersistArgs *d = reinterpret_cast<PersistArgs *>(pargs_dev) + slot;
+    h->p = p;
+    h->a = FusedArgs{W, theta, v_exc, v_inh, x_post, rf, o};
+    ChunkPtrs &c = h->ch;
+    c.bits = bits;
+    c.lin = lin;
+    c.cin = cin;
+    c.lt = lt;
+    c.ct = ct;
+    c.xpre = x_pre;
+    c.C = C;
+    c.steps = steps;
+    c.has_next = has_next ? 1 : 0;
+    c.par0 = (int)(gstep & 1);
+    c.mod0 = (int)(gstep % 3);
+    c.k0 = k0;
+    h->sy = PersistSync{bar, err};
+    HIP_TRY(hipMemcpyAsync(d, h, sizeof(PersistArgs), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(pargs_ev[slot], stream));
+    SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
+    const size_t lds = persist_lds_bytes(p);
+    if (lds > persist_attr_bytes) {
+        HIP_TRY(hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        persist_attr_bytes = lds;
+    }
+    void *kargs[] = {(void *)&d};
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    int kid = -1;
+    if (prof) {
+        kid = kstat_id("persistent");
+        ev = prof_begin();
+    }
+    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_persist, dim3((unsigned)p.nblk), dim3(kFusedThreads), kargs,
+                                       (unsigned)lds, stream));
+    if (prof) prof_end(kid, ev);
+    gstep += (uint64_t)steps;
+    return SNN_OK;
+}
+
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o)
 {
+    if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
     for (uint32_t k0 = 0; k0 < T; k0 += chunk) {
         const int steps = (int)std::min<uint32_t>(chunk, T - k0);
@@ -655,7 +739,7 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
         const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
         snn_status st = encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
         if (st != SNN_OK) return st;
-        if (path == SNN_PATH_FUSED) {
+        if (path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT) {
             const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
             SNN_LAUNCH("lists", k_lists, dim3((unsigned)((nq + 255) / 256), (unsigned)enc_steps), dim3(256), 0, p,
                        (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, p.learn);
@@ -664,10 +748,15 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
                 st = xpre_first(bits);
                 if (st != SNN_OK) return st;
             }
-            for (int kk = 0; kk < steps; ++kk) {
-                const bool has_next = (kk + 1 < enc_steps);
-                st = fused_step(kk, (int)k0 + kk, has_next, o);
+            if (path == SNN_PATH_PERSISTENT) {
+                st = persist_chunk(steps, more, (int)k0, o);
                 if (st != SNN_OK) return st;
+            } else {
+                for (int kk = 0; kk < steps; ++kk) {
+                    const bool has_next = (kk + 1 < enc_steps);
+                    st = fused_step(kk, (int)k0 + kk, has_next, o);
+                    if (st != SNN_OK) return st;
+                }
             }
         } else {
             for (int kk = 0; kk < steps; ++kk) {

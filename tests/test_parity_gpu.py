@@ -102,7 +102,7 @@ def check_parity(g, ref, learn=True):
     return t_div
 
 
-PATHS = ["plain", "fused"]
+PATHS = ["plain", "fused", "persistent"]
 
 
 @pytest.mark.parametrize("path", PATHS)
