@@ -5,7 +5,7 @@
 //   g = j / JB, jj = j % JB; every per-neuron array and the weight matrix are
 //   block-major, so one column block (the unit a fused or plasticity
 //   workgroup owns) is one contiguous span:
-//     state(b, j)  at (g * B + b) * JBP + jj       (v_exc, v_inh, x_post, rf)
+//     state(b, j)  at (g * Bs + b) * JBP + jj      (v_exc, v_inh, x_post, rf)
 //                  (JBP = JB rounded up to 8: 32-byte aligned 8-neuron groups)
 //     W(i, j)      at (g * n_in_pad + i) * JB + jj (FP32 master)
 //   inputs are padded to n_in_pad = 32 * in_words; pad inputs never spike
@@ -13,8 +13,8 @@
 //   input spikes of step t: bits[t * bits_stride + b * in_words + w] (bit
 //   i % 32 of word i / 32) and the transpose bitsT[t][i][bw] (bit b % 32 of
 //   word b / 32).
-//   presynaptic traces x_pre[t & 1][b][i]; inhibitory spike counts per sample
-//   C[t % 3][b].
+//   presynaptic traces x_pre[t & 1][b][i] (buffer stride Bs rows);
+//   inhibitory spike counts per sample C[t % 3][b] (slot stride Bs).
 #pragma once
 #include <stdint.h>
 
@@ -32,6 +32,8 @@ struct Params {
     int lt_stride;            // entries per per-input sample list (B rounded to 8)
     int has_inh;
     int B, bwords;            // batch, ceil(B / 32)
+    int Bs;                   // sample stride of the per-neuron state arrays
+                              // (allocated capacity; B <= Bs may vary)
     int bits_stride;          // words per step of the per-sample input spikes
                               // (B * in_words rounded up to 4: 16-byte rows)
     int learn, adaptive, trace_add, reduce;

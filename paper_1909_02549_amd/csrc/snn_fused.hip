@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     __syncthreads();
 
     // B: one (sample, 8 columns) task at a time, state through registers
-    const size_t sbase = (size_t)g * p.B * JBP;
+    const size_t sbase = (size_t)g * p.Bs * JBP;
     const int nv_blk = min(JB, p.n_exc - g * JB);
     for (int q = tid; q < p.B * ncg; q += nt) {
         const int b = q / ncg;

@@ -197,5 +197,7 @@ __global__ void k_plastic(Params p, float *W, double *theta, const uint16_t *rf,
 __global__ void k_reset(Params p, float *v_exc, float *v_inh, uint16_t *rf, float *x_post, float *x_pre,
                         uint32_t *C, const uint8_t *mask);
 __global__ void k_fill_u32(uint32_t *dst, uint32_t value, size_t n);
+__global__ void k_slot_init(const uint8_t *mask, uint32_t *tl, uint32_t *counts, int n_exc, int B);
+__global__ void k_add_u32(uint32_t *v, uint32_t add, int n);
 
 }  // namespace snn

@@ -94,15 +94,16 @@ __global__ void k_xpre(Params p, const uint32_t *__restrict__ bits_t, const floa
 __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t *__restrict__ bits_t,
                            float *__restrict__ I)
 {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t tix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)p.nblk * p.B * p.jbp;
-    if (n >= total) return;
-    const int jj = (int)(n % p.jbp);
-    const size_t gb = n / p.jbp;
+    if (tix >= total) return;
+    const int jj = (int)(tix % p.jbp);
+    const size_t gb = tix / p.jbp;
     const int b = (int)(gb % p.B);
     const int g = (int)(gb / p.B);
+    const size_t ns = ((size_t)g * p.Bs + b) * p.jbp + jj;
     if (jj >= p.jb) {
-        I[n] = 0.f;
+        I[ns] = 0.f;
         return;
     }
     const float *Wg = W + (size_t)g * p.n_in_pad * p.jb + jj;
@@ -116,7 +117,7 @@ __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t
             acc += Wg[(size_t)i * p.jb];
         }
     }
-    I[n] = acc;
+    I[ns] = acc;
 }
 
 // Plain neuron update, one thread per (b, j): recurrent currents, both
@@ -126,16 +127,17 @@ __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__
                          uint32_t *__restrict__ Cnext, float *__restrict__ v_exc, float *__restrict__ v_inh,
                          uint16_t *__restrict__ rf, float *__restrict__ x_post, int k, Outs o)
 {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t tix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)p.nblk * p.B * p.jbp;
-    if (n >= total) return;
-    const int jj = (int)(n % p.jbp);
-    const size_t gb = n / p.jbp;
+    if (tix >= total) return;
+    const int jj = (int)(tix % p.jbp);
+    const size_t gb = tix / p.jbp;
     const int b = (int)(gb % p.B);
     const int g = (int)(gb / p.B);
     const int j = g * p.jb + jj;
     if (j == 0 && Cnext) Cnext[b] = 0u;
     if (jj >= p.jb || j >= p.n_exc) return;
+    const size_t n = ((size_t)g * p.Bs + b) * p.jbp + jj;
     NeuronState st{v_exc[n], p.has_inh ? v_inh[n] : 0.f, (uint32_t)rf[n], p.learn ? x_post[n] : 0.f};
     const float th_off = theta_offset(p, theta[j]);
     bool se, si;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
 
     for (int q = tid; q < JB * p.bwords; q += blockDim.x) spk[q] = 0u;
     __syncthreads();
-    const size_t sbase = (size_t)g * p.B * p.jbp;
+    const size_t sbase = (size_t)g * p.Bs * p.jbp;
     for (int q = tid; q < p.B * JB; q += blockDim.x) {
         const int b = q / JB, jj = q % JB;
         if (rf[sbase + (size_t)b * p.jbp + jj] & RF_SPIKE)
@@ -233,16 +235,21 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
     }
 }
 
-// Episodic reset of per-sample state (all samples, or those with mask[b]).
+// Episodic reset of per-sample state (all samples b < B, or those with
+// mask[b] set).
 __global__ void k_reset(Params p, float *__restrict__ v_exc, float *__restrict__ v_inh, uint16_t *__restrict__ rf,
                         float *__restrict__ x_post, float *__restrict__ x_pre, uint32_t *__restrict__ C,
                         const uint8_t *__restrict__ mask)
 {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t ns = (size_t)p.nblk * p.B * p.jbp;
-    if (n < ns) {
-        const int b = (int)((n / p.jbp) % p.B);
+    if (t < ns) {
+        const int jj = (int)(t % p.jbp);
+        const size_t gb = t / p.jbp;
+        const int b = (int)(gb % p.B);
+        const int g = (int)(gb / p.B);
         if (!mask || mask[b]) {
+            const size_t n = ((size_t)g * p.Bs + b) * p.jbp + jj;
             v_exc[n] = p.exc.v_rest;
             v_inh[n] = p.inh.v_rest;
             rf[n] = 0;
@@ -250,20 +257,37 @@ __global__ void k_reset(Params p, float *__restrict__ v_exc, float *__restrict__
         }
     }
     const size_t nx = (size_t)p.B * p.n_in_pad;
-    if (n < nx) {
-        const int b = (int)(n / p.n_in_pad);
+    if (t < nx) {
+        const int b = (int)(t / p.n_in_pad);
         if (!mask || mask[b]) {
-            x_pre[n] = 0.f;
-            x_pre[nx + n] = 0.f;
+            x_pre[t] = 0.f;
+            x_pre[(size_t)p.Bs * p.n_in_pad + t] = 0.f;
         }
     }
-    if (n < (size_t)p.B) {
-        if (!mask || mask[n]) {
-            C[n] = 0u;
-            C[p.B + n] = 0u;
-            C[2 * p.B + n] = 0u;
+    if (t < (size_t)p.B) {
+        if (!mask || mask[t]) {
+            C[t] = 0u;
+            C[p.Bs + t] = 0u;
+            C[2 * p.Bs + t] = 0u;
         }
     }
+}
+
+// Serving: new slots (mask[b] set) start at local step 0 with zero counts.
+__global__ void k_slot_init(const uint8_t *__restrict__ mask, uint32_t *__restrict__ tl, uint32_t *__restrict__ counts,
+                            int n_exc, int B)
+{
+    const int b = blockIdx.x;
+    if (b >= B || !mask[b]) return;
+    if (threadIdx.x == 0) tl[b] = 0u;
+    for (int j = threadIdx.x; j < n_exc; j += blockDim.x) counts[(size_t)b * n_exc + j] = 0u;
+}
+
+// Serving: every slot's local step advances by the steps just run.
+__global__ void k_add_u32(uint32_t *__restrict__ v, uint32_t add, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) v[q] += add;
 }
 
 __global__ void k_fill_u32(uint32_t *__restrict__ dst, uint32_t value, size_t n)

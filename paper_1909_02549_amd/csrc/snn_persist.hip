@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__
     const bool has_task = tid < p.B * ncg;
     const int b = has_task ? tid / ncg : 0;
     const int c0 = 8 * (tid - b * ncg);
-    const size_t n0 = (size_t)g * p.B * JBP + (size_t)b * JBP + c0;
+    const size_t n0 = (size_t)g * p.Bs * JBP + (size_t)b * JBP + c0;
     const int nv = max(0, min(8, min(JB, p.n_exc - g * JB) - c0));
     float ve[8], vi[8];
     uint32_t rw[4];
@@ -87,10 +87,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__
     for (int k = 0; k < ch.steps; ++k) {
         const int par = (ch.par0 + k) & 1;
         const int mod = (ch.mod0 + k) % 3;
-        const float *xpre = ch.xpre + (size_t)par * p.B * p.n_in_pad;
-        float *xpre_nx = ch.xpre + (size_t)(par ^ 1) * p.B * p.n_in_pad;
+        const float *xpre = ch.xpre + (size_t)par * p.Bs * p.n_in_pad;
+        float *xpre_nx = ch.xpre + (size_t)(par ^ 1) * p.Bs * p.n_in_pad;
 
-        step_begin<true>(p, S, ch.C + (size_t)((mod + 2) % 3) * p.B, tid, nt);
+        step_begin<true>(p, S, ch.C + (size_t)((mod + 2) % 3) * p.Bs, tid, nt);
         __syncthreads();
         if (has_task) {
             float acc[8];
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__
             neuron_task(p, S, a.o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, ve, vi, rw);
         }
         __syncthreads();
-        step_publish<true>(p, S, ch.C + (size_t)mod * p.B, ch.C + (size_t)((mod + 1) % 3) * p.B, g, tid, nt);
+        step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
         if (p.learn) {
             __syncthreads();
             plasticity_all<true>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride, ch.ct + (size_t)k * p.n_in_pad, xpre,

@@ -63,6 +63,8 @@ struct snn_net {
 
     uint64_t gstep = 0;  // steps since the state was initialised
     uint64_t tloc = 0;   // local step of the current samples (encoder counter)
+    // the C ABI's error helper for other translation units
+    static snn_status error(snn_status st, const char *msg);
 
     ~snn_net();
     void free_state();
@@ -94,6 +96,11 @@ struct snn_net {
     snn_status run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch, uint32_t T,
                    uint32_t flags, const snn_outputs *out);
     snn_status run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t T,
-                         const snn::Outs &o);
+                         const snn::Outs &o, const uint32_t *tl = nullptr);
+    // serving: `steps` more steps of the first B slots, encoder keyed by the
+    // per-slot local steps tl, exc spike counts added into counts
+    snn_status serve_steps(const uint8_t *images, const uint64_t *ids, const uint32_t *tl, uint32_t B, uint32_t steps,
+                           uint32_t *counts, const uint8_t *new_mask);
+    friend struct snn_server;
     int choose_path(uint32_t batch, uint32_t T);
 };

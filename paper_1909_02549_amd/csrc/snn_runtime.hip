@@ -509,6 +509,7 @@ void snn_net::set_batch(uint32_t B)
     p.bwords = (int)((B + 31) / 32);
     p.inv_B = 1.f / (float)B;
     p.inv_Bd = 1.0 / (double)B;
+    p.Bs = (int)cap_B;
     p.bits_stride = (int)((((size_t)B * p.in_words) + 3) & ~(size_t)3);
     p.lt_stride = (int)((B + 7) & ~7u);
     // never more steps than the buffers were sized for at capacity
@@ -518,7 +519,7 @@ void snn_net::set_batch(uint32_t B)
 snn_status snn_net::reset_state(const uint8_t *mask_dev)
 {
     const size_t ns = (size_t)p.nblk * p.jbp * p.B;
-    const size_t n = std::max(ns, (size_t)p.B * p.n_in_pad);
+    const size_t n = std::max(ns, (size_t)p.B * p.n_in_pad);  // k_reset covers b < B
     const int tpb = 256;
     SNN_LAUNCH("reset", k_reset, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, p, v_exc, v_inh, rf, x_post,
                x_pre, C, mask_dev);
@@ -560,11 +561,11 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o)
     const uint32_t *bits_t = bits + (size_t)kk * p.bits_stride;
     const uint32_t *bitsT_t = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
     const int cur = (int)(gstep & 1);
-    float *xcur = x_pre + (size_t)cur * p.B * p.n_in_pad;
-    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
-    uint32_t *Ccur = C + (size_t)(gstep % 3) * p.B;
-    uint32_t *Cprev = C + (size_t)((gstep + 2) % 3) * p.B;
-    uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.B;
+    float *xcur = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
+    uint32_t *Ccur = C + (size_t)(gstep % 3) * p.Bs;
+    uint32_t *Cprev = C + (size_t)((gstep + 2) % 3) * p.Bs;
+    uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
     const size_t ns = (size_t)p.nblk * p.jbp * p.B;
     const int tpb = 256;
     if (p.learn)
@@ -632,8 +633,8 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
 snn_status snn_net::xpre_first(const uint32_t *bits_t)
 {
     const int cur = (int)(gstep & 1);
-    float *xcur = x_pre + (size_t)cur * p.B * p.n_in_pad;
-    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
+    float *xcur = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
     SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, 256)), dim3(256), 0, p, bits_t, xprev, xcur);
     HIP_TRY(hipGetLastError());
     return SNN_OK;
@@ -654,11 +655,11 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.cin = cin + (size_t)kk * p.B;
     s.lt = lt + (size_t)kk * p.n_in_pad * p.lt_stride;
     s.ct = ct + (size_t)kk * p.n_in_pad;
-    s.xpre = x_pre + (size_t)cur * p.B * p.n_in_pad;
-    s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.B * p.n_in_pad;
-    s.Ccur = C + (size_t)(gstep % 3) * p.B;
-    s.Cprev = C + (size_t)((gstep + 2) % 3) * p.B;
-    s.Cnext = C + (size_t)((gstep + 1) % 3) * p.B;
+    s.xpre = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
+    s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
+    s.Ccur = C + (size_t)(gstep % 3) * p.Bs;
+    s.Cprev = C + (size_t)((gstep + 2) % 3) * p.Bs;
+    s.Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
     s.k = k;
     FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
     const size_t lds = fused_lds_bytes(p);
@@ -727,8 +728,33 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     return SNN_OK;
 }
 
+snn_status snn_net::error(snn_status st, const char *msg) { return fail(st, msg); }
+
+snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, const uint32_t *tl_dev, uint32_t B,
+                                uint32_t steps, uint32_t *counts, const uint8_t *new_mask)
+{
+    if (B == 0 || B > cap_B || steps == 0) return fail(SNN_EINVAL, "serve_steps: bad batch or steps");
+    set_batch(B);
+    cur_B = B;
+    if (new_mask) {
+        snn_status st = reset_state(new_mask);
+        if (st != SNN_OK) return st;
+        SNN_LAUNCH("slot_init", k_slot_init, dim3(B), dim3(256), 0, new_mask, const_cast<uint32_t *>(tl_dev), counts,
+                   p.n_exc, (int)B);
+    }
+    Outs o{};
+    o.counts = counts;
+    int path = this->path == SNN_PATH_AUTO ? choose_path(B, steps) : this->path;
+    snn_status st = run_steps(path, images, ids, nullptr, steps, o, tl_dev);
+    if (st != SNN_OK) return st;
+    SNN_LAUNCH("slot_step", k_add_u32, dim3((B + 255) / 256), dim3(256), 0, const_cast<uint32_t *>(tl_dev), steps,
+               (int)B);
+    HIP_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
-                              uint32_t T, const Outs &o)
+                              uint32_t T, const Outs &o, const uint32_t *tl)
 {
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
@@ -737,7 +763,8 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
         const bool more = k0 + (uint32_t)steps < T;
         const int enc_steps = steps + (more ? 1 : 0);
         const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
-        snn_status st = encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
+        snn_status st = tl ? encode_chunk(images, ids, tl, k0, enc_steps, fc, o.raster_in, (int)k0)
+                           : encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
         if (st != SNN_OK) return st;
         if (path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT) {
             const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
@@ -769,7 +796,14 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
     return SNN_OK;
 }
 
-int snn_net::choose_path(uint32_t, uint32_t) { return SNN_PATH_PLAIN; }
+// Without a measured table the persistent path is preferred where its
+// cooperative launch fits, then the fused per-step path.
+int snn_net::choose_path(uint32_t, uint32_t)
+{
+    if (persist_ok()) return SNN_PATH_PERSISTENT;
+    if (fused_ok()) return SNN_PATH_FUSED;
+    return SNN_PATH_PLAIN;
+}
 
 extern "C" snn_status snn_run(snn_net *net, const uint8_t *images_dev, const uint64_t *ids_dev, uint32_t batch,
                               uint32_t T, uint32_t flags, const snn_outputs *out)

@@ -269,6 +269,50 @@ class Net:
         return out
 
 
+class Server:
+    """Continuous-batching server over a frozen Net (snn_serve_* calls)."""
+
+    def __init__(self, net: Net, max_slots: int, hbm_budget: int = 0, chunk_steps: int = 25):
+        self.lib = net.lib
+        self.net = net
+        self.n_exc = net.n_exc
+        h = C.c_void_p()
+        _check(self.lib.snn_serve_create(net.h, int(max_slots), int(hbm_budget), int(chunk_steps), C.byref(h)))
+        self.h = h
+
+    def snn_serve_submit(self, image: np.ndarray, sample_id: int, T: int) -> int:
+        img = np.ascontiguousarray(image, dtype=np.uint8)
+        rid = C.c_uint64()
+        _check(self.lib.snn_serve_submit(self.h, img.ctypes.data, int(sample_id), int(T), C.byref(rid)))
+        return int(rid.value)
+
+    def snn_serve_poll(self, req_id: int):
+        """(counts, latency_s) when finished, None while queued or running."""
+        counts = np.zeros(self.n_exc, np.uint32)
+        lat = C.c_double()
+        st = self.lib.snn_serve_poll(self.h, int(req_id), counts.ctypes.data, C.byref(lat))
+        if st == -4:
+            return None
+        _check(st)
+        return counts, float(lat.value)
+
+    def snn_serve_stats(self) -> dict:
+        c, s, pk, bs = C.c_uint64(), C.c_uint64(), C.c_uint32(), C.c_double()
+        _check(self.lib.snn_serve_stats(self.h, C.byref(c), C.byref(s), C.byref(pk), C.byref(bs)))
+        return {"completed": c.value, "slot_steps": s.value, "peak_active": pk.value, "busy_s": bs.value}
+
+    def snn_serve_destroy(self):
+        if getattr(self, "h", None):
+            h, self.h = self.h, None
+            _check(self.lib.snn_serve_destroy(h))
+
+    def __del__(self):
+        try:
+            self.snn_serve_destroy()
+        except Exception:
+            pass
+
+
 def unpack_bits(words, n: int) -> np.ndarray:
     """(..., n_words) int32/uint32 bit rasters -> (..., n) uint8 0/1."""
     w = np.ascontiguousarray(np.asarray(words)).astype(np.uint32)

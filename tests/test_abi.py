@@ -1,0 +1,93 @@
+"""CPU tests of the C-ABI library: it loads without a GPU, exports every
+symbol include/snn.h declares, and rejects invalid configurations before
+touching the device.  No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "snn.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(snn_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1909_02549_amd import snn
+    if not os.path.exists(snn.LIB_PATH):
+        pytest.skip("libsnn.so not built")
+    return snn.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    from paper_1909_02549_amd import snn
+    assert sorted(snn.EXPORTED) == declared_symbols()
+
+
+def test_abi_version(lib):
+    assert lib.snn_abi_version() == 1
+
+
+def _cfg(**over):
+    from paper_1909_02549_amd import inputs, snn
+    cfg = inputs.dc_config(100)
+    c = snn.make_config(cfg, max_batch=4)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("field,value", [("abi_version", 7), ("n_in", 0), ("n_exc", 0), ("n_inh", 5),
+                                         ("reduce", 9), ("precision", 5), ("path", 8), ("max_batch", 0),
+                                         ("dt_ms", 0.0), ("w_min", 2.0)])
+def test_invalid_config_rejected_without_gpu(lib, field, value):
+    c = _cfg(**{field: value})
+    h = C.c_void_p()
+    st = lib.snn_create(C.byref(c), None, C.byref(h))
+    assert st == -1 and not h.value
+    assert lib.snn_last_error().decode()
+
+
+def test_refractory_bound_rejected(lib):
+    c = _cfg()
+    c.exc.refrac_steps = 200
+    h = C.c_void_p()
+    assert lib.snn_create(C.byref(c), None, C.byref(h)) == -1
+
+
+def test_null_handle_calls(lib):
+    assert lib.snn_run(None, None, None, 1, 1, 0, None) == -1
+    assert lib.snn_sync(None) == -1
+    assert lib.snn_stdp_reduce(None, 0) == -1
+    assert lib.snn_serve_poll(None, 1, None, None) == -1
+
+
+def test_state_bytes_grow_with_batch(lib):
+    c = _cfg()
+    b1 = lib.snn_state_bytes(C.byref(c), 1)
+    b64 = lib.snn_state_bytes(C.byref(c), 64)
+    assert 0 < b1 < b64
+
+
+def test_bit_packing_roundtrip():
+    from paper_1909_02549_amd.snn import pack_bits, unpack_bits
+    rng = np.random.default_rng(0)
+    for n in (1, 31, 32, 33, 784, 1000):
+        x = (rng.random((3, 5, n)) < 0.3).astype(np.uint8)
+        w = pack_bits(x)
+        assert w.shape == (3, 5, (n + 31) // 32)
+        assert np.array_equal(unpack_bits(w, n), x)
+    assert pack_bits(np.array([1, 0, 0, 0, 0, 1] + [0] * 26, np.uint8))[0] == (1 | 1 << 5)

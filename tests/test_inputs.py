@@ -1,0 +1,33 @@
+"""CPU tests of the seeded synthetic inputs (shared by oracle and HIP runs)."""
+import numpy as np
+
+from paper_1909_02549_amd import inputs
+
+
+def test_stroke_images_shape_density_determinism():
+    a = inputs.stroke_images(8, 5, 0.19)
+    b = inputs.stroke_images(8, 5, 0.19)
+    assert a.shape == (8, 784) and a.dtype == np.uint8
+    assert np.array_equal(a, b)
+    assert np.allclose((a > 0).mean(axis=1), 0.19, atol=0.002)
+    assert a.max() == 255
+    c = inputs.stroke_images(8, 5, (0.1, 0.3))
+    d = (c > 0).mean(axis=1)
+    assert d.min() >= 0.099 and d.max() <= 0.301
+
+
+def test_image_depends_only_on_seed_and_index():
+    a = inputs.stroke_images(4, 9, 0.2, start=10)
+    b = np.stack([inputs.stroke_image(9, 10 + k, 0.2) for k in range(4)])
+    assert np.array_equal(a, b)
+
+
+def test_weights_and_arrivals():
+    w = inputs.uniform_weights(784, 10, 0.0, 0.3, 0)
+    assert w.dtype == np.float32 and 0 <= w.min() and w.max() < 0.3
+    s = inputs.column_scaled(w, 78.4)
+    assert np.allclose(s.astype(np.float64).sum(0), 78.4, rtol=1e-5)
+    t = inputs.poisson_arrivals(20000, 5000.0)
+    assert abs(np.diff(t).mean() - 1 / 5000.0) < 1e-5
+    T = inputs.request_durations(3000)
+    assert set(np.unique(T)) == {100, 250, 500}
