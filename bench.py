@@ -5,19 +5,25 @@ One bench step is one episodic trial of the whole hot path: ``snn_run`` of
 B = 256 samples for T = 350 clock steps of the 784 -> 6400/6400 Diehl & Cook
 style network with STDP on (Poisson encoding, contraction, inhibition, neuron
 updates, traces, batch-reduced weight change, clamp, column normalisation,
-threshold update).  Inputs (images, ids, weights) are resident in HBM before
-the timed region.  value = B * T * steps / elapsed seconds (sample-steps/s).
+threshold update), on the execution path the library's autotuner picks.
+Inputs (images, ids, weights) are resident in HBM before the timed region.
+value = B * T * steps / elapsed seconds (sample-steps/s).
 
 Also reported on the same JSON line:
-  plain_path    the same workload on the plain per-step launch path;
-  roofline      the dominant kernel's algorithmic bytes per launch divided by
-                its average launch time, measured with HIP events recorded on
-                the library's stream during the timed region;
+  paths         the same workload on each execution path (plain per-step
+                launches, fused per-step kernel, persistent kernel);
+  roofline      the dominant kernel's algorithmic HBM bytes per launch divided
+                by its average launch time, measured with HIP events recorded
+                on the library's stream during the timed region;
+  serving       frozen 784 -> 1600 network, Poisson arrivals, T in
+                {100, 250, 500}: p50 / p99 latency and sample-steps/s;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -33,53 +39,72 @@ METRIC = "sample·steps/s (784→6400 D&C, B=256) vs plain path; serving p50/p99
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1909_02549_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def dims(cfg, B):
     n_in = cfg["n_in"]
     n_in_pad = 32 * ((n_in + 31) // 32)
-    return dict(n_in=n_in, n_in_pad=n_in_pad, n_exc=cfg["n_exc"], B=B,
-                in_words=n_in_pad // 32, bwords=(B + 31) // 32, learn=cfg["learn"], has_inh=cfg["n_inh"] > 0)
+    return dict(n_in=n_in, n_in_pad=n_in_pad, n_exc=cfg["n_exc"], B=B, in_words=n_in_pad // 32,
+                bwords=(B + 31) // 32, learn=cfg["learn"], has_inh=cfg["n_inh"] > 0)
 
 
-def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: int = 1) -> float | None:
-    """HBM bytes one launch of `kernel` must move at minimum (read + write),
-    per the per-unit figures in the design notes.  None if not modelled."""
+def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: float = 1.0):
+    """HBM bytes one launch of `kernel` has to move (read + write), from the
+    per-unit figures of the design notes.  None if not modelled."""
     n_in, n_in_pad, N, B = d["n_in"], d["n_in_pad"], d["n_exc"], d["B"]
-    w = n_in * N * 4                     # FP32 weights, one pass
-    st_exc = 4 + 2 + (4 if d["learn"] else 0)     # v_exc, packed rf/flags, x_post
-    st_inh = 4 if d["has_inh"] else 0             # v_inh
-    state = B * N * (st_exc + st_inh)             # one pass over per-neuron state
-    bits = B * d["in_words"] * 4 + n_in_pad * d["bwords"] * 4
-    xpre = B * n_in_pad * 4
-    if kernel == "plastic":
-        return 2 * w + B * N * (4 + 2) + bits
-    if kernel == "neuron":
-        return 2 * state + B * N * 4
-    if kernel == "contract":
-        return B * N * 4 + bits
-    if kernel == "xpre":
-        return 2 * xpre
+    w = n_in * N * 4                                   # FP32 weights, one pass
+    st = B * N * (4 + 2 + (4 if d["learn"] else 0) + (4 if d["has_inh"] else 0))  # per-neuron state, one pass
+    spikes = B * d["in_words"] * 4 + n_in_pad * d["bwords"] * 4  # one step's input spikes, both layouts
+    xpre = B * n_in_pad * 4 if d["learn"] else 0        # presynaptic traces of one step
     if kernel == "fused_step":
-        return 2 * w + 2 * state + (2 * xpre if d["learn"] else 0) + 2 * bits
+        return 2 * w * (1 if d["learn"] else 0.5) + 2 * st + 2 * xpre + spikes
+    if kernel == "persistent":
+        return (2 * w if d["learn"] else w) + 2 * st + steps_per_launch * (2 * xpre + spikes)
+    if kernel == "plastic":
+        return 2 * w + B * N * (4 + 2) + spikes
+    if kernel == "neuron":
+        return 2 * st + B * N * 4
+    if kernel == "contract":
+        return B * N * 4 + spikes
+    if kernel == "xpre":
+        return 2 * xpre + spikes
     if kernel == "encode":
-        return steps_per_launch * 2 * bits + B * n_in
+        return steps_per_launch * 2 * spikes + B * n_in
     return None
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0) -> dict:
     """Time the FP64 oracle (test infrastructure) on the first steps of one
     trial of the same workload."""
-    from oracle.oracle import OracleNet
     from oracle import build as obuild
     from oracle import oracle as omod
     if not os.path.exists(omod.LIB_PATH):
         obuild.build()
     cfg, B = wl["cfg"], wl["B"]
-    net = OracleNet(cfg, W.astype(np.float64))
+    net = omod.OracleNet(cfg, W.astype(np.float64))
     t0 = time.perf_counter()
-    net.run(imgs, ids, 1, record=())
-    t1 = time.perf_counter() - t0
+    net.run(imgs, ids, 2, record=())
+    t1 = (time.perf_counter() - t0) / 2
     steps = int(max(2, min(wl["T"], target_s / max(t1, 1e-3))))
-    net = OracleNet(cfg, W.astype(np.float64))
+    net = omod.OracleNet(cfg, W.astype(np.float64))
     t0 = time.perf_counter()
     net.run(imgs, ids, steps, record=())
     el = time.perf_counter() - t0
@@ -101,10 +126,56 @@ def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
         net.snn_run(imgs_d, ids_d, T, reset=True, record=())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    net.snn_sync()
     prof = net.snn_profile_get() if profile else {}
     if profile:
         net.snn_profile_enable(False)
     return el, prof
+
+
+def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
+    """Frozen 784 -> 1600/1600 network; requests arrive as a Poisson process
+    with T drawn from {100, 250, 500}; continuous batching on the device."""
+    from paper_1909_02549_amd import inputs
+    from paper_1909_02549_amd.snn import Net, Server
+    wl = inputs.workload("serve")
+    cfg = wl["cfg"]
+    W = inputs.column_scaled(inputs.uniform_weights(cfg["n_in"], cfg["n_exc"], wl["wlo"], wl["whi"], 0), 78.4)
+    net = Net(cfg, max_batch=1, path="auto")
+    net.snn_set_weights(W)
+    arrivals = inputs.poisson_arrivals(n_req, rate_hz, seed=1)
+    Ts = inputs.request_durations(n_req, seed=1)
+    imgs = inputs.stroke_images(n_req, 4242, wl["density"])
+    srv = Server(net, max_slots=max_slots, chunk_steps=chunk)
+    # warm the server (autotune, first launches)
+    w = srv.snn_serve_submit(imgs[0], 10 ** 9, 100)
+    while srv.snn_serve_poll(w) is None:
+        time.sleep(0.001)
+    rids = []
+    t0 = time.perf_counter()
+    for k in range(n_req):
+        while time.perf_counter() - t0 < arrivals[k]:
+            pass
+        rids.append(srv.snn_serve_submit(imgs[k], k, int(Ts[k])))
+    lat = {}
+    while len(lat) < n_req:
+        for r in rids:
+            if r in lat:
+                continue
+            res = srv.snn_serve_poll(r)
+            if res is not None:
+                lat[r] = res[1]
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    st = srv.snn_serve_stats()
+    srv.snn_serve_destroy()
+    net.close()
+    lv = np.array(list(lat.values()))
+    return {"workload": "784->1600/1600 frozen, T in {100,250,500}, Poisson arrivals",
+            "rate_req_s": rate_hz, "requests": n_req, "max_slots": max_slots, "chunk_steps": chunk,
+            "p50_ms": float(np.percentile(lv, 50) * 1e3), "p99_ms": float(np.percentile(lv, 99) * 1e3),
+            "value": float(Ts.astype(np.float64).sum() / wall), "unit": "sample·steps/s",
+            "peak_active": st["peak_active"]}
 
 
 def main():
@@ -113,16 +184,19 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed trials (one trial = T clock steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dc6400")
-    ap.add_argument("--path", default="plain", choices=["plain", "fused", "persistent", "auto"])
+    ap.add_argument("--path", default="auto", choices=["plain", "fused", "persistent", "auto"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
+    ap.add_argument("--no-paths", action="store_true", help="skip the per-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-rate", type=float, default=5000.0)
+    ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is in "
+              "DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -152,30 +226,46 @@ def main():
     net = Net(cfg, max_batch=B, path=args.path, precision=args.precision)
     net.snn_set_weights(W)
     el, prof = time_path(net, imgs_d, ids_d, T, args.steps, args.warmup, profile=True)
+    used_path = net.snn_last_path()
     value = B * T * args.steps / el
 
     d = dims(cfg, B)
     roof = None
     if prof:
         kname, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
-        per = algorithmic_bytes(kname, d)
+        spl = T * args.steps / max(launches, 1)
+        per = algorithmic_bytes(kname, d, spl)
         avg_s = total_ms / 1e3 / max(launches, 1)
         if per is not None:
             achieved = per / avg_s / 1e9
-            roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "bytes_per_launch": per, "avg_launch_us": avg_s * 1e6, "launches": launches,
+            traffic = measured_traffic(kname)
+            roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": per,
+                    "avg_launch_us": avg_s * 1e6, "launches": launches, "steps_per_launch": spl,
                     "share_of_gpu_time": total_ms / sum(v[1] for v in prof.values())}
     net.close()
 
-    plain = None
-    if not args.no_plain and args.path != "plain":
-        pnet = Net(cfg, max_batch=B, path="plain", precision="fp32")
-        pnet.snn_set_weights(W)
-        pel, _ = time_path(pnet, imgs_d, ids_d, T, max(1, args.steps // 2), 1)
-        plain = {"value": B * T * max(1, args.steps // 2) / pel,
-                 "ms_per_step": pel * 1e3 / max(1, args.steps // 2)}
-        pnet.close()
+    paths = {}
+    if not args.no_paths:
+        for pth in ("plain", "fused", "persistent"):
+            pnet = Net(cfg, max_batch=B, path=pth, precision=args.precision)
+            pnet.snn_set_weights(W)
+            n = 1 if pth == "plain" else 2
+            pel, pprof = time_path(pnet, imgs_d, ids_d, T, n, 1, profile=True)
+            entry = {"value": B * T * n / pel, "ms_per_step": pel * 1e3 / n, "used": pnet.snn_last_path()}
+            main_k = {"fused": "fused_step", "persistent": "persistent"}.get(pth)
+            if main_k and main_k in pprof:
+                ln, ms = pprof[main_k]
+                spl = T * n / max(ln, 1)
+                per = algorithmic_bytes(main_k, d, spl)
+                entry["kernel_avg_us"] = ms * 1e3 / max(ln, 1)
+                entry["hbm_frac"] = per / (ms / 1e3 / max(ln, 1)) / 1e9 / HBM_PEAK_GBS
+            paths[pth] = entry
+            pnet.close()
+
+    serving = None
+    if not args.no_serve:
+        serving = serving_run(args.serve_requests, args.serve_rate, max_slots=1024, chunk=25)
 
     cpu = None if args.no_cpu else cpu_baseline(wl, imgs, ids, W)
 
@@ -186,10 +276,11 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['n_in']}->{cfg['n_exc']}/{cfg['n_inh']} Diehl&Cook, "
                                f"B={B}, T={T}, STDP {'on' if cfg['learn'] else 'off'}, reduce="
-                               f"{['sum', 'mean', 'max'][cfg['reduce']]}",
-                   "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": args.path,
+                               f"{['sum', 'mean', 'max'][cfg['reduce']]}, synthetic stroke images",
+                   "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},
-        "roofline": roof, "cpu_baseline": cpu, "plain_path": plain,
+        "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
+        "vs_plain_path": (value / paths["plain"]["value"]) if "plain" in paths else None,
         "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1)} for k, v in prof.items()},
     }
     print(json.dumps(line), flush=True)

@@ -151,6 +151,11 @@ snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
 /* Select the execution path (snn_path) and contraction precision. */
 snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision);
 
+/* The execution path the most recent snn_run / snn_run_spikes used (the
+ * autotuner's choice when the handle's path is SNN_PATH_AUTO, or the fallback
+ * when the requested path does not fit the batch). */
+snn_status snn_last_path(snn_net *net, int32_t *path);
+
 /* Advance `batch` samples by T steps (Implementation section).
  *   images_dev batch x n_in u8 pixels (ignored when uniform_rate)
  *   ids_dev    batch u64 sample ids; the encoder is keyed by (seed, id,

@@ -1,0 +1,125 @@
+// snn_autotune.hip -- choice of the execution path for SNN_PATH_AUTO.
+//
+// The candidates are the paths whose kernels fit the batch (persistent:
+// cooperative launch with every task's state in registers; fused: the weight
+// block and post traces fit in LDS; plain: always).  The first AUTO run of a
+// given network shape and batch size times each candidate on a scratch copy
+// of the network (same weights, thresholds and inputs, so the spike activity
+// is representative) for a short warm-up and a timed run, keeps the fastest
+// in a process-wide table, and appends it to the file named by
+// SNN_AUTOTUNE_CACHE if set (lines "key path").  SNN_AUTOTUNE=0 skips the
+// measurement and takes the first available path in the order persistent,
+// fused, plain.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+#include "snn_runtime.h"
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, int> g_table;
+bool g_loaded = false;
+
+void load_file_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *fn = std::getenv("SNN_AUTOTUNE_CACHE");
+    if (!fn) return;
+    std::ifstream f(fn);
+    std::string key;
+    int path;
+    while (f >> key >> path)
+        if (path >= 0 && path <= 2) g_table[key] = path;
+}
+
+void append_file(const std::string &key, int path)
+{
+    const char *fn = std::getenv("SNN_AUTOTUNE_CACHE");
+    if (!fn) return;
+    std::ofstream f(fn, std::ios::app);
+    f << key << ' ' << path << '\n';
+}
+
+}  // namespace
+
+int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, const uint64_t *ids,
+                         const uint32_t *forced)
+{
+    std::vector<int> cand;
+    if (persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
+    if (fused_ok()) cand.push_back(SNN_PATH_FUSED);
+    cand.push_back(SNN_PATH_PLAIN);
+    const char *env = std::getenv("SNN_AUTOTUNE");
+    if (cand.size() == 1 || (env && env[0] == '0')) return cand[0];
+
+    std::ostringstream ks;
+    ks << cfg.n_in << 'x' << cfg.n_exc << 'x' << cfg.n_inh << "_l" << cfg.learn << "_r" << cfg.reduce << "_p"
+       << precision << "_jb" << p.jb << "_B" << batch << "_cu" << cus;
+    const std::string key = ks.str();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_file_locked();
+        auto it = g_table.find(key);
+        if (it != g_table.end())
+            for (int c : cand)
+                if (c == it->second) return c;
+    }
+
+    // time each candidate on a scratch copy
+    snn_config c = cfg;
+    c.max_batch = batch;
+    c.hbm_budget_bytes = 0;
+    c.path = SNN_PATH_PLAIN;
+    snn_net *tmp = nullptr;
+    int best = cand[0];
+    if (snn_create(&c, stream, &tmp) == SNN_OK && tmp->p.jb == p.jb) {
+        const size_t nw = (size_t)p.n_in_pad * p.n_pad;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool ok = hipMemcpyAsync(tmp->W, W, nw * sizeof(float), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+                  hipMemcpyAsync(tmp->theta, theta, (size_t)p.n_pad * sizeof(double), hipMemcpyDeviceToDevice,
+                                 stream) == hipSuccess &&
+                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        // the first steps of an episode are not representative (the whole
+        // layer charges up and fires together): run into the episode, then
+        // time a stretch of it
+        const uint32_t lead = T < 32u ? T : 32u;
+        const uint32_t steps = T < 64u ? T : 64u;
+        float best_ms = 1e30f;
+        for (int cnd : cand) {
+            if (!ok) break;
+            tmp->path = cnd;
+            if (tmp->run(images, ids, forced, batch, lead, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
+            if (hipEventRecord(e0, stream) != hipSuccess) break;
+            if (tmp->run(images, ids, forced, batch, steps, forced ? SNN_RUN_RESET : 0u, nullptr) != SNN_OK) continue;
+            float ms = 0.f;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                break;
+            if (tmp->check_device_error() != SNN_OK) continue;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cnd;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    snn_destroy(tmp);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[key] = best;
+    }
+    append_file(key, best);
+    return best;
+}

@@ -25,7 +25,9 @@
 
 namespace snn {
 
-constexpr int kFusedThreads = 1024;  // 16 waves
+constexpr int kFusedThreads = 1024;   // fused per-step kernel: 16 waves
+constexpr int kPersistThreads = 512;  // persistent kernel: 8 waves, with
+constexpr int kPersistTasks = 2;      //   two (sample, 8 columns) tasks each
 
 // Per-network pointers (state and parameters owned by the handle).
 struct FusedArgs {
@@ -316,88 +318,96 @@ __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, 
     }
 }
 
-// Step phase C for one task: input row i, columns c0 .. c0+7.
+// Step phase C for input row i (one thread, all column groups):
 //   P[c] = R over listed spiking samples b with neuron c fired of x_pre[b, i]
 //   D[c] = R over the samples in input i's spike list of x_post[b, c]
 //   w = clamp(float(w * scale[c]) + nu_post * P[c] - nu_pre * D[c])
-// The x_pre loads of up to eight samples are issued before the D gather.
-template <bool Coherent>
-__device__ __forceinline__ void plasticity_task(const Params &p, const StepLds &S, int i, int c0, int cnt, uint2 head,
-                                                const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany)
+// The x_pre values of the first XR spiking samples are loaded once into
+// registers (all in flight together) and reused by every column group.
+template <bool Coherent, int XR>
+__device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S, int i, int cnt, uint2 head,
+                                               const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany)
 {
-    float P[8];
+    const int ncg = p.jbp >> 3;
+    float x[XR];
+    uint32_t cm[XR];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) P[c] = 0.f;
-    const uint32_t grp = (colany >> c0) & 0xFFu;
-    if (grp) {
-        for (int u0 = 0; u0 < ucnt; u0 += 8) {
-            float x[8];
-            uint32_t cm[8];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                cm[v] = 0u;
-                x[v] = 0.f;
-                if (u0 + v < ucnt) {
-                    const int b = (int)S.ulist[u0 + v];
-                    cm[v] = (S.colmask[b] >> c0) & 0xFFu;
-                    if (cm[v]) x[v] = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 8; ++v)
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if ((cm[v] >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+    for (int v = 0; v < XR; ++v) {
+        cm[v] = 0u;
+        x[v] = 0.f;
+        if (v < ucnt) {
+            const int b = (int)S.ulist[v];
+            cm[v] = S.colmask[b];
+            if (cm[v]) x[v] = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
         }
     }
-    float D[8];
-    gather8(ltrow, cnt, head, head, 4, S.xpost, p.jbp, c0, p.B, p.reduce, D);
-    float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.jbp + c0);
-    const float4 w0 = wr[0], w1 = wr[1];
-    float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    for (int cg = 0; cg < ncg; ++cg) {
+        const int c0 = 8 * cg;
+        float P[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        float x = (float)((double)w[c] * S.scale[c0 + c]);
-        if ((grp >> c) & 1u) x = x + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
-        const float d = p.reduce == RED_MEAN ? D[c] * p.inv_B : D[c];
-        w[c] = fminf(fmaxf(x - p.nu_pre * d, p.w_min), p.w_max);
+        for (int c = 0; c < 8; ++c) P[c] = 0.f;
+        const uint32_t grp = (colany >> c0) & 0xFFu;
+        if (grp) {
+#pragma unroll
+            for (int v = 0; v < XR; ++v) {
+                const uint32_t m = (cm[v] >> c0) & 0xFFu;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+            }
+            for (int u = XR; u < ucnt; ++u) {
+                const int b = (int)S.ulist[u];
+                const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
+                if (!m) continue;
+                const float xv = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
+            }
+        }
+        float D[8];
+        gather8(ltrow, cnt, head, head, 4, S.xpost, p.jbp, c0, p.B, p.reduce, D);
+        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.jbp + c0);
+        const float4 w0 = wr[0], w1 = wr[1];
+        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float xw = (float)((double)w[c] * S.scale[c0 + c]);
+            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
+            const float d = p.reduce == RED_MEAN ? D[c] * p.inv_B : D[c];
+            w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
+        }
+        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
     }
-    wr[0] = make_float4(w[0], w[1], w[2], w[3]);
-    wr[1] = make_float4(w[4], w[5], w[6], w[7]);
 }
 
-// Phase C over all (row, column group) tasks of the block; each thread loads
-// the next task's list head before working on the current one.
-template <bool Coherent>
+// Phase C over all input rows of the block; a thread loads its next row's
+// list head before working on the current row.
+template <bool Coherent, int XR>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const float *xpre, int tid, int nt)
 {
-    const int ncg = p.jbp >> 3;
     const int ucnt = (int)S.ulist[p.B];
     uint32_t colany = 0u;
     for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
-    const int ntask = p.n_in * ncg;
-    int q = tid;
+    int i = tid;
     uint32_t cnt_n = 0u;
     uint2 head_n = make_uint2(0u, 0u);
-    if (q < ntask) {
-        const int i = q / ncg;
+    if (i < p.n_in) {
         cnt_n = ct[i];
         head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)i * p.lt_stride);
     }
-    while (q < ntask) {
-        const int i = q / ncg;
-        const int c0 = 8 * (q - i * ncg);
+    while (i < p.n_in) {
         const uint32_t cnt = cnt_n;
         const uint2 head = head_n;
-        const int qn = q + nt;
-        if (qn < ntask) {
-            const int inx = qn / ncg;
-            cnt_n = ct[inx];
-            head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)inx * p.lt_stride);
+        const int in = i + nt;
+        if (in < p.n_in) {
+            cnt_n = ct[in];
+            head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)in * p.lt_stride);
         }
-        plasticity_task<Coherent>(p, S, i, c0, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany);
-        q = qn;
+        plasticity_row<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany);
+        i = in;
     }
 }
 

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     if (!p.learn) return;
     __syncthreads();
 
-    plasticity_all<false>(p, S, s.lt, s.ct, s.xpre, tid, nt);
+    plasticity_all<false, 16>(p, S, s.lt, s.ct, s.xpre, tid, nt);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);

@@ -19,7 +19,7 @@ namespace snn {
 
 constexpr uint32_t kSpinLimit = 1u << 25;  // about a second of s_sleep(1) polls
 
-size_t persist_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads).total; }
+size_t persist_lds_bytes(const Params &p) { return FusedLds(p, kPersistThreads).total; }
 
 // Grid-wide barrier between steps.  Data another workgroup reads after the
 // barrier is written with agent-scope atomic stores or atomic RMWs; every
@@ -48,7 +48,7 @@ __device__ __forceinline__ bool grid_barrier(const PersistSync &sy, uint32_t tar
     return *abort_lds == 0;
 }
 
-__global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__restrict__ args)
+__global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *__restrict__ args)
 {
     const Params &p = args->p;
     const FusedArgs &a = args->a;
@@ -64,23 +64,34 @@ __global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__
     const int JB = p.jb, JBP = p.jbp, ncg = p.jbp >> 3;
     float *Wg = a.W + (size_t)g * p.n_in_pad * JB;
 
-    // prologue: weight block, thresholds, this thread's neuron state
+    // prologue: weight block, thresholds, the state of this thread's tasks
+    // (task u = (sample, 8 columns) number tid + u * nt)
     load_block(p, S, Wg, a.theta, g, tid, nt);
-    const bool has_task = tid < p.B * ncg;
-    const int b = has_task ? tid / ncg : 0;
-    const int c0 = 8 * (tid - b * ncg);
-    const size_t n0 = (size_t)g * p.Bs * JBP + (size_t)b * JBP + c0;
-    const int nv = max(0, min(8, min(JB, p.n_exc - g * JB) - c0));
-    float ve[8], vi[8];
-    uint32_t rw[4];
-    if (has_task) load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
-    // the spike lists are read-only during the launch: the next step's list
-    // head is fetched before each barrier
-    uint32_t hin_cnt = 0u;
-    uint4 hin = make_uint4(0u, 0u, 0u, 0u);
-    if (has_task && ch.steps > 0) {
-        hin_cnt = ch.cin[b];
-        hin = *reinterpret_cast<const uint4 *>(ch.lin + (size_t)b * p.n_in_pad);
+    bool has_task[kPersistTasks];
+    int tb[kPersistTasks], tc0[kPersistTasks], tnv[kPersistTasks];
+    float ve[kPersistTasks][8], vi[kPersistTasks][8];
+    uint32_t rw[kPersistTasks][4];
+    uint32_t hin_cnt[kPersistTasks];
+    uint4 hin[kPersistTasks];
+#pragma unroll
+    for (int u = 0; u < kPersistTasks; ++u) {
+        const int q = tid + u * nt;
+        has_task[u] = q < p.B * ncg;
+        tb[u] = has_task[u] ? q / ncg : 0;
+        tc0[u] = 8 * (q - tb[u] * ncg);
+        tnv[u] = max(0, min(8, min(JB, p.n_exc - g * JB) - tc0[u]));
+        hin_cnt[u] = 0u;
+        hin[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (has_task[u]) {
+            load_task_state(p, S, a, (size_t)g * p.Bs * JBP + (size_t)tb[u] * JBP + tc0[u], tb[u], tc0[u], ve[u],
+                            vi[u], rw[u]);
+            // the spike lists are read-only during the launch: the next
+            // step's list head is fetched before each barrier
+            if (ch.steps > 0) {
+                hin_cnt[u] = ch.cin[tb[u]];
+                hin[u] = *reinterpret_cast<const uint4 *>(ch.lin + (size_t)tb[u] * p.n_in_pad);
+            }
+        }
     }
     __syncthreads();
 
@@ -92,33 +103,43 @@ __global__ __launch_bounds__(kFusedThreads) void k_persist(const PersistArgs *__
 
         step_begin<true>(p, S, ch.C + (size_t)((mod + 2) % 3) * p.Bs, tid, nt);
         __syncthreads();
-        if (has_task) {
+#pragma unroll
+        for (int u = 0; u < kPersistTasks; ++u) {
+            if (!has_task[u]) continue;
             float acc[8];
-            const uint16_t *row = ch.lin + ((size_t)k * p.B + b) * p.n_in_pad;
-            gather8(row, (int)hin_cnt, make_uint2(hin.x, hin.y), make_uint2(hin.z, hin.w), 8, S.W, JBP, c0,
-                    p.n_in_pad, RED_SUM, acc);
-            neuron_task(p, S, a.o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, ve, vi, rw);
+            const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
+            gather8(row, (int)hin_cnt[u], make_uint2(hin[u].x, hin[u].y), make_uint2(hin[u].z, hin[u].w), 8, S.W, JBP,
+                    tc0[u], p.n_in_pad, RED_SUM, acc);
+            neuron_task(p, S, a.o, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, ve[u], vi[u], rw[u]);
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
         if (p.learn) {
             __syncthreads();
-            plasticity_all<true>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride, ch.ct + (size_t)k * p.n_in_pad, xpre,
-                           tid, nt);
+            plasticity_all<true, 16>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
+                                     ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt);
             __syncthreads();
             colsums_theta(p, S, tid, nt);
             if (k + 1 < ch.steps || ch.has_next)
                 xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
         }
-        if (has_task && k + 1 < ch.steps) {
-            hin_cnt = ch.cin[(size_t)(k + 1) * p.B + b];
-            hin = *reinterpret_cast<const uint4 *>(ch.lin + ((size_t)(k + 1) * p.B + b) * p.n_in_pad);
+        if (k + 1 < ch.steps) {
+#pragma unroll
+            for (int u = 0; u < kPersistTasks; ++u) {
+                if (!has_task[u]) continue;
+                hin_cnt[u] = ch.cin[(size_t)(k + 1) * p.B + tb[u]];
+                hin[u] = *reinterpret_cast<const uint4 *>(ch.lin + ((size_t)(k + 1) * p.B + tb[u]) * p.n_in_pad);
+            }
         }
         if (!grid_barrier(sy, (uint32_t)(k + 1) * gridDim.x, &abort_lds)) return;
     }
 
     // epilogue: state, weights (normalised) and thresholds back to HBM
-    if (has_task) store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
+#pragma unroll
+    for (int u = 0; u < kPersistTasks; ++u)
+        if (has_task[u])
+            store_task_state(p, S, a, (size_t)g * p.Bs * JBP + (size_t)tb[u] * JBP + tc0[u], tb[u], tc0[u], ve[u],
+                             vi[u], rw[u]);
     if (p.learn) store_block(p, S, Wg, a.theta, g, tid, nt);
 }
 

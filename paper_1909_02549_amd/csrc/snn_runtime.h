@@ -23,6 +23,7 @@ struct snn_net {
     int cus = 256;
     int path = 0;
     int precision = 0;
+    int last_path = -1;
 
     // shared parameters
     float *W = nullptr;          // FP32 master, block layout
@@ -102,5 +103,7 @@ struct snn_net {
     snn_status serve_steps(const uint8_t *images, const uint64_t *ids, const uint32_t *tl, uint32_t B, uint32_t steps,
                            uint32_t *counts, const uint8_t *new_mask);
     friend struct snn_server;
-    int choose_path(uint32_t batch, uint32_t T);
+    // AUTO: the fastest available execution path for this batch, measured
+    // once on a scratch copy of the network (snn_autotune.hip)
+    int choose_path(uint32_t batch, uint32_t T, const uint8_t *images, const uint64_t *ids, const uint32_t *forced);
 };

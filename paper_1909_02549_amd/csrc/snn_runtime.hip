@@ -442,6 +442,13 @@ snn_status snn_net::check_device_error()
     return SNN_OK;
 }
 
+extern "C" snn_status snn_last_path(snn_net *net, int32_t *path)
+{
+    if (!net || !path) return fail(SNN_EINVAL, "NULL argument");
+    *path = net->last_path;
+    return SNN_OK;
+}
+
 extern "C" snn_status snn_sync(snn_net *net)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
@@ -626,7 +633,7 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     zero(o.raster_inh, (size_t)T * batch * words);
     HIP_TRY(hipGetLastError());
 
-    int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T) : this->path;
+    int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T, images, ids, forced) : this->path;
     return run_steps(path, images, ids, forced, T, o);
 }
 
@@ -679,7 +686,7 @@ bool snn_net::persist_ok()
         int v = 0;
         coop_ok = (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess && v) ? 1 : 0;
     }
-    return coop_ok == 1 && p.jb <= 32 && p.B * (p.jbp / 8) <= kFusedThreads && p.nblk <= cus &&
+    return coop_ok == 1 && p.jb <= 32 && p.B * (p.jbp / 8) <= kPersistThreads * kPersistTasks && p.nblk <= cus &&
            p.n_in_pad < 65535 && p.B < 65535 && persist_lds_bytes(p) + 64 <= kMaxLds;
 }
 
@@ -721,7 +728,7 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
         kid = kstat_id("persistent");
         ev = prof_begin();
     }
-    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_persist, dim3((unsigned)p.nblk), dim3(kFusedThreads), kargs,
+    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_persist, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
                                        (unsigned)lds, stream));
     if (prof) prof_end(kid, ev);
     gstep += (uint64_t)steps;
@@ -744,7 +751,7 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
     }
     Outs o{};
     o.counts = counts;
-    int path = this->path == SNN_PATH_AUTO ? choose_path(B, steps) : this->path;
+    int path = this->path == SNN_PATH_AUTO ? choose_path(B, steps, images, ids, nullptr) : this->path;
     snn_status st = run_steps(path, images, ids, nullptr, steps, o, tl_dev);
     if (st != SNN_OK) return st;
     SNN_LAUNCH("slot_step", k_add_u32, dim3((B + 255) / 256), dim3(256), 0, const_cast<uint32_t *>(tl_dev), steps,
@@ -758,6 +765,7 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
 {
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
+    last_path = path;
     for (uint32_t k0 = 0; k0 < T; k0 += chunk) {
         const int steps = (int)std::min<uint32_t>(chunk, T - k0);
         const bool more = k0 + (uint32_t)steps < T;
@@ -796,14 +804,6 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
     return SNN_OK;
 }
 
-// Without a measured table the persistent path is preferred where its
-// cooperative launch fits, then the fused per-step path.
-int snn_net::choose_path(uint32_t, uint32_t)
-{
-    if (persist_ok()) return SNN_PATH_PERSISTENT;
-    if (fused_ok()) return SNN_PATH_FUSED;
-    return SNN_PATH_PLAIN;
-}
 
 extern "C" snn_status snn_run(snn_net *net, const uint8_t *images_dev, const uint64_t *ids_dev, uint32_t batch,
                               uint32_t T, uint32_t flags, const snn_outputs *out)

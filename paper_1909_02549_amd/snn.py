@@ -26,7 +26,7 @@ STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4
 
 EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "snn_set_stream",
             "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce",
-            "snn_set_path", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
+            "snn_set_path", "snn_last_path", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
             "snn_serve_destroy"]
@@ -86,6 +86,7 @@ def load_library():
         "snn_get_theta": ([VP, VP, SZ], I32),
         "snn_stdp_reduce": ([VP, I32], I32),
         "snn_set_path": ([VP, I32, I32], I32),
+        "snn_last_path": ([VP, P(I32)], I32),
         "snn_run": ([VP, VP, VP, U32, U32, U32, P(snn_outputs)], I32),
         "snn_run_spikes": ([VP, VP, U32, U32, U32, P(snn_outputs)], I32),
         "snn_sync": ([VP], I32),
@@ -203,6 +204,11 @@ class Net:
     def snn_set_path(self, path="plain", precision="fp32"):
         _check(self.lib.snn_set_path(self.h, PATHS[path] if isinstance(path, str) else int(path),
                                      PRECISIONS[precision] if isinstance(precision, str) else int(precision)))
+
+    def snn_last_path(self) -> str:
+        v = C.c_int32()
+        _check(self.lib.snn_last_path(self.h, C.byref(v)))
+        return {v_: k for k, v_ in PATHS.items()}.get(v.value, str(v.value))
 
     def snn_sync(self):
         _check(self.lib.snn_sync(self.h))
