@@ -31,7 +31,7 @@ class _Lif(C.Structure):
 class _Config(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_exc", C.c_int32), ("n_inh", C.c_int32),
                 ("uniform_rate", C.c_int32), ("learn", C.c_int32),
-                ("trace_additive", C.c_int32), ("reduce", C.c_int32), ("pad0", C.c_int32),
+                ("trace_additive", C.c_int32), ("reduce", C.c_int32), ("precision", C.c_int32),
                 ("dt_ms", C.c_double), ("max_rate_hz", C.c_double),
                 ("exc", _Lif), ("inh", _Lif), ("w_ei", C.c_double), ("w_ie", C.c_double),
                 ("nu_pre", C.c_double), ("nu_post", C.c_double), ("tau_pre_ms", C.c_double),
@@ -56,6 +56,8 @@ def lib():
         _lib.orc_threshold.argtypes = [C.POINTER(_Config), C.c_int]
         _lib.orc_threshold.restype = C.c_uint32
         _lib.orc_run.restype = C.c_int
+        _lib.orc_quantize.argtypes = [C.c_double, C.c_int]
+        _lib.orc_quantize.restype = C.c_double
     return _lib
 
 
@@ -65,10 +67,14 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
-def make_config(cfg: dict) -> _Config:
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+
+
+def make_config(cfg: dict, precision=0) -> _Config:
     c = _Config()
     for k in ("n_in", "n_exc", "n_inh", "uniform_rate", "learn", "trace_additive", "reduce"):
         setattr(c, k, int(cfg[k]))
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     for k in ("dt_ms", "max_rate_hz", "w_ei", "w_ie", "nu_pre", "nu_post", "tau_pre_ms",
               "tau_post_ms", "w_min", "w_max", "norm"):
         setattr(c, k, float(cfg[k]))
@@ -97,6 +103,15 @@ def uniform32(seed: int, sample_id: int, t: int, i: int) -> int:
     return int(lib().orc_uniform32(seed, sample_id, t, i))
 
 
+def quantize(x, precision) -> np.ndarray:
+    """Operand rounding of the reduced-precision forms (``orc_quantize``):
+    0 none, 1 bfloat16, 2 OCP FP8 E4M3, each from the value's FP32 form,
+    round to nearest even."""
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    f = lib().orc_quantize
+    return np.array([f(float(v), p) for v in np.ravel(x)]).reshape(np.shape(x))
+
+
 def threshold_table(cfg: dict) -> np.ndarray:
     c = make_config(cfg)
     return np.array([lib().orc_threshold(C.byref(c), p) for p in range(256)], dtype=np.uint64)
@@ -104,11 +119,13 @@ def threshold_table(cfg: dict) -> np.ndarray:
 
 class OracleNet:
     """FP64 reference network.  ``W`` is (n_in, n_exc) float64, shared;
-    ``theta`` is (n_exc,) float64, shared."""
+    ``theta`` is (n_exc,) float64, shared.  ``precision`` ("fp32", "bf16",
+    "fp8") rounds the weight and trace operands of the two contractions (see
+    ``quantize``); "fp32" leaves them in FP64."""
 
-    def __init__(self, cfg: dict, W: np.ndarray, theta: np.ndarray | None = None):
+    def __init__(self, cfg: dict, W: np.ndarray, theta: np.ndarray | None = None, precision="fp32"):
         self.cfg = dict(cfg)
-        self.c = make_config(cfg)
+        self.c = make_config(cfg, precision)
         n_in, n_exc = cfg["n_in"], cfg["n_exc"]
         assert W.shape == (n_in, n_exc)
         self.W = np.ascontiguousarray(W, dtype=np.float64).copy()

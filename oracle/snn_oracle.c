@@ -96,13 +96,52 @@ typedef struct {
     int32_t n_in, n_exc, n_inh;      /* n_inh = 0: no inhibitory layer      */
     int32_t uniform_rate, learn;     /* uniform_rate: every input max_rate  */
     int32_t trace_additive, reduce;  /* reduce: 0 sum, 1 mean, 2 max         */
-    int32_t pad0;
+    int32_t precision;               /* operand rounding, see orc_quantize  */
     double dt_ms, max_rate_hz;
     orc_lif exc, inh;
     double w_ei, w_ie;
     double nu_pre, nu_post, tau_pre_ms, tau_post_ms, w_min, w_max, norm;
     uint64_t seed;
 } orc_config;
+
+/* ------------------------------------------------------------------------ */
+/* Operand precision of the two contractions.  The synaptic contraction and  */
+/* the STDP products multiply exact 0/1 spikes by a weight or a trace; in    */
+/* the reduced-precision forms that weight or trace enters rounded to        */
+/* bfloat16 or to OCP FP8 E4M3, while sums stay wide and the master weights  */
+/* stay full precision.  The rounding starts from the value's single-        */
+/* precision form (the precision the kernels hold it in), so both sides take */
+/* the same rounding decision.                                                */
+/*   0  none (FP64 here)                                                      */
+/*   1  bfloat16: 8 significant bits, FP32 exponent range                     */
+/*   2  E4M3 (OCP FP8): 4 significant bits, exponent bias 7, smallest normal  */
+/*      2^-6, subnormal spacing 2^-9, largest finite 448 (saturating here)    */
+/* Both round to nearest, ties to even.                                       */
+/* ------------------------------------------------------------------------ */
+static double round_to_grid(double x, int mant_bits, int min_exp)
+{
+    /* nearest multiple of 2^(e - mant_bits + 1), e = max(floor(log2|x|), min_exp) */
+    double a = fabs(x);
+    if (a == 0.0 || !isfinite(a)) return x;
+    int e;
+    frexp(a, &e);        /* a = m 2^e, m in [0.5, 1): floor(log2 a) = e - 1 */
+    e -= 1;
+    if (e < min_exp) e = min_exp;
+    double ulp = ldexp(1.0, e - mant_bits + 1);
+    double q = nearbyint(a / ulp) * ulp; /* default rounding: nearest, ties to even */
+    return x < 0 ? -q : q;
+}
+
+double orc_quantize(double x, int precision)
+{
+    if (precision == 0) return x;
+    double f = (double)(float)x;
+    if (precision == 1) return round_to_grid(f, 8, -126);
+    double q = round_to_grid(f, 4, -6);
+    if (q > 448.0) q = 448.0;
+    if (q < -448.0) q = -448.0;
+    return q;
+}
 
 /* Spike probability per step as a 32-bit threshold: a spike happens when the
  * uniform word is below thr.  Rate for pixel p is p/255 * max_rate (Hz), so
@@ -191,6 +230,8 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
     const double lam_pre = exp(-c->dt_ms / c->tau_pre_ms);
     const double lam_post = exp(-c->dt_ms / c->tau_post_ms);
     const int adaptive = c->exc.adaptive != 0;
+    const int prec = c->precision;
+    if (prec < 0 || prec > 2) return -1;
 
     uint32_t thr_lut[256];
     for (int p = 0; p < 256; ++p) thr_lut[p] = orc_threshold(c, p);
@@ -231,7 +272,7 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
             for (int i = 0; i < n_in; ++i) {
                 if (!s_in[(size_t)b * n_in + i]) continue;
                 const double *row = W + (size_t)i * n_exc;
-                for (int j = 0; j < n_exc; ++j) Ie[j] += row[j];
+                for (int j = 0; j < n_exc; ++j) Ie[j] += orc_quantize(row[j], prec);
             }
             if (n_inh > 0) {
                 const uint8_t *si = s_inh_prev + (size_t)b * n_inh;
@@ -291,8 +332,8 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                         const uint8_t *se = s_exc + (size_t)b * n_exc;
                         const double *xq = x_post + (size_t)b * n_exc;
                         for (int j = 0; j < n_exc; ++j) {
-                            double tp = se[j] ? xp : 0.0;
-                            double td = sp ? xq[j] : 0.0;
+                            double tp = se[j] ? orc_quantize(xp, prec) : 0.0;
+                            double td = sp ? orc_quantize(xq[j], prec) : 0.0;
                             if (b == 0) {
                                 P[j] = tp;
                                 D[j] = td;
