@@ -74,9 +74,56 @@ def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: float = 1.0):
         return B * N * 4 + spikes
     if kernel == "xpre":
         return 2 * xpre + spikes
+    if kernel == "mfma_contract":
+        return w + B * N * 4 + B * d["in_words"] * 4
+    if kernel == "mfma_plastic":
+        return 2 * w + B * N * (4 + 2) + B * n_in_pad * 4 + n_in_pad * d["bwords"] * 4
     if kernel == "encode":
         return steps_per_launch * 2 * spikes + B * n_in
     return None
+
+
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+# matrix-core operations per algorithmic product: the FP32 form multiplies
+# three bfloat16 parts of each operand value
+MFMA_PLANES = {"fp32": 3, "bf16": 1, "fp8": 1}
+
+
+def algorithmic_flops(kernel: str, d: dict):
+    """Dense-equivalent flops of one launch of a matrix-core kernel: the
+    synaptic current B x n_in x N, the STDP terms P and D as two outer
+    products over the batch (the potentiation K is compacted to the samples
+    that fired, so fewer products actually run)."""
+    if kernel == "mfma_contract":
+        return 2.0 * d["B"] * d["n_in"] * d["n_exc"]
+    if kernel == "mfma_plastic":
+        return 4.0 * d["B"] * d["n_in"] * d["n_exc"]
+    return None
+
+
+def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms: float, spl: float):
+    """Roofline entry of one kernel from its live HIP-event timing: HBM
+    fraction from the algorithmic bytes, and for the matrix-core kernels the
+    MFMA fraction from the dense-equivalent flops; `bound` is the resource
+    with the larger fraction."""
+    per = algorithmic_bytes(kname, d, spl)
+    if per is None:
+        return None
+    avg_s = total_ms / 1e3 / max(launches, 1)
+    gbs = per / avg_s / 1e9
+    r = {"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kname), "bytes_per_launch": per,
+         "avg_launch_us": avg_s * 1e6, "launches": launches, "steps_per_launch": spl}
+    fl = algorithmic_flops(kname, d)
+    if fl is not None:
+        dt = "fp8" if precision == "fp8" else "bf16"
+        tf = fl / avg_s / 1e12
+        mfrac = tf * MFMA_PLANES[precision] / MFMA_PEAK_TFLOPS[dt]
+        r["mfma"] = {"achieved": tf, "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s", "frac": mfrac,
+                     "flops_per_launch": fl, "mfma_ops_per_product": MFMA_PLANES[precision], "dtype": dt}
+        if mfrac > r["frac"]:
+            r.update(bound="mfma", achieved=tf, peak=MFMA_PEAK_TFLOPS[dt], unit="TFLOP/s", frac=mfrac)
+    return r
 
 
 def measured_traffic(kernel: str):
@@ -178,19 +225,77 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
             "peak_active": st["peak_active"]}
 
 
+def sweep(name: str, trials: int) -> dict:
+    """Throughput sweeps (not part of the default run):
+    scale  1000 uniform 20 Hz inputs -> 1000 LIF, no learning, T=1000, over
+           B = 1 .. 4096: per-step launches with and without graph replay,
+           the matrix-core route, the fused and the persistent kernel;
+    dc400  784 -> 400/400, T=250, STDP on, over B = 16 .. 1024, each batch
+           reduction and operand precision on the autotuned path."""
+    import torch
+    from paper_1909_02549_amd import inputs
+    from paper_1909_02549_amd.snn import Net, SnnError
+    wl = inputs.workload(name)
+    cfg, T = wl["cfg"], wl["T"]
+    if "wlo" in wl:
+        W = inputs.uniform_weights(cfg["n_in"], cfg["n_exc"], wl["wlo"], wl["whi"], 0)
+    else:
+        W = inputs.normal_weights(cfg["n_in"], cfg["n_exc"], wl["wmean"], wl["wstd"], 0)
+    dev = torch.device("cuda:0")
+    rows = []
+
+    def one(B, path, graphs=False, reduce=None, precision="fp32"):
+        c = dict(cfg)
+        if reduce is not None:
+            c["reduce"] = {"sum": 0, "mean": 1, "max": 2}[reduce]
+        imgs = inputs.stroke_images(B, 99, wl["density"]) if wl["density"] is not None else None
+        imgs_d = torch.from_numpy(imgs).to(dev) if imgs is not None else None
+        ids_d = torch.from_numpy(inputs.sample_ids(B).astype(np.int64)).to(dev)
+        try:
+            net = Net(c, max_batch=B, path=path, precision=precision)
+        except SnnError as e:
+            return {"B": B, "path": path, "error": str(e)}
+        net.snn_set_weights(W)
+        if graphs:
+            net.snn_set_graphs(True)
+        el, _ = time_path(net, imgs_d, ids_d, T, trials, 1)
+        r = {"B": B, "path": path, "graphs": graphs, "used": net.snn_last_path(), "precision": precision,
+             "value": B * T * trials / el, "ms_per_step": el * 1e3 / (T * trials)}
+        if reduce is not None:
+            r["reduce"] = reduce
+        net.close()
+        return r
+
+    if name == "scale":
+        for B in (1, 8, 64, 512, 4096):
+            for path, graphs in (("plain", False), ("plain", True), ("mfma", False), ("mfma", True),
+                                 ("fused", False), ("fused", True), ("persistent", False)):
+                rows.append(one(B, path, graphs))
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    else:
+        for B in (16, 64, 256, 1024):
+            for reduce in ("sum", "mean", "max"):
+                for precision in ("fp32", "bf16", "fp8"):
+                    rows.append(one(B, "auto", True, reduce, precision))
+                    print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"workload": name, "T": T, "trials": trials, "unit": "sample·steps/s", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed trials (one trial = T clock steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dc6400")
-    ap.add_argument("--path", default="auto", choices=["plain", "fused", "persistent", "auto"])
+    ap.add_argument("--path", default="auto", choices=["plain", "fused", "persistent", "mfma", "auto"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-paths", action="store_true", help="skip the per-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--sweep", choices=["scale", "dc400"], default=None,
+                    help="print a throughput sweep instead of the benchmark line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (profiler calibration)")
     args = ap.parse_args()
@@ -198,6 +303,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is in "
               "DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        print(json.dumps({"sweep": sweep(args.sweep, args.steps)}), flush=True)
+        return
 
     import torch
     from paper_1909_02549_amd import inputs
@@ -231,35 +340,35 @@ def main():
 
     d = dims(cfg, B)
     roof = None
+    kroofs = {}
     if prof:
-        kname, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
-        spl = T * args.steps / max(launches, 1)
-        per = algorithmic_bytes(kname, d, spl)
-        avg_s = total_ms / 1e3 / max(launches, 1)
-        if per is not None:
-            achieved = per / avg_s / 1e9
-            traffic = measured_traffic(kname)
-            roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": per,
-                    "avg_launch_us": avg_s * 1e6, "launches": launches, "steps_per_launch": spl,
-                    "share_of_gpu_time": total_ms / sum(v[1] for v in prof.values())}
+        gpu_ms = sum(v[1] for v in prof.values())
+        for kn, (ln, ms) in prof.items():
+            kr = kernel_roofline(kn, d, args.precision, ln, ms, T * args.steps / max(ln, 1))
+            if kr is not None:
+                kr["share_of_gpu_time"] = ms / gpu_ms
+                kroofs[kn] = kr
+        kname = max(prof.items(), key=lambda kv: kv[1][1])[0]
+        roof = kroofs.get(kname)
     net.close()
 
     paths = {}
     if not args.no_paths:
-        for pth in ("plain", "fused", "persistent"):
+        for pth in ("plain", "mfma", "fused", "persistent"):
             pnet = Net(cfg, max_batch=B, path=pth, precision=args.precision)
             pnet.snn_set_weights(W)
             n = 1 if pth == "plain" else 2
             pel, pprof = time_path(pnet, imgs_d, ids_d, T, n, 1, profile=True)
             entry = {"value": B * T * n / pel, "ms_per_step": pel * 1e3 / n, "used": pnet.snn_last_path()}
-            main_k = {"fused": "fused_step", "persistent": "persistent"}.get(pth)
-            if main_k and main_k in pprof:
-                ln, ms = pprof[main_k]
-                spl = T * n / max(ln, 1)
-                per = algorithmic_bytes(main_k, d, spl)
-                entry["kernel_avg_us"] = ms * 1e3 / max(ln, 1)
-                entry["hbm_frac"] = per / (ms / 1e3 / max(ln, 1)) / 1e9 / HBM_PEAK_GBS
+            entry["kernels"] = {}
+            for kn, (ln, ms) in pprof.items():
+                kr = kernel_roofline(kn, d, args.precision, ln, ms, T * n / max(ln, 1))
+                ke = {"launches": ln, "avg_us": ms * 1e3 / max(ln, 1)}
+                if kr is not None:
+                    ke["hbm_frac"] = kr["bytes_per_launch"] / (kr["avg_launch_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
+                    if "mfma" in kr:
+                        ke["mfma_frac"] = kr["mfma"]["frac"]
+                entry["kernels"][kn] = ke
             paths[pth] = entry
             pnet.close()
 
@@ -281,7 +390,8 @@ def main():
                    "precision": args.precision},
         "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
         "vs_plain_path": (value / paths["plain"]["value"]) if "plain" in paths else None,
-        "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1)} for k, v in prof.items()},
+        "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1),
+                        **({"roofline": kroofs[k]} if k in kroofs else {})} for k, v in prof.items()},
     }
     print(json.dumps(line), flush=True)
 

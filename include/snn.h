@@ -54,18 +54,36 @@ typedef enum {
  * in the unsupervised-learning experiment). */
 typedef enum { SNN_REDUCE_SUM = 0, SNN_REDUCE_MEAN = 1, SNN_REDUCE_MAX = 2 } snn_reduce;
 
-/* Operand type of the synaptic contraction.  Weights are always kept as an
- * FP32 master copy; BF16 / FP8(e4m3) are contraction copies of it. */
+/* Operand form of the two contractions of a step (the synaptic current and
+ * the STDP products).  Spikes are exact 0/1 operands; the weight (current)
+ * and the traces (STDP) enter
+ *   SNN_FP32      unrounded (the matrix-core route splits each FP32 value
+ *                 into three bfloat16 parts that sum to it exactly),
+ *   SNN_BF16      rounded to bfloat16, nearest even,
+ *   SNN_FP8_E4M3  rounded to OCP FP8 E4M3, nearest even (saturating at 448),
+ * each from its FP32 value.  Sums accumulate in FP32; the master weights stay
+ * FP32, theta and the column sums FP64.  The reduced forms run on the PLAIN
+ * and MFMA paths; a FUSED or PERSISTENT request with them runs MFMA. */
 typedef enum { SNN_FP32 = 0, SNN_BF16 = 1, SNN_FP8_E4M3 = 2 } snn_precision;
 
 /* How the T-step loop is executed.
  *   PLAIN      one launch per kernel per step (encoder, contraction, neuron
- *              update, plasticity), the straightforward per-step path;
+ *              update, plasticity), gathers over the spiking inputs and
+ *              samples: the straightforward per-step path;
  *   FUSED      one column-partitioned launch per step carrying contraction,
  *              neuron update and plasticity, encoder hoisted over all T;
  *   PERSISTENT one cooperative launch for all T steps, state kept on chip;
- *   AUTO       chosen by the library's autotuner for (batch, T). */
-typedef enum { SNN_PATH_PLAIN = 0, SNN_PATH_FUSED = 1, SNN_PATH_PERSISTENT = 2, SNN_PATH_AUTO = 3 } snn_path;
+ *   AUTO       chosen by the library's autotuner for (batch, T, precision);
+ *   MFMA       per-step launches with the synaptic current and the STDP
+ *              outer products over the batch on the matrix cores (max
+ *              reduction keeps the gather plasticity kernel). */
+typedef enum {
+    SNN_PATH_PLAIN = 0,
+    SNN_PATH_FUSED = 1,
+    SNN_PATH_PERSISTENT = 2,
+    SNN_PATH_AUTO = 3,
+    SNN_PATH_MFMA = 4
+} snn_path;
 
 /* One LIF population (Scaling and Unsupervised Learning sections).
  * Voltages in mV, times in ms.  adaptive != 0 adds the shared threshold
@@ -148,8 +166,20 @@ snn_status snn_get_theta(snn_net *net, double *theta_host, size_t n);
  * methods section).  Takes effect at the next step. */
 snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
 
-/* Select the execution path (snn_path) and contraction precision. */
+/* Select the execution path (snn_path) and the operand form of the
+ * contractions (snn_precision).  SNN_EINVAL for values out of range. */
 snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision);
+
+/* Replay repeated episodic runs from captured HIP graphs (on = 1) or launch
+ * every kernel (on = 0, the default).  With graphs on, an snn_run /
+ * snn_run_spikes with SNN_RUN_RESET (or a new batch size) on the PLAIN,
+ * MFMA or FUSED path is captured the first time its arguments occur (batch,
+ * T, buffers, reduction, precision) and replayed with a single launch
+ * afterwards; results are those of the launched kernels.  Profiling
+ * (snn_profile_enable) and the PERSISTENT path always launch directly.
+ * Captured graphs are dropped when the batch capacity, path, precision or
+ * reduction changes.  SNN_EINVAL for a NULL handle or on not in {0, 1}. */
+snn_status snn_set_graphs(snn_net *net, int32_t on);
 
 /* The execution path the most recent snn_run / snn_run_spikes used (the
  * autotuner's choice when the handle's path is SNN_PATH_AUTO, or the fallback

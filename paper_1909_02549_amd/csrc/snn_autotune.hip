@@ -40,7 +40,7 @@ void load_file_locked()
     std::string key;
     int path;
     while (f >> key >> path)
-        if (path >= 0 && path <= 2) g_table[key] = path;
+        if (path >= 0 && path <= 4 && path != SNN_PATH_AUTO) g_table[key] = path;
 }
 
 void append_file(const std::string &key, int path)
@@ -57,8 +57,10 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
                          const uint32_t *forced)
 {
     std::vector<int> cand;
-    if (persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
-    if (fused_ok()) cand.push_back(SNN_PATH_FUSED);
+    // the step kernels compute in the FP32 form only
+    if (p.prec == 0 && persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
+    if (p.prec == 0 && fused_ok()) cand.push_back(SNN_PATH_FUSED);
+    cand.push_back(SNN_PATH_MFMA);
     cand.push_back(SNN_PATH_PLAIN);
     const char *env = std::getenv("SNN_AUTOTUNE");
     if (cand.size() == 1 || (env && env[0] == '0')) return cand[0];
@@ -81,6 +83,7 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
     c.max_batch = batch;
     c.hbm_budget_bytes = 0;
     c.path = SNN_PATH_PLAIN;
+    c.precision = precision;
     snn_net *tmp = nullptr;
     int best = cand[0];
     if (snn_create(&c, stream, &tmp) == SNN_OK && tmp->p.jb == p.jb) {

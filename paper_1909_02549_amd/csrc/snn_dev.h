@@ -37,6 +37,7 @@ struct Params {
     int bits_stride;          // words per step of the per-sample input spikes
                               // (B * in_words rounded up to 4: 16-byte rows)
     int learn, adaptive, trace_add, reduce;
+    int prec;                 // operand form of the contractions (Prec)
     int uniform_rate;
     uint32_t thr_uniform;
     LifP exc, inh;

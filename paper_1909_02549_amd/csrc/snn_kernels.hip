@@ -13,6 +13,7 @@
 
 #include "snn_dev.h"
 #include "snn_kern.h"
+#include "snn_mfma.h"
 
 namespace snn {
 
@@ -90,7 +91,8 @@ __global__ void k_xpre(Params p, const uint32_t *__restrict__ bits_t, const floa
 }
 
 // Plain feed-forward contraction: I[b, j] = sum over inputs i that spiked in
-// sample b of W[i, j], summed in increasing i.  One thread per (b, j).
+// sample b of q(W[i, j]), summed in increasing i, q the operand form of the
+// precision (identity for FP32).  One thread per (b, j).
 __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t *__restrict__ bits_t,
                            float *__restrict__ I)
 {
@@ -114,7 +116,7 @@ __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t
         while (m) {
             const int i = 32 * w + __builtin_ctz(m);
             m &= m - 1;
-            acc += Wg[(size_t)i * p.jb];
+            acc += operand_value(p.prec, Wg[(size_t)i * p.jb]);
         }
     }
     I[ns] = acc;
@@ -155,7 +157,8 @@ __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__
 //   D[i, j] = R_b s_in[b, i] x_post[b, j]   (depression on a pre spike)
 //   W <- clamp(W + nu_post P - nu_pre D), column sums in FP64, W[:, j] *=
 //   norm / c_j; theta <- theta * beta + theta_plus * R_b s_exc[b, j].
-// R is sum, mean (sum / B) or max, applied to P and D separately.
+// R is sum, mean (sum / B) or max, applied to P and D separately; the traces
+// enter in the operand form of the precision (unrounded for FP32).
 __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W, double *__restrict__ theta,
                                                  const uint16_t *__restrict__ rf,
                                                  const float *__restrict__ x_post,
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
                 while (m) {
                     const int b = 32 * bw + __builtin_ctz(m);
                     m &= m - 1;
-                    D = reduce2(p.reduce, D, x_post[sbase + (size_t)b * p.jbp + jj]);
+                    D = reduce2(p.reduce, D, operand_value(p.prec, x_post[sbase + (size_t)b * p.jbp + jj]));
                 }
             }
             const uint32_t *sp = spk + jj * p.bwords;
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
                 while (m) {
                     const int b = 32 * bw + __builtin_ctz(m);
                     m &= m - 1;
-                    P = reduce2(p.reduce, P, x_pre[(size_t)b * p.n_in_pad + i]);
+                    P = reduce2(p.reduce, P, operand_value(p.prec, x_pre[(size_t)b * p.n_in_pad + i]));
                 }
             }
             const float w = stdp_apply(p, Wg[(size_t)i * JB + jj], P, D);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -27,7 +28,6 @@ struct snn_net {
 
     // shared parameters
     float *W = nullptr;          // FP32 master, block layout
-    void *Wq = nullptr;          // BF16 / FP8 contraction copy (MFMA path)
     double *theta = nullptr;     // n_pad, FP64
     uint32_t *thr_lut = nullptr; // 256 spike thresholds
 
@@ -72,11 +72,26 @@ struct snn_net {
     snn_status ensure_state(uint32_t B);
     void set_batch(uint32_t B);
     snn_status reset_state(const uint8_t *mask_dev);
-    snn_status refresh_weight_copies();
+    // captured episodic runs of the per-step paths (snn_graph.hip)
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        int last_path = 0;
+    };
+    static constexpr size_t kMaxGraphs = 16;
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, Graph> graphs;
     void graphs_invalidate();
+    snn_status episode(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch,
+                       uint32_t T, const snn::Outs &o);
+    snn_status episode_body(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                            uint32_t batch, uint32_t T, const snn::Outs &o);
+    snn_status run_graph(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                         uint32_t batch, uint32_t T, const snn::Outs &o);
     snn_status encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase, int steps,
                             const uint32_t *forced, uint32_t *raster_in, int raster_k0);
-    snn_status plain_step(int kk, int k, const snn::Outs &o);
+    snn_status plain_step(int kk, int k, const snn::Outs &o, bool mfma);
+    size_t mfma_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};
     snn_status xpre_first(const uint32_t *bits_t);
     bool fused_ok() const;
     size_t fused_attr_bytes = 64 * 1024;

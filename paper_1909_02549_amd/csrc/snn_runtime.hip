@@ -15,6 +15,7 @@
 #include "snn_dev.h"
 #include "snn_fused.h"
 #include "snn_kern.h"
+#include "snn_mfma.h"
 #include "snn_runtime.h"
 
 using namespace snn;
@@ -136,7 +137,7 @@ static snn_status validate(const snn_config *c)
         return fail(SNN_EINVAL, "refrac_steps must be in [0, 127]");
     if (c->reduce < 0 || c->reduce > 2) return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean) or 2 (max)");
     if (c->precision < 0 || c->precision > 2) return fail(SNN_EINVAL, "precision must be 0, 1 or 2");
-    if (c->path < 0 || c->path > 3) return fail(SNN_EINVAL, "path must be 0..3");
+    if (c->path < 0 || c->path > 4) return fail(SNN_EINVAL, "path must be 0..4");
     if (c->learn && (!(c->tau_pre_ms > 0) || !(c->tau_post_ms > 0)))
         return fail(SNN_EINVAL, "trace time constants must be > 0");
     if (c->learn && c->exc.adaptive && !(c->exc.tau_theta_ms > 0))
@@ -176,6 +177,7 @@ static void fill_params(Params &p, const snn_config &c)
     p.adaptive = c.exc.adaptive != 0;
     p.trace_add = c.trace_additive != 0;
     p.reduce = c.reduce;
+    p.prec = c.precision;
     p.uniform_rate = c.uniform_rate != 0;
     p.thr_uniform = rate_threshold(c, 0, true);
     p.w_ei = (float)c.w_ei;
@@ -253,6 +255,8 @@ snn_status snn_net::prof_flush()
 snn_net::~snn_net()
 {
     prof_flush();
+    graphs_invalidate();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto &e : evpool) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -267,7 +271,6 @@ snn_net::~snn_net()
     (void)hipFree(W);
     (void)hipFree(theta);
     (void)hipFree(thr_lut);
-    (void)hipFree(Wq);
 }
 
 void snn_net::free_state()
@@ -369,7 +372,7 @@ extern "C" snn_status snn_set_weights(snn_net *net, const float *w, size_t n)
         }
     HIP_TRY(hipStreamSynchronize(net->stream));
     HIP_TRY(hipMemcpy(net->W, blk.data(), blk.size() * sizeof(float), hipMemcpyHostToDevice));
-    return net->refresh_weight_copies();
+    return SNN_OK;
 }
 
 extern "C" snn_status snn_get_weights(snn_net *net, float *w, size_t n)
@@ -419,14 +422,11 @@ extern "C" snn_status snn_stdp_reduce(snn_net *net, int32_t mode)
 extern "C" snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
-    if (path < 0 || path > 3) return fail(SNN_EINVAL, "path must be 0..3");
+    if (path < 0 || path > 4) return fail(SNN_EINVAL, "path must be 0..4");
     if (precision < 0 || precision > 2) return fail(SNN_EINVAL, "precision must be 0..2");
     net->path = path;
-    if (precision != net->precision) {
-        net->precision = precision;
-        snn_status st = net->refresh_weight_copies();
-        if (st != SNN_OK) return st;
-    }
+    net->precision = precision;
+    net->p.prec = precision;
     net->graphs_invalidate();
     return SNN_OK;
 }
@@ -538,15 +538,6 @@ snn_status snn_net::reset_state(const uint8_t *mask_dev)
     return SNN_OK;
 }
 
-snn_status snn_net::refresh_weight_copies()
-{
-    // Contraction copies in BF16 / FP8 are derived from the FP32 master by the
-    // MFMA path when it is selected; nothing to do for FP32.
-    return SNN_OK;
-}
-
-void snn_net::graphs_invalidate() {}
-
 // ---------------------------------------------------------------------------
 // plain per-step path
 // ---------------------------------------------------------------------------
@@ -563,7 +554,7 @@ snn_status snn_net::encode_chunk(const uint8_t *img, const uint64_t *ids, const 
     return SNN_OK;
 }
 
-snn_status snn_net::plain_step(int kk, int k, const Outs &o)
+snn_status snn_net::plain_step(int kk, int k, const Outs &o, bool mfma)
 {
     const uint32_t *bits_t = bits + (size_t)kk * p.bits_stride;
     const uint32_t *bitsT_t = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
@@ -578,10 +569,40 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o)
     if (p.learn)
         SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, p, bits_t, xprev,
                    xcur);
-    SNN_LAUNCH("contract", k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)W, bits_t, I);
+    if (mfma) {
+        const dim3 grid((unsigned)p.nblk, (unsigned)((p.B + 127) / 128));
+        const size_t lds = mfma_contract_lds(p.prec);
+        if (p.prec == PREC_FP32)
+            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_FP32>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+        else if (p.prec == PREC_BF16)
+            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_BF16>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+        else
+            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_FP8>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+    } else {
+        SNN_LAUNCH("contract", k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)W, bits_t, I);
+    }
     SNN_LAUNCH("neuron", k_neuron, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)I, (const double *)theta,
                (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf, x_post, k, o);
-    if (p.learn) {
+    if (p.learn && mfma && mfma_plastic_fits(p, p.prec)) {
+        const size_t lds = mfma_plastic_lds(p, p.prec);
+        const void *fn = p.prec == PREC_FP32   ? (const void *)k_mfma_plastic<PREC_FP32>
+                         : p.prec == PREC_BF16 ? (const void *)k_mfma_plastic<PREC_BF16>
+                                               : (const void *)k_mfma_plastic<PREC_FP8>;
+        if (lds > mfma_attr_bytes[p.prec]) {
+            HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            mfma_attr_bytes[p.prec] = lds;
+        }
+        const dim3 grid((unsigned)p.nblk);
+        if (p.prec == PREC_FP32)
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP32>, grid, dim3(512), lds, p, W, theta,
+                       (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
+        else if (p.prec == PREC_BF16)
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_BF16>, grid, dim3(512), lds, p, W, theta,
+                       (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
+        else
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP8>, grid, dim3(512), lds, p, W, theta,
+                       (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
+    } else if (p.learn) {
         const int R = 256 / p.jb;
         const size_t sm = align16((size_t)p.jb * p.bwords * 4) + (size_t)(R * p.jb + p.jb) * 8;
         SNN_LAUNCH("plastic", k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, p, W, theta, (const uint16_t *)rf,
@@ -606,13 +627,6 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     }
     snn_status st = ensure_state(batch);
     if (st != SNN_OK) return st;
-    const bool new_batch = batch != cur_B;
-    set_batch(batch);
-    if (new_batch || (flags & SNN_RUN_RESET)) {
-        st = reset_state(nullptr);
-        if (st != SNN_OK) return st;
-        cur_B = batch;
-    }
     Outs o{};
     if (out) {
         o.counts = out->counts;
@@ -622,6 +636,34 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
         o.v_exc = out->v_exc;
         o.v_inh = out->v_inh;
     }
+    const bool reset = batch != cur_B || (flags & SNN_RUN_RESET);
+    set_batch(batch);
+    const int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T, images, ids, forced) : this->path;
+    set_batch(batch);
+    if (reset && use_graphs && !prof && path != SNN_PATH_PERSISTENT)
+        return run_graph(path, images, ids, forced, batch, T, o);
+    if (reset) {
+        st = reset_state(nullptr);
+        if (st != SNN_OK) return st;
+        cur_B = batch;
+    }
+    return episode_body(path, images, ids, forced, batch, T, o);
+}
+
+// One episode from a reset state: reset, clear the outputs, run T steps.
+snn_status snn_net::episode(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                            uint32_t batch, uint32_t T, const Outs &o)
+{
+    snn_status st = reset_state(nullptr);
+    if (st != SNN_OK) return st;
+    cur_B = batch;
+    return episode_body(path, images, ids, forced, batch, T, o);
+}
+
+// Clear the outputs of a run, then T steps on `path`.
+snn_status snn_net::episode_body(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                                 uint32_t batch, uint32_t T, const Outs &o)
+{
     const int words = (p.n_exc + 31) / 32;
     auto zero = [&](uint32_t *ptr, size_t n) {
         if (!ptr) return;
@@ -632,8 +674,6 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     zero(o.raster_exc, (size_t)T * batch * words);
     zero(o.raster_inh, (size_t)T * batch * words);
     HIP_TRY(hipGetLastError());
-
-    int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T, images, ids, forced) : this->path;
     return run_steps(path, images, ids, forced, T, o);
 }
 
@@ -763,8 +803,12 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
+    // the step kernels compute in the FP32 form only; the reduced forms run
+    // on the matrix-core route
+    if ((path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT) && p.prec != PREC_FP32) path = SNN_PATH_MFMA;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
+    if (path == SNN_PATH_MFMA && p.jb > 32) path = SNN_PATH_PLAIN;
     last_path = path;
     for (uint32_t k0 = 0; k0 < T; k0 += chunk) {
         const int steps = (int)std::min<uint32_t>(chunk, T - k0);
@@ -795,7 +839,7 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
             }
         } else {
             for (int kk = 0; kk < steps; ++kk) {
-                st = plain_step(kk, (int)k0 + kk, o);
+                st = plain_step(kk, (int)k0 + kk, o, path == SNN_PATH_MFMA);
                 if (st != SNN_OK) return st;
             }
         }

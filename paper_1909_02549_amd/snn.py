@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SNN_ABI_VERSION = 1
 SNN_RUN_RESET = 1
-PATHS = {"plain": 0, "fused": 1, "persistent": 2, "auto": 3}
+PATHS = {"plain": 0, "fused": 1, "persistent": 2, "auto": 3, "mfma": 4}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 REDUCES = {"sum": 0, "mean": 1, "max": 2}
 STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4: "SNN_EAGAIN",
@@ -26,7 +26,7 @@ STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4
 
 EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "snn_set_stream",
             "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce",
-            "snn_set_path", "snn_last_path", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
+            "snn_set_path", "snn_last_path", "snn_set_graphs", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
             "snn_serve_destroy"]
@@ -87,6 +87,7 @@ def load_library():
         "snn_stdp_reduce": ([VP, I32], I32),
         "snn_set_path": ([VP, I32, I32], I32),
         "snn_last_path": ([VP, P(I32)], I32),
+        "snn_set_graphs": ([VP, I32], I32),
         "snn_run": ([VP, VP, VP, U32, U32, U32, P(snn_outputs)], I32),
         "snn_run_spikes": ([VP, VP, U32, U32, U32, P(snn_outputs)], I32),
         "snn_sync": ([VP], I32),
@@ -204,6 +205,9 @@ class Net:
     def snn_set_path(self, path="plain", precision="fp32"):
         _check(self.lib.snn_set_path(self.h, PATHS[path] if isinstance(path, str) else int(path),
                                      PRECISIONS[precision] if isinstance(precision, str) else int(precision)))
+
+    def snn_set_graphs(self, on: bool = True):
+        _check(self.lib.snn_set_graphs(self.h, 1 if on else 0))
 
     def snn_last_path(self) -> str:
         v = C.c_int32()

@@ -37,10 +37,13 @@ def to_dev(torch, a, dtype=None):
 
 
 def run_both(torch, oracle_mod, cfg, W, imgs, ids, T, path="plain", record=("in", "exc", "inh", "v_exc", "counts"),
-             reduce=None, forced=None):
+             reduce=None, forced=None, precision="fp32", oracle_precision=None):
+    """Run the HIP path and the oracle on the same inputs.  The oracle takes
+    the same operand form as the GPU unless ``oracle_precision`` says
+    otherwise.  Returns (gpu, oracle, path the GPU ran)."""
     from paper_1909_02549_amd.snn import Net, pack_bits, unpack_bits
     B = len(ids)
-    net = Net(cfg, max_batch=B, path=path)
+    net = Net(cfg, max_batch=B, path=path, precision=precision)
     net.snn_set_weights(W)
     if forced is not None:
         bits = pack_bits(forced.transpose(1, 0, 2))  # T, B, words
@@ -63,8 +66,10 @@ def run_both(torch, oracle_mod, cfg, W, imgs, ids, T, path="plain", record=("in"
             g[k] = a.astype(np.int64)
     g["W"] = net.snn_get_weights()
     g["theta"] = net.snn_get_theta()
+    g["path"] = net.snn_last_path()
     net.close()
-    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
+    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64),
+                               precision=precision if oracle_precision is None else oracle_precision)
     ref = orc.run(imgs, ids, T, forced_in=forced, record=tuple(record))
     ref["W"] = orc.W
     ref["theta"] = orc.theta
@@ -102,7 +107,7 @@ def check_parity(g, ref, learn=True):
     return t_div
 
 
-PATHS = ["plain", "fused", "persistent"]
+PATHS = ["plain", "fused", "persistent", "mfma"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -116,6 +121,7 @@ def test_dc100_learning_parity(torch_cuda, oracle_mod, path):
     assert ref["exc"].sum() > 50
     t_div = check_parity(g, ref)
     assert np.array_equal(g["counts"], ref["counts"].astype(np.int64)) or t_div < 100
+    assert g["path"] == path
 
 
 @pytest.mark.parametrize("path", PATHS)
