@@ -74,8 +74,8 @@ def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: float = 1.0):
         return B * N * 4 + spikes
     if kernel == "xpre":
         return 2 * xpre + spikes
-    if kernel == "mfma_contract":
-        return w + B * N * 4 + B * d["in_words"] * 4
+    if kernel == "mfma_front":
+        return w + 2 * st + 2 * xpre + B * d["in_words"] * 4
     if kernel == "mfma_plastic":
         return 2 * w + B * N * (4 + 2) + B * n_in_pad * 4 + n_in_pad * d["bwords"] * 4
     if kernel == "encode":
@@ -94,7 +94,7 @@ def algorithmic_flops(kernel: str, d: dict):
     synaptic current B x n_in x N, the STDP terms P and D as two outer
     products over the batch (the potentiation K is compacted to the samples
     that fired, so fewer products actually run)."""
-    if kernel == "mfma_contract":
+    if kernel == "mfma_front":
         return 2.0 * d["B"] * d["n_in"] * d["n_exc"]
     if kernel == "mfma_plastic":
         return 4.0 * d["B"] * d["n_in"] * d["n_exc"]

@@ -1,15 +1,16 @@
 // snn_autotune.hip -- choice of the execution path for SNN_PATH_AUTO.
 //
-// The candidates are the paths whose kernels fit the batch (persistent:
-// cooperative launch with every task's state in registers; fused: the weight
-// block and post traces fit in LDS; plain: always).  The first AUTO run of a
-// given network shape and batch size times each candidate on a scratch copy
-// of the network (same weights, thresholds and inputs, so the spike activity
-// is representative) for a short warm-up and a timed run, keeps the fastest
-// in a process-wide table, and appends it to the file named by
-// SNN_AUTOTUNE_CACHE if set (lines "key path").  SNN_AUTOTUNE=0 skips the
-// measurement and takes the first available path in the order persistent,
-// fused, plain.
+// The candidates are the paths whose kernels fit the batch and precision
+// (persistent: cooperative launch with every task's state in registers;
+// fused: the weight block and post traces fit in LDS; both FP32 only;
+// MFMA: matrix-core current and STDP; plain: always).  The first AUTO run of
+// a given network shape, batch size and precision times each candidate on a
+// scratch copy of the network (same weights, thresholds and inputs, so the
+// spike activity is representative) for a short warm-up and one timed
+// episode, keeps the fastest in a process-wide table, and appends it to the
+// file named by SNN_AUTOTUNE_CACHE if set (lines "key path").
+// SNN_AUTOTUNE=0 skips the measurement and takes the first available path in
+// the order persistent, fused, MFMA, plain.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -67,7 +68,8 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
 
     std::ostringstream ks;
     ks << cfg.n_in << 'x' << cfg.n_exc << 'x' << cfg.n_inh << "_l" << cfg.learn << "_r" << cfg.reduce << "_p"
-       << precision << "_jb" << p.jb << "_B" << batch << "_cu" << cus;
+       << precision << "_jb" << p.jb << "_B" << batch << "_T" << (T < 512u ? T : 512u) << "_g" << use_graphs
+       << "_cu" << cus;
     const std::string key = ks.str();
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -87,24 +89,28 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
     snn_net *tmp = nullptr;
     int best = cand[0];
     if (snn_create(&c, stream, &tmp) == SNN_OK && tmp->p.jb == p.jb) {
+        tmp->use_graphs = use_graphs;
         const size_t nw = (size_t)p.n_in_pad * p.n_pad;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool ok = hipMemcpyAsync(tmp->W, W, nw * sizeof(float), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
                   hipMemcpyAsync(tmp->theta, theta, (size_t)p.n_pad * sizeof(double), hipMemcpyDeviceToDevice,
                                  stream) == hipSuccess &&
                   hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-        // the first steps of an episode are not representative (the whole
-        // layer charges up and fires together): run into the episode, then
-        // time a stretch of it
-        const uint32_t lead = T < 32u ? T : 32u;
-        const uint32_t steps = T < 64u ? T : 64u;
+        // a short warm-up (code loading, LDS limits), then one episode of
+        // the requested length (at most 512 steps) from a reset, so the
+        // bursty first steps weigh as much as they will in the real run
+        const uint32_t warm = T < 8u ? T : 8u;
+        const uint32_t steps = T < 512u ? T : 512u;
         float best_ms = 1e30f;
         for (int cnd : cand) {
             if (!ok) break;
             tmp->path = cnd;
-            if (tmp->run(images, ids, forced, batch, lead, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
+            if (tmp->run(images, ids, forced, batch, warm, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
+            // with graph replay on, the timed episode replays a captured graph
+            if (tmp->use_graphs && tmp->run(images, ids, forced, batch, steps, SNN_RUN_RESET, nullptr) != SNN_OK)
+                continue;
             if (hipEventRecord(e0, stream) != hipSuccess) break;
-            if (tmp->run(images, ids, forced, batch, steps, forced ? SNN_RUN_RESET : 0u, nullptr) != SNN_OK) continue;
+            if (tmp->run(images, ids, forced, batch, steps, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
             float ms = 0.f;
             if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)

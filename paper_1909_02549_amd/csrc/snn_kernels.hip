@@ -122,34 +122,85 @@ __global__ void k_contract(Params p, const float *__restrict__ W, const uint32_t
     I[ns] = acc;
 }
 
-// Plain neuron update, one thread per (b, j): recurrent currents, both
+// Per-step neuron update, one thread per group of 8 consecutive neurons of
+// one sample (16-byte state loads and stores): recurrent currents, both
 // layers, post trace, spike outputs.
 __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__restrict__ theta,
                          const uint32_t *__restrict__ Cprev, uint32_t *__restrict__ Ccur,
                          uint32_t *__restrict__ Cnext, float *__restrict__ v_exc, float *__restrict__ v_inh,
                          uint16_t *__restrict__ rf, float *__restrict__ x_post, int k, Outs o)
 {
+    const int ncg = p.jbp >> 3;
     const size_t tix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)p.nblk * p.B * p.jbp;
-    if (tix >= total) return;
-    const int jj = (int)(tix % p.jbp);
-    const size_t gb = tix / p.jbp;
+    if (tix >= (size_t)p.nblk * p.B * ncg) return;
+    const int cg = (int)(tix % ncg);
+    const size_t gb = tix / ncg;
     const int b = (int)(gb % p.B);
     const int g = (int)(gb / p.B);
-    const int j = g * p.jb + jj;
-    if (j == 0 && Cnext) Cnext[b] = 0u;
-    if (jj >= p.jb || j >= p.n_exc) return;
-    const size_t n = ((size_t)g * p.Bs + b) * p.jbp + jj;
-    NeuronState st{v_exc[n], p.has_inh ? v_inh[n] : 0.f, (uint32_t)rf[n], p.learn ? x_post[n] : 0.f};
-    const float th_off = theta_offset(p, theta[j]);
-    bool se, si;
-    neuron_update(p, I[n], p.has_inh ? Cprev[b] : 0u, th_off, st, se, si);
-    v_exc[n] = st.ve;
-    if (p.has_inh) v_inh[n] = st.vi;
-    rf[n] = (uint16_t)st.rf;
-    if (p.learn) x_post[n] = st.xpost;
-    if (si) atomicAdd(&Ccur[b], 1u);
-    write_outputs(p, o, k, b, j, se, si, st.ve, st.vi);
+    const int c0 = 8 * cg, j0 = g * p.jb + c0;
+    if (j0 == 0 && Cnext) Cnext[b] = 0u;
+    const int nv = max(0, min(8, min(p.jb - c0, p.n_exc - j0)));
+    if (nv == 0) return;
+    const size_t n0 = ((size_t)g * p.Bs + b) * p.jbp + c0;
+    float ve[8], vi[8], xp[8], cur[8];
+    uint32_t rw[4];
+    {
+        const float4 a0 = *reinterpret_cast<const float4 *>(v_exc + n0);
+        const float4 a1 = *reinterpret_cast<const float4 *>(v_exc + n0 + 4);
+        ve[0] = a0.x, ve[1] = a0.y, ve[2] = a0.z, ve[3] = a0.w, ve[4] = a1.x, ve[5] = a1.y, ve[6] = a1.z, ve[7] = a1.w;
+        const float4 i0 = *reinterpret_cast<const float4 *>(I + n0);
+        const float4 i1 = *reinterpret_cast<const float4 *>(I + n0 + 4);
+        cur[0] = i0.x, cur[1] = i0.y, cur[2] = i0.z, cur[3] = i0.w;
+        cur[4] = i1.x, cur[5] = i1.y, cur[6] = i1.z, cur[7] = i1.w;
+        const uint4 r = *reinterpret_cast<const uint4 *>(rf + n0);
+        rw[0] = r.x, rw[1] = r.y, rw[2] = r.z, rw[3] = r.w;
+    }
+    if (p.has_inh) {
+        const float4 a0 = *reinterpret_cast<const float4 *>(v_inh + n0);
+        const float4 a1 = *reinterpret_cast<const float4 *>(v_inh + n0 + 4);
+        vi[0] = a0.x, vi[1] = a0.y, vi[2] = a0.z, vi[3] = a0.w, vi[4] = a1.x, vi[5] = a1.y, vi[6] = a1.z, vi[7] = a1.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) vi[c] = 0.f;
+    }
+    if (p.learn) {
+        const float4 a0 = *reinterpret_cast<const float4 *>(x_post + n0);
+        const float4 a1 = *reinterpret_cast<const float4 *>(x_post + n0 + 4);
+        xp[0] = a0.x, xp[1] = a0.y, xp[2] = a0.z, xp[3] = a0.w, xp[4] = a1.x, xp[5] = a1.y, xp[6] = a1.z, xp[7] = a1.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xp[c] = 0.f;
+    }
+    const uint32_t cp = p.has_inh ? Cprev[b] : 0u;
+    uint32_t se_m = 0u, si_m = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (c < nv) {
+            const uint32_t r16 = (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
+            NeuronState st{ve[c], vi[c], r16, xp[c]};
+            bool se, si;
+            neuron_update(p, cur[c], cp, theta_offset(p, theta[j0 + c]), st, se, si);
+            ve[c] = st.ve;
+            vi[c] = st.vi;
+            xp[c] = st.xpost;
+            rw[c >> 1] = (rw[c >> 1] & ~(0xFFFFu << (16 * (c & 1)))) | (st.rf << (16 * (c & 1)));
+            se_m |= (se ? 1u : 0u) << c;
+            si_m |= (si ? 1u : 0u) << c;
+        }
+    }
+    *reinterpret_cast<float4 *>(v_exc + n0) = make_float4(ve[0], ve[1], ve[2], ve[3]);
+    *reinterpret_cast<float4 *>(v_exc + n0 + 4) = make_float4(ve[4], ve[5], ve[6], ve[7]);
+    if (p.has_inh) {
+        *reinterpret_cast<float4 *>(v_inh + n0) = make_float4(vi[0], vi[1], vi[2], vi[3]);
+        *reinterpret_cast<float4 *>(v_inh + n0 + 4) = make_float4(vi[4], vi[5], vi[6], vi[7]);
+    }
+    if (p.learn) {
+        *reinterpret_cast<float4 *>(x_post + n0) = make_float4(xp[0], xp[1], xp[2], xp[3]);
+        *reinterpret_cast<float4 *>(x_post + n0 + 4) = make_float4(xp[4], xp[5], xp[6], xp[7]);
+    }
+    *reinterpret_cast<uint4 *>(rf + n0) = make_uint4(rw[0], rw[1], rw[2], rw[3]);
+    if (si_m) atomicAdd(&Ccur[b], (uint32_t)__builtin_popcount(si_m));
+    write_outputs8(p, o, k, b, j0, nv, se_m, si_m, ve, vi);
 }
 
 // Plain plasticity, one workgroup per column block:

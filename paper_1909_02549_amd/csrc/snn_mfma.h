@@ -50,13 +50,27 @@ __device__ __forceinline__ float operand_value(int prec, float x)
     return x;
 }
 
-size_t mfma_contract_lds(int prec);
+// Arguments of one step's front-half launch (traces, current, neurons).
+struct FrontArgs {
+    const float *W;
+    const double *theta;
+    const uint32_t *bits;   // this step's input spikes, per sample
+    const float *xprev;     // x_pre(t-1)
+    float *xcur;            // x_pre(t)
+    const uint32_t *Cprev;  // inhibitory spike counts of step t-1
+    uint32_t *Ccur, *Cnext;
+    float *v_exc, *v_inh, *x_post;
+    uint16_t *rf;
+    int k;                  // step index within the call (outputs)
+    Outs o;
+};
+
+size_t mfma_front_lds(const Params &p, int prec);
 size_t mfma_plastic_lds(const Params &p, int prec);
 bool mfma_plastic_fits(const Params &p, int prec);
 
 template <int PREC>
-__global__ void k_mfma_contract(Params p, const float *__restrict__ W, const uint32_t *__restrict__ bits_t,
-                                float *__restrict__ I);
+__global__ void k_mfma_front(Params p, FrontArgs a);
 template <int PREC>
 __global__ void k_mfma_plastic(Params p, float *__restrict__ W, double *__restrict__ theta,
                                const uint16_t *__restrict__ rf, const float *__restrict__ x_post,

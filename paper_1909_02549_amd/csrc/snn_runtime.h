@@ -91,7 +91,8 @@ struct snn_net {
     snn_status encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase, int steps,
                             const uint32_t *forced, uint32_t *raster_in, int raster_k0);
     snn_status plain_step(int kk, int k, const snn::Outs &o, bool mfma);
-    size_t mfma_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};
+    size_t mfma_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};    // STDP kernel, per precision
+    size_t mfma_c_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};  // current kernel, per precision
     snn_status xpre_first(const uint32_t *bits_t);
     bool fused_ok() const;
     size_t fused_attr_bytes = 64 * 1024;

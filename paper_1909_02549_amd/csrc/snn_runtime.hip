@@ -566,23 +566,33 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o, bool mfma)
     uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
     const size_t ns = (size_t)p.nblk * p.jbp * p.B;
     const int tpb = 256;
-    if (p.learn)
-        SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, p, bits_t, xprev,
-                   xcur);
-    if (mfma) {
-        const dim3 grid((unsigned)p.nblk, (unsigned)((p.B + 127) / 128));
-        const size_t lds = mfma_contract_lds(p.prec);
+    const size_t clds = mfma ? mfma_front_lds(p, p.prec) : 0;
+    if (mfma && clds <= kMaxLds) {
+        // traces, synaptic current on the matrix cores and neurons in one launch
+        const void *fn = p.prec == PREC_FP32   ? (const void *)k_mfma_front<PREC_FP32>
+                         : p.prec == PREC_BF16 ? (const void *)k_mfma_front<PREC_BF16>
+                                               : (const void *)k_mfma_front<PREC_FP8>;
+        if (clds > mfma_c_attr_bytes[p.prec]) {
+            HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
+            mfma_c_attr_bytes[p.prec] = clds;
+        }
+        FrontArgs fa{W, theta, bits_t, xprev, xcur, Cprev, Ccur, Cnext, v_exc, v_inh, x_post, rf, k, o};
+        const dim3 grid((unsigned)p.nblk);
         if (p.prec == PREC_FP32)
-            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_FP32>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+            SNN_LAUNCH("mfma_front", k_mfma_front<PREC_FP32>, grid, dim3(512), clds, p, fa);
         else if (p.prec == PREC_BF16)
-            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_BF16>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+            SNN_LAUNCH("mfma_front", k_mfma_front<PREC_BF16>, grid, dim3(512), clds, p, fa);
         else
-            SNN_LAUNCH("mfma_contract", k_mfma_contract<PREC_FP8>, grid, dim3(256), lds, p, (const float *)W, bits_t, I);
+            SNN_LAUNCH("mfma_front", k_mfma_front<PREC_FP8>, grid, dim3(512), clds, p, fa);
     } else {
+        if (p.learn)
+            SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, tpb)), dim3(tpb), 0, p, bits_t,
+                       xprev, xcur);
         SNN_LAUNCH("contract", k_contract, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)W, bits_t, I);
+        SNN_LAUNCH("neuron", k_neuron, dim3(blocks_for((size_t)p.nblk * p.B * (p.jbp / 8), tpb)), dim3(tpb), 0, p,
+                   (const float *)I, (const double *)theta, (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf,
+                   x_post, k, o);
     }
-    SNN_LAUNCH("neuron", k_neuron, dim3(blocks_for(ns, tpb)), dim3(tpb), 0, p, (const float *)I, (const double *)theta,
-               (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf, x_post, k, o);
     if (p.learn && mfma && mfma_plastic_fits(p, p.prec)) {
         const size_t lds = mfma_plastic_lds(p, p.prec);
         const void *fn = p.prec == PREC_FP32   ? (const void *)k_mfma_plastic<PREC_FP32>
@@ -791,7 +801,16 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
     }
     Outs o{};
     o.counts = counts;
-    int path = this->path == SNN_PATH_AUTO ? choose_path(B, steps, images, ids, nullptr) : this->path;
+    // the active width changes with every admission: tune per power-of-two
+    // width (at most log2(capacity) measurements, on the slot buffers, which
+    // hold capacity entries)
+    int path = this->path;
+    if (path == SNN_PATH_AUTO) {
+        uint32_t Bk = 1;
+        while (Bk < B) Bk <<= 1;
+        path = choose_path(std::min(Bk, cap_B), steps, images, ids, nullptr);
+        set_batch(B);
+    }
     snn_status st = run_steps(path, images, ids, nullptr, steps, o, tl_dev);
     if (st != SNN_OK) return st;
     SNN_LAUNCH("slot_step", k_add_u32, dim3((B + 255) / 256), dim3(256), 0, const_cast<uint32_t *>(tl_dev), steps,

@@ -53,16 +53,17 @@ def test_bf16_against_unrounded_oracle(torch_cuda, oracle_mod):
         assert agree >= 0.99, f"{k} raster agreement {agree}"
 
 
-@pytest.mark.parametrize("B", [300, 600])
-def test_mfma_route_large_batch(torch_cuda, oracle_mod, B):
-    """B = 300: the STDP matrix kernel with 19 sample steps and a ragged
-    tail; B = 600 in the FP32 form exceeds its LDS plan, so the route keeps
-    the gather plasticity kernel.  Both against the FP32 oracle."""
+@pytest.mark.parametrize("B,precision", [(200, "fp32"), (300, "bf16"), (600, "fp32")])
+def test_mfma_route_large_batch(torch_cuda, oracle_mod, B, precision):
+    """B = 200 and 300: the STDP matrix kernel with a ragged sample tail
+    (13 and 19 sample steps) and the front kernel over two sample rounds
+    (300); B = 600 in the FP32 form exceeds the STDP kernel's LDS plan, so
+    the route keeps the gather plasticity kernel."""
     cfg = dc_config(20)
     imgs = stroke_images(B, 70, 0.19)
     W = uniform_weights(784, 20, 0.0, 0.3, 14)
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(B, 900), 30, path="mfma",
-                      record=("in", "exc", "inh", "v_exc", "counts"))
+                      precision=precision, record=("in", "exc", "inh", "v_exc", "counts"))
     assert g["path"] == "mfma"
     check_parity(g, ref)
 
