@@ -62,8 +62,7 @@ typedef enum { SNN_REDUCE_SUM = 0, SNN_REDUCE_MEAN = 1, SNN_REDUCE_MAX = 2 } snn
  *   SNN_BF16      rounded to bfloat16, nearest even,
  *   SNN_FP8_E4M3  rounded to OCP FP8 E4M3, nearest even (saturating at 448),
  * each from its FP32 value.  Sums accumulate in FP32; the master weights stay
- * FP32, theta and the column sums FP64.  The reduced forms run on the PLAIN
- * and MFMA paths; a FUSED or PERSISTENT request with them runs MFMA. */
+ * FP32, theta and the column sums FP64.  Every path computes every form. */
 typedef enum { SNN_FP32 = 0, SNN_BF16 = 1, SNN_FP8_E4M3 = 2 } snn_precision;
 
 /* How the T-step loop is executed.

@@ -1,9 +1,9 @@
 // snn_autotune.hip -- choice of the execution path for SNN_PATH_AUTO.
 //
-// The candidates are the paths whose kernels fit the batch and precision
-// (persistent: cooperative launch with every task's state in registers;
-// fused: the weight block and post traces fit in LDS; both FP32 only;
-// MFMA: matrix-core current and STDP; plain: always).  The first AUTO run of
+// The candidates are the paths whose kernels fit the batch (persistent:
+// cooperative launch with every task's state in registers; fused: the
+// weight block and post traces fit in LDS; MFMA: matrix-core current and
+// STDP; plain: always).  The first AUTO run of
 // a given network shape, batch size and precision times each candidate on a
 // scratch copy of the network (same weights, thresholds and inputs, so the
 // spike activity is representative) for a short warm-up and one timed
@@ -58,9 +58,8 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
                          const uint32_t *forced)
 {
     std::vector<int> cand;
-    // the step kernels compute in the FP32 form only
-    if (p.prec == 0 && persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
-    if (p.prec == 0 && fused_ok()) cand.push_back(SNN_PATH_FUSED);
+    if (persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
+    if (fused_ok()) cand.push_back(SNN_PATH_FUSED);
     cand.push_back(SNN_PATH_MFMA);
     cand.push_back(SNN_PATH_PLAIN);
     const char *env = std::getenv("SNN_AUTOTUNE");

@@ -28,7 +28,8 @@ struct LifP {
 struct Params {
     int n_in, n_in_pad, in_words;
     int n_exc, n_pad, jb, nblk;
-    int jbp;                  // jb rounded up to a multiple of 8 (LDS rows)
+    int jbp;                  // jb rounded up to a multiple of 8 (state rows)
+    int ls;                   // LDS row stride of a column block (jbp, + 4 at 16 / 32)
     int lt_stride;            // entries per per-input sample list (B rounded to 8)
     int has_inh;
     int B, bwords;            // batch, ceil(B / 32)

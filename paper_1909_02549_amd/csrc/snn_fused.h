@@ -7,7 +7,9 @@
 // columns is small: the per-sample inhibitory spike count C[b] (all-but-self
 // inhibition) and the presynaptic traces x_pre (read by every column).
 //
-// In LDS the weight block and the post traces are stored with JBP = JB
+// In LDS the weight block and the post traces are stored with row stride
+// p.ls (JBP, or JBP + 4 when JBP is 16 or 32 so that rows read by
+// different lanes start on different banks); JBP = JB
 // rounded up to 8 columns per row plus one all-zero row, so a thread owning 8
 // consecutive columns reads a row with two 16-byte loads, and the padding
 // slots of an index list point at the zero row (adding +0 changes no sum).
@@ -22,6 +24,7 @@
 
 #include "snn_dev.h"
 #include "snn_kern.h"
+#include "snn_mfma.h"
 
 namespace snn {
 
@@ -86,7 +89,9 @@ struct PersistArgs {
 
 size_t fused_lds_bytes(const Params &p);
 size_t persist_lds_bytes(const Params &p);
+template <int PREC>
 __global__ void k_fused_step(Params p, FusedArgs a, StepPtrs s);
+template <int PREC>
 __global__ void k_persist(const PersistArgs *args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
@@ -125,13 +130,15 @@ __device__ __forceinline__ void st_x(T *ptr, T v)
 // LDS carve-up shared by host (size) and device (offsets).
 struct FusedLds {
     size_t w, xpost, cprev, cinh, spk, colmask, ulist, part, scale, theta, theta64, total;
-    __host__ __device__ FusedLds(const Params &p, int nthreads)
+    // share_part: the column-sum partials reuse the post-trace rows (the
+    // fused kernel, whose post traces are dead by then)
+    __host__ __device__ FusedLds(const Params &p, int nthreads, bool share_part = false)
     {
         size_t o = 0;
         w = o;
-        o += align16((size_t)(p.n_in_pad + 1) * p.jbp * 4);
+        o += align16((size_t)(p.n_in_pad + 1) * p.ls * 4);
         xpost = o;
-        o += p.learn ? align16((size_t)(p.B + 1) * p.jbp * 4) : 0;
+        o += p.learn ? align16((size_t)(p.B + 1) * p.ls * 4) : 0;
         cprev = o;
         o += align16((size_t)p.B * 4);
         cinh = o;
@@ -142,8 +149,13 @@ struct FusedLds {
         o += align16((size_t)p.B * 4);
         ulist = o;
         o += align16((size_t)(p.B + 1) * 4);
-        part = o;
-        o += align16((size_t)(nthreads / 32) * 32 * 8);
+        const size_t part_bytes = (size_t)(nthreads / 32) * 32 * 8;
+        if (share_part && p.learn && (size_t)(p.B + 1) * p.ls * 4 >= part_bytes) {
+            part = xpost;
+        } else {
+            part = o;
+            o += align16(part_bytes);
+        }
         scale = o;
         o += 32 * 8;
         theta = o;
@@ -187,8 +199,16 @@ __device__ __forceinline__ void red4(int mode, float *acc, const float4 v)
 }
 
 // Four list entries (two u32 words of u16 indices) -> acc[0..8) R= rows.
+// Operand rounding of the reduced-precision forms on four loaded values.
+__device__ __forceinline__ float4 round4(int prec, float4 v)
+{
+    if (!prec) return v;
+    return make_float4(operand_value(prec, v.x), operand_value(prec, v.y), operand_value(prec, v.z),
+                       operand_value(prec, v.w));
+}
+
 __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const float *rows, int jbp, int c0, int zero_row,
-                                            int mode, float *acc)
+                                            int mode, float *acc, int prec)
 {
     const int i0 = (int)(q.x & 0xFFFFu);
     const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
@@ -198,8 +218,10 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
     const float4 *r1 = reinterpret_cast<const float4 *>(rows + i1 * jbp + c0);
     const float4 *r2 = reinterpret_cast<const float4 *>(rows + i2 * jbp + c0);
     const float4 *r3 = reinterpret_cast<const float4 *>(rows + i3 * jbp + c0);
-    const float4 a0 = r0[0], b0 = r0[1], a1 = r1[0], b1 = r1[1];
-    const float4 a2 = r2[0], b2 = r2[1], a3 = r3[0], b3 = r3[1];
+    const float4 a0 = round4(prec, r0[0]), b0 = round4(prec, r0[1]);
+    const float4 a1 = round4(prec, r1[0]), b1 = round4(prec, r1[1]);
+    const float4 a2 = round4(prec, r2[0]), b2 = round4(prec, r2[1]);
+    const float4 a3 = round4(prec, r3[0]), b3 = round4(prec, r3[1]);
     if (mode == RED_MAX) {
         red4(mode, acc, a0), red4(mode, acc + 4, b0);
         red4(mode, acc, a1), red4(mode, acc + 4, b1);
@@ -214,20 +236,21 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
 }
 
 // acc[0..8) = R over the first `cnt` entries of `list` (u16 row indices, in
-// list order) of rows[idx * jbp + c0 .. + 8), four rows in flight at a time;
+// list order) of q(rows[idx * jbp + c0 .. + 8)), four rows in flight at a
+// time, q the operand rounding of the precision `prec` (none for FP32);
 // slots past cnt read row `zero_row` (all zeros).  The first `nhead` (4 or
 // 8) entries are passed in registers (head0, head1), loaded ahead of time.
 __device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int cnt, uint2 head0, uint2 head1,
                                         int nhead, const float *rows, int jbp, int c0, int zero_row, int mode,
-                                        float *acc)
+                                        float *acc, int prec)
 {
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    if (cnt <= 0) return;
     const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
-    for (int k0 = 0; k0 < cnt; k0 += 4) {
-        const uint2 q = k0 == 0 ? head0 : (k0 == 4 && nhead == 8) ? head1 : l4[k0 >> 2];
-        gather4rows(q, k0, cnt, rows, jbp, c0, zero_row, mode, acc);
-    }
+    gather4rows(head0, 0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    if (cnt > 4) gather4rows(nhead == 8 ? head1 : l4[1], 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    for (int k0 = 8; k0 < cnt; k0 += 4) gather4rows(l4[k0 >> 2], k0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
 }
 
 // Step phase A: C(t-1) and per-step scratch in LDS, threshold offsets.
@@ -253,8 +276,8 @@ __device__ __forceinline__ void neuron_task(const Params &p, const StepLds &S, c
 {
     float xp[8];
     if (p.learn) {
-        const float4 x0 = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0);
-        const float4 x1 = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0 + 4);
+        const float4 x0 = *reinterpret_cast<const float4 *>(S.xpost + b * p.ls + c0);
+        const float4 x1 = *reinterpret_cast<const float4 *>(S.xpost + b * p.ls + c0 + 4);
         xp[0] = x0.x, xp[1] = x0.y, xp[2] = x0.z, xp[3] = x0.w;
         xp[4] = x1.x, xp[5] = x1.y, xp[6] = x1.z, xp[7] = x1.w;
     } else {
@@ -285,8 +308,8 @@ __device__ __forceinline__ void neuron_task(const Params &p, const StepLds &S, c
         }
     }
     if (p.learn) {
-        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0) = make_float4(xp[0], xp[1], xp[2], xp[3]);
-        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0 + 4) = make_float4(xp[4], xp[5], xp[6], xp[7]);
+        *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0) = make_float4(xp[0], xp[1], xp[2], xp[3]);
+        *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0 + 4) = make_float4(xp[4], xp[5], xp[6], xp[7]);
         if (cm) atomicOr(&S.colmask[b], cm);
     }
     if (si_m) atomicAdd(&S.cinh[b], (uint32_t)__builtin_popcount(si_m));
@@ -326,7 +349,8 @@ __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, 
 // registers (all in flight together) and reused by every column group.
 template <bool Coherent, int XR>
 __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S, int i, int cnt, uint2 head,
-                                               const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany)
+                                               const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
+                                               int prec, int prec_d)
 {
     const int ncg = p.jbp >> 3;
     float x[XR];
@@ -338,7 +362,88 @@ __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S
         if (v < ucnt) {
             const int b = (int)S.ulist[v];
             cm[v] = S.colmask[b];
-            if (cm[v]) x[v] = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
+            if (cm[v]) x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+        }
+    }
+    // D of all column groups in one walk over the input's sample list, four
+    // entries at a time, the next four loaded while these are summed
+    float D[4][8];
+#pragma unroll
+    for (int cg = 0; cg < 4; ++cg)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) D[cg][c] = 0.f;
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
+    uint2 cur = head;
+    for (int k0 = 0; k0 < cnt; k0 += 4) {
+        const uint2 nxt = k0 + 4 < cnt ? l4[(k0 >> 2) + 1] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int cg = 0; cg < 4; ++cg)
+            if (cg < ncg) gather4rows(cur, k0, cnt, S.xpost, p.ls, 8 * cg, p.B, p.reduce, D[cg], prec_d);
+        cur = nxt;
+    }
+#pragma unroll
+    for (int cg = 0; cg < 4; ++cg) {
+        if (cg >= ncg) break;
+        const int c0 = 8 * cg;
+        float P[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) P[c] = 0.f;
+        const uint32_t grp = (colany >> c0) & 0xFFu;
+        if (grp) {
+            // the spike masks are the same in every lane: scalar branches skip
+            // the samples and columns that did not fire
+#pragma unroll
+            for (int v = 0; v < XR; ++v) {
+                const uint32_t m = __builtin_amdgcn_readfirstlane((cm[v] >> c0) & 0xFFu);
+                if (m) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+                }
+            }
+            for (int u = XR; u < ucnt; ++u) {
+                const int b = (int)S.ulist[u];
+                const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
+                if (!m) continue;
+                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
+            }
+        }
+        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
+        const float4 w0 = wr[0], w1 = wr[1];
+        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float xw = (float)((double)w[c] * S.scale[c0 + c]);
+            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
+            const float d = p.reduce == RED_MEAN ? D[cg][c] * p.inv_B : D[cg][c];
+            w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
+        }
+        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
+    }
+}
+
+// The same with the depression sums gathered per column group (each group
+// walks the sample list; fewer registers, for the persistent kernel).
+template <bool Coherent, int XR>
+__device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds &S, int i, int cnt, uint2 head,
+                                                  const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
+                                                  int prec, int prec_d)
+{
+    const int ncg = p.jbp >> 3;
+    float x[XR];
+    uint32_t cm[XR];
+#pragma unroll
+    for (int v = 0; v < XR; ++v) {
+        cm[v] = 0u;
+        x[v] = 0.f;
+        if (v < ucnt) {
+            const int b = (int)S.ulist[v];
+            cm[v] = S.colmask[b];
+            if (cm[v]) x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
         }
     }
     for (int cg = 0; cg < ncg; ++cg) {
@@ -348,26 +453,30 @@ __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S
         for (int c = 0; c < 8; ++c) P[c] = 0.f;
         const uint32_t grp = (colany >> c0) & 0xFFu;
         if (grp) {
+            // the spike masks are the same in every lane: scalar branches skip
+            // the samples and columns that did not fire
 #pragma unroll
             for (int v = 0; v < XR; ++v) {
-                const uint32_t m = (cm[v] >> c0) & 0xFFu;
+                const uint32_t m = __builtin_amdgcn_readfirstlane((cm[v] >> c0) & 0xFFu);
+                if (m) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+                    for (int c = 0; c < 8; ++c)
+                        if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+                }
             }
             for (int u = XR; u < ucnt; ++u) {
                 const int b = (int)S.ulist[u];
                 const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
                 if (!m) continue;
-                const float xv = ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i);
+                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
             }
         }
         float D[8];
-        gather8(ltrow, cnt, head, head, 4, S.xpost, p.jbp, c0, p.B, p.reduce, D);
-        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.jbp + c0);
+        gather8(ltrow, cnt, head, head, 4, S.xpost, p.ls, c0, p.B, p.reduce, D, prec_d);
+        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
         const float4 w0 = wr[0], w1 = wr[1];
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
@@ -384,9 +493,10 @@ __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S
 
 // Phase C over all input rows of the block; a thread loads its next row's
 // list head before working on the current row.
-template <bool Coherent, int XR>
+template <bool Coherent, int XR, bool OneWalk>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
-                                               const uint32_t *ct, const float *xpre, int tid, int nt)
+                                               const uint32_t *ct, const float *xpre, int tid, int nt, int prec,
+                                               int prec_d)
 {
     const int ucnt = (int)S.ulist[p.B];
     uint32_t colany = 0u;
@@ -406,19 +516,38 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             cnt_n = ct[in];
             head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)in * p.lt_stride);
         }
-        plasticity_row<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany);
+        if constexpr (OneWalk)
+            plasticity_row<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
+                                         prec, prec_d);
+        else
+            plasticity_row_cg<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt,
+                                            colany, prec, prec_d);
         i = in;
     }
 }
 
 // Phase C3: FP64 column sums of the updated block, the pending
 // normalisation scale, the threshold update.  Two workgroup barriers.
+// Apply the pending column scale to the LDS block (w <- float(w * scale))
+// and reset it: the reduced-precision forms round the normalised weight.
+__device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, int tid, int nt)
+{
+    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
+    if (jj < p.jb) {
+        const double sc = S.scale[jj];
+        for (int i = rg; i < p.n_in; i += nrg) S.W[i * p.ls + jj] = (float)((double)S.W[i * p.ls + jj] * sc);
+    }
+    __syncthreads();
+    if (tid < 32) S.scale[tid] = 1.0;
+    __syncthreads();
+}
+
 __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, int tid, int nt)
 {
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     double cs = 0.0;
     if (jj < p.jb)
-        for (int i = rg; i < p.n_in; i += nrg) cs += (double)S.W[i * p.jbp + jj];
+        for (int i = rg; i < p.n_in; i += nrg) cs += (double)S.W[i * p.ls + jj];
     S.part[rg * 32 + jj] = cs;
     __syncthreads();
     if (tid < 32) {
@@ -454,7 +583,7 @@ __device__ __forceinline__ void xpre_next(const Params &p, const uint32_t *bits_
 __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, const float *Wg, const double *theta,
                                            int g, int tid, int nt)
 {
-    const int JB = p.jb, JBP = p.jbp;
+    const int JB = p.jb, JBP = p.jbp, LS = p.ls;
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     if (jj < JBP) {
         int i = rg;
@@ -466,15 +595,15 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
                 v2 = Wg[(size_t)(i + 2 * nrg) * JB + jj];
                 v3 = Wg[(size_t)(i + 3 * nrg) * JB + jj];
             }
-            S.W[i * JBP + jj] = v0;
-            S.W[(i + nrg) * JBP + jj] = v1;
-            S.W[(i + 2 * nrg) * JBP + jj] = v2;
-            S.W[(i + 3 * nrg) * JBP + jj] = v3;
+            S.W[i * LS + jj] = v0;
+            S.W[(i + nrg) * LS + jj] = v1;
+            S.W[(i + 2 * nrg) * LS + jj] = v2;
+            S.W[(i + 3 * nrg) * LS + jj] = v3;
         }
-        for (; i < p.n_in_pad; i += nrg) S.W[i * JBP + jj] = jj < JB ? Wg[(size_t)i * JB + jj] : 0.f;
+        for (; i < p.n_in_pad; i += nrg) S.W[i * LS + jj] = jj < JB ? Wg[(size_t)i * JB + jj] : 0.f;
         if (rg == 0) {
-            S.W[p.n_in_pad * JBP + jj] = 0.f;
-            if (p.learn) S.xpost[p.B * JBP + jj] = 0.f;
+            S.W[p.n_in_pad * LS + jj] = 0.f;
+            if (p.learn) S.xpost[p.B * LS + jj] = 0.f;
         }
     }
     if (tid < 32) {
@@ -485,15 +614,37 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
 }
 
 // Epilogue of a learning launch: the block, normalised, and the thresholds.
+// The block's FP32 weights into LDS again (after a contraction on rounded
+// weights), the rows of load_block without the thresholds.
+__device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S, const float *Wg, int tid, int nt)
+{
+    const int JB = p.jb, JBP = p.jbp, LS = p.ls;
+    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
+    if (jj < JB) {
+        int i = rg;
+        for (; i + 3 * nrg < p.n_in_pad; i += 4 * nrg) {
+            const float v0 = Wg[(size_t)i * JB + jj];
+            const float v1 = Wg[(size_t)(i + nrg) * JB + jj];
+            const float v2 = Wg[(size_t)(i + 2 * nrg) * JB + jj];
+            const float v3 = Wg[(size_t)(i + 3 * nrg) * JB + jj];
+            S.W[i * LS + jj] = v0;
+            S.W[(i + nrg) * LS + jj] = v1;
+            S.W[(i + 2 * nrg) * LS + jj] = v2;
+            S.W[(i + 3 * nrg) * LS + jj] = v3;
+        }
+        for (; i < p.n_in_pad; i += nrg) S.W[i * LS + jj] = Wg[(size_t)i * JB + jj];
+    }
+}
+
 __device__ __forceinline__ void store_block(const Params &p, const StepLds &S, float *Wg, double *theta, int g,
                                             int tid, int nt)
 {
-    const int JB = p.jb, JBP = p.jbp;
+    const int JB = p.jb, JBP = p.jbp, LS = p.ls;
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     if (jj < JB) {
         const double sc = S.scale[jj];
         for (int i = rg; i < p.n_in_pad; i += nrg) {
-            float w = S.W[i * JBP + jj];
+            float w = S.W[i * LS + jj];
             if (i < p.n_in) w = (float)((double)w * sc);
             Wg[(size_t)i * JB + jj] = w;
         }
@@ -518,8 +669,8 @@ __device__ __forceinline__ void load_task_state(const Params &p, const StepLds &
         for (int c = 0; c < 8; ++c) vi[c] = 0.f;
     }
     if (p.learn) {
-        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0) = *reinterpret_cast<const float4 *>(a.x_post + n0);
-        *reinterpret_cast<float4 *>(S.xpost + b * p.jbp + c0 + 4) =
+        *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0) = *reinterpret_cast<const float4 *>(a.x_post + n0);
+        *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0 + 4) =
             *reinterpret_cast<const float4 *>(a.x_post + n0 + 4);
     }
     const uint4 r = *reinterpret_cast<const uint4 *>(a.rf + n0);
@@ -536,9 +687,9 @@ __device__ __forceinline__ void store_task_state(const Params &p, const StepLds 
         *reinterpret_cast<float4 *>(a.v_inh + n0 + 4) = make_float4(vi[4], vi[5], vi[6], vi[7]);
     }
     if (p.learn) {
-        *reinterpret_cast<float4 *>(a.x_post + n0) = *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0);
+        *reinterpret_cast<float4 *>(a.x_post + n0) = *reinterpret_cast<const float4 *>(S.xpost + b * p.ls + c0);
         *reinterpret_cast<float4 *>(a.x_post + n0 + 4) =
-            *reinterpret_cast<const float4 *>(S.xpost + b * p.jbp + c0 + 4);
+            *reinterpret_cast<const float4 *>(S.xpost + b * p.ls + c0 + 4);
     }
     *reinterpret_cast<uint4 *>(a.rf + n0) = make_uint4(rw[0], rw[1], rw[2], rw[3]);
 }

@@ -20,12 +20,17 @@
 
 namespace snn {
 
-size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads).total; }
+size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads, true).total; }
 
+// PREC: the operand form.  For BF16 / FP8 the block's weights are rounded
+// in LDS for the contraction and reloaded in FP32 for the plasticity, and
+// the post traces in LDS are rounded once after the neurons' state went back
+// to HBM in FP32; the presynaptic traces are rounded as they are read.
+template <int PREC>
 __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const FusedLds L(p, blockDim.x);
+    const FusedLds L(p, blockDim.x, true);
     const StepLds S(smem, L);
     const int g = blockIdx.x;
     const int tid = threadIdx.x;
@@ -35,6 +40,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
 
     load_block(p, S, Wg, a.theta, g, tid, nt);
     __syncthreads();
+    if (PREC != PREC_FP32)
+        for (int q = tid; q < p.n_in_pad * p.ls; q += nt) S.W[q] = operand_value(PREC, S.W[q]);
     step_begin<false>(p, S, s.Cprev, tid, nt);
     __syncthreads();
 
@@ -51,21 +58,34 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
         const uint16_t *row = s.lin + (size_t)b * p.n_in_pad;
         const uint4 h = *reinterpret_cast<const uint4 *>(row);
         load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
-        gather8(row, (int)cnt, make_uint2(h.x, h.y), make_uint2(h.z, h.w), 8, S.W, JBP, c0, p.n_in_pad, RED_SUM, acc);
+        gather8(row, (int)cnt, make_uint2(h.x, h.y), make_uint2(h.z, h.w), 8, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, 0);
         neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, ve, vi, rw);
         store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
+        if (PREC != PREC_FP32 && p.learn) {
+            float *xr = S.xpost + b * p.ls + c0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) xr[c] = operand_value(PREC, xr[c]);
+        }
     }
     __syncthreads();
     step_publish<false>(p, S, s.Ccur, s.Cnext, g, tid, nt);
     if (!p.learn) return;
+    if (PREC != PREC_FP32) {
+        __syncthreads();
+        reload_weights(p, S, Wg, tid, nt);
+    }
     __syncthreads();
 
-    plasticity_all<false, 16>(p, S, s.lt, s.ct, s.xpre, tid, nt);
+    plasticity_all<false, 16, false>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);
     store_block(p, S, Wg, a.theta, g, tid, nt);
 }
+
+template __global__ void k_fused_step<PREC_FP32>(Params, FusedArgs, StepPtrs);
+template __global__ void k_fused_step<PREC_BF16>(Params, FusedArgs, StepPtrs);
+template __global__ void k_fused_step<PREC_FP8>(Params, FusedArgs, StepPtrs);
 
 // Sparse index lists of one chunk of encoded steps:
 //   lin[t][b][0 .. cin[t][b])  inputs that spiked in sample b (increasing)

@@ -41,12 +41,26 @@ __device__ __forceinline__ float e4m3_value(uint32_t c)
     return (c & 0x80u) ? -v : v;
 }
 
+// x rounded to the E4M3 grid, as an FP32 value (the value of e4m3_code(x)):
+// 3 fraction bits at or above 2^-6, multiples of 2^-9 below, at most 448.
+__device__ __forceinline__ float e4m3_round(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t a = u & 0x7FFFFFFFu;
+    float r;
+    if (a >= 0x3C800000u)
+        r = fminf(__uint_as_float((a + 0x7FFFFu + ((a >> 20) & 1u)) & 0xFFF00000u), 448.f);
+    else
+        r = rintf(__uint_as_float(a) * 512.f) * (1.f / 512.f);
+    return __uint_as_float(__float_as_uint(r) | (u & 0x80000000u));
+}
+
 // Value of x as the contraction sees it in the form `prec` (the gather
 // kernels' view of the same operand rounding).
 __device__ __forceinline__ float operand_value(int prec, float x)
 {
     if (prec == PREC_BF16) return bf16_value(bf16_code(x));
-    if (prec == PREC_FP8) return e4m3_value(e4m3_code(x));
+    if (prec == PREC_FP8) return e4m3_round(x);
     return x;
 }
 

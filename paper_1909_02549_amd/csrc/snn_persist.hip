@@ -13,6 +13,7 @@
 
 #include "snn_dev.h"
 #include "snn_fused.h"
+#include "snn_mfma.h"
 #include "snn_kern.h"
 
 namespace snn {
@@ -48,8 +49,11 @@ __device__ __forceinline__ bool grid_barrier(const PersistSync &sy, uint32_t tar
     return *abort_lds == 0;
 }
 
+template <int PREC>
 __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *__restrict__ args)
 {
+    // PREC: the operand form (rounding in the gathers for BF16 / FP8)
+
     const Params &p = args->p;
     const FusedArgs &a = args->a;
     const ChunkPtrs &ch = args->ch;
@@ -108,18 +112,19 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             if (!has_task[u]) continue;
             float acc[8];
             const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
-            gather8(row, (int)hin_cnt[u], make_uint2(hin[u].x, hin[u].y), make_uint2(hin[u].z, hin[u].w), 8, S.W, JBP,
-                    tc0[u], p.n_in_pad, RED_SUM, acc);
+            gather8(row, (int)hin_cnt[u], make_uint2(hin[u].x, hin[u].y), make_uint2(hin[u].z, hin[u].w), 8, S.W, p.ls,
+                    tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
             neuron_task(p, S, a.o, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, ve[u], vi[u], rw[u]);
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
         if (p.learn) {
             __syncthreads();
-            plasticity_all<true, 16>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
-                                     ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt);
+            plasticity_all<true, 16, false>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
+                                     ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC);
             __syncthreads();
             colsums_theta(p, S, tid, nt);
+            if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);
             if (k + 1 < ch.steps || ch.has_next)
                 xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
         }
@@ -142,5 +147,9 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
                              vi[u], rw[u]);
     if (p.learn) store_block(p, S, Wg, a.theta, g, tid, nt);
 }
+
+template __global__ void k_persist<PREC_FP32>(const PersistArgs *);
+template __global__ void k_persist<PREC_BF16>(const PersistArgs *);
+template __global__ void k_persist<PREC_FP8>(const PersistArgs *);
 
 }  // namespace snn

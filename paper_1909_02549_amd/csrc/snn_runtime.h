@@ -95,7 +95,7 @@ struct snn_net {
     size_t mfma_c_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};  // current kernel, per precision
     snn_status xpre_first(const uint32_t *bits_t);
     bool fused_ok() const;
-    size_t fused_attr_bytes = 64 * 1024;
+    size_t fused_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};  // per operand form
     snn_status fused_step(int kk, int k, bool has_next, const snn::Outs &o);
 
     // persistent path: grid barrier counter / error flag, argument ring
@@ -105,7 +105,7 @@ struct snn_net {
     void *pargs_host = nullptr;          // kArgSlots x PersistArgs (pinned)
     hipEvent_t pargs_ev[kArgSlots] = {};
     int pargs_next = 0;
-    size_t persist_attr_bytes = 64 * 1024;
+    size_t persist_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};
     int coop_ok = -1;
     bool persist_ok();
     snn_status persist_chunk(int steps, bool has_next, int k0, const snn::Outs &o);

@@ -96,6 +96,8 @@ static void fill_dims(Params &p, const snn_config &c, int jb)
     p.n_exc = (int)c.n_exc;
     p.jb = jb;
     p.jbp = (jb + 7) & ~7;
+    // LDS rows of 16 or 32 floats would start on only 2 or 4 banks
+    p.ls = (p.jbp == 16 || p.jbp == 32) ? p.jbp + 4 : p.jbp;
     p.nblk = (int)((c.n_exc + jb - 1) / jb);
     p.n_pad = p.nblk * jb;
     p.has_inh = c.n_inh > 0;
@@ -720,11 +722,20 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.k = k;
     FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
     const size_t lds = fused_lds_bytes(p);
-    if (lds > fused_attr_bytes) {
-        HIP_TRY(hipFuncSetAttribute((const void *)k_fused_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        fused_attr_bytes = lds;
+    const void *fn = p.prec == PREC_FP32   ? (const void *)k_fused_step<PREC_FP32>
+                     : p.prec == PREC_BF16 ? (const void *)k_fused_step<PREC_BF16>
+                                           : (const void *)k_fused_step<PREC_FP8>;
+    if (lds > fused_attr_bytes[p.prec]) {
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        fused_attr_bytes[p.prec] = lds;
     }
-    SNN_LAUNCH("fused_step", k_fused_step, dim3((unsigned)p.nblk), dim3(kFusedThreads), lds, p, a, s);
+    const dim3 grid((unsigned)p.nblk);
+    if (p.prec == PREC_FP32)
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP32>, grid, dim3(kFusedThreads), lds, p, a, s);
+    else if (p.prec == PREC_BF16)
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_BF16>, grid, dim3(kFusedThreads), lds, p, a, s);
+    else
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP8>, grid, dim3(kFusedThreads), lds, p, a, s);
     HIP_TRY(hipGetLastError());
     ++gstep;
     return SNN_OK;
@@ -767,9 +778,12 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     HIP_TRY(hipEventRecord(pargs_ev[slot], stream));
     SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
     const size_t lds = persist_lds_bytes(p);
-    if (lds > persist_attr_bytes) {
-        HIP_TRY(hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        persist_attr_bytes = lds;
+    const void *kfn = p.prec == PREC_FP32   ? (const void *)k_persist<PREC_FP32>
+                      : p.prec == PREC_BF16 ? (const void *)k_persist<PREC_BF16>
+                                            : (const void *)k_persist<PREC_FP8>;
+    if (lds > persist_attr_bytes[p.prec]) {
+        HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        persist_attr_bytes[p.prec] = lds;
     }
     void *kargs[] = {(void *)&d};
     std::pair<hipEvent_t, hipEvent_t> ev{};
@@ -778,7 +792,7 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
         kid = kstat_id("persistent");
         ev = prof_begin();
     }
-    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_persist, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
+    HIP_TRY(hipLaunchCooperativeKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
                                        (unsigned)lds, stream));
     if (prof) prof_end(kid, ev);
     gstep += (uint64_t)steps;
@@ -822,9 +836,6 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
-    // the step kernels compute in the FP32 form only; the reduced forms run
-    // on the matrix-core route
-    if ((path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT) && p.prec != PREC_FP32) path = SNN_PATH_MFMA;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
     if (path == SNN_PATH_MFMA && p.jb > 32) path = SNN_PATH_PLAIN;

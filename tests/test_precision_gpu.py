@@ -16,7 +16,7 @@ from test_parity_gpu import check_parity, run_both, torch_cuda  # noqa: F401
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "fused", "persistent"])
 @pytest.mark.parametrize("precision", ["bf16", "fp8"])
 @pytest.mark.parametrize("reduce", ["mean", "sum"])
 def test_reduced_forms_match_rounded_oracle(torch_cuda, oracle_mod, path, precision, reduce):
@@ -29,13 +29,16 @@ def test_reduced_forms_match_rounded_oracle(torch_cuda, oracle_mod, path, precis
     check_parity(g, ref)
 
 
-def test_max_reduction_in_reduced_form(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", ["mfma", "persistent"])
+def test_max_reduction_in_reduced_form(torch_cuda, oracle_mod, path):
     """max has no matrix form: the MFMA route keeps the gather plasticity
-    kernel, which takes the same rounded traces."""
+    kernel, which takes the same rounded traces; the persistent kernel
+    rounds in its own gathers."""
     cfg = dc_config(60, reduce="max")
     imgs = stroke_images(6, 50, 0.19)
     W = uniform_weights(784, 60, 0.0, 0.3, 12)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(6, 400), 60, path="mfma", precision="bf16")
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(6, 400), 60, path=path, precision="bf16")
+    assert g["path"] == path
     check_parity(g, ref)
 
 
