@@ -161,12 +161,12 @@ def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0) -> dict:
 
 
 def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
+    """Wall time of `steps` episodic trials after `warmup` untimed ones, with
+    no per-kernel events in the timed region; with `profile`, one more trial
+    with HIP events around every launch gives the per-kernel times."""
     import torch
     for _ in range(warmup):
         net.snn_run(imgs_d, ids_d, T, reset=True, record=())
-    torch.cuda.synchronize()
-    if profile:
-        net.snn_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -174,8 +174,13 @@ def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     net.snn_sync()
-    prof = net.snn_profile_get() if profile else {}
+    prof = {}
     if profile:
+        net.snn_profile_enable(True)
+        net.snn_run(imgs_d, ids_d, T, reset=True, record=())
+        torch.cuda.synchronize()
+        net.snn_sync()
+        prof = net.snn_profile_get()
         net.snn_profile_enable(False)
     return el, prof
 
@@ -344,7 +349,7 @@ def main():
     if prof:
         gpu_ms = sum(v[1] for v in prof.values())
         for kn, (ln, ms) in prof.items():
-            kr = kernel_roofline(kn, d, args.precision, ln, ms, T * args.steps / max(ln, 1))
+            kr = kernel_roofline(kn, d, args.precision, ln, ms, T / max(ln, 1))
             if kr is not None:
                 kr["share_of_gpu_time"] = ms / gpu_ms
                 kroofs[kn] = kr
@@ -362,7 +367,7 @@ def main():
             entry = {"value": B * T * n / pel, "ms_per_step": pel * 1e3 / n, "used": pnet.snn_last_path()}
             entry["kernels"] = {}
             for kn, (ln, ms) in pprof.items():
-                kr = kernel_roofline(kn, d, args.precision, ln, ms, T * n / max(ln, 1))
+                kr = kernel_roofline(kn, d, args.precision, ln, ms, T / max(ln, 1))
                 ke = {"launches": ln, "avg_us": ms * 1e3 / max(ln, 1)}
                 if kr is not None:
                     ke["hbm_frac"] = kr["bytes_per_launch"] / (kr["avg_launch_us"] / 1e6) / 1e9 / HBM_PEAK_GBS

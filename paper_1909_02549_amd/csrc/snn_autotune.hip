@@ -10,7 +10,8 @@
 // episode, keeps the fastest in a process-wide table, and appends it to the
 // file named by SNN_AUTOTUNE_CACHE if set (lines "key path").
 // SNN_AUTOTUNE=0 skips the measurement and takes the first available path in
-// the order persistent, fused, MFMA, plain.
+// the order persistent, fused, MFMA, plain; SNN_AUTOTUNE_VERBOSE=1 reports
+// each candidate's time on stderr.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -63,6 +64,8 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
     cand.push_back(SNN_PATH_MFMA);
     cand.push_back(SNN_PATH_PLAIN);
     const char *env = std::getenv("SNN_AUTOTUNE");
+    const char *venv = std::getenv("SNN_AUTOTUNE_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
     if (cand.size() == 1 || (env && env[0] == '0')) return cand[0];
 
     std::ostringstream ks;
@@ -103,6 +106,11 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
         float best_ms = 1e30f;
         for (int cnd : cand) {
             if (!ok) break;
+            // every candidate starts from the caller's weights and thresholds
+            ok = hipMemcpyAsync(tmp->W, W, nw * sizeof(float), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+                 hipMemcpyAsync(tmp->theta, theta, (size_t)p.n_pad * sizeof(double), hipMemcpyDeviceToDevice,
+                                stream) == hipSuccess;
+            if (!ok) break;
             tmp->path = cnd;
             if (tmp->run(images, ids, forced, batch, warm, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
             // with graph replay on, the timed episode replays a captured graph
@@ -115,6 +123,9 @@ int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, cons
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 break;
             if (tmp->check_device_error() != SNN_OK) continue;
+            if (verbose)
+                std::fprintf(stderr, "snn autotune %s: path %d (ran %d) %.3f ms for %u steps\n", key.c_str(), cnd,
+                             tmp->last_path, ms, steps);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = cnd;

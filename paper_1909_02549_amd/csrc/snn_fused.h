@@ -348,7 +348,7 @@ __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, 
 // The x_pre values of the first XR spiking samples are loaded once into
 // registers (all in flight together) and reused by every column group.
 template <bool Coherent, int XR>
-__device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S, int i, int cnt, uint2 head,
+__device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S, int i, int cnt, uint4 head8,
                                                const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
                                                int prec, int prec_d)
 {
@@ -373,9 +373,9 @@ __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S
 #pragma unroll
         for (int c = 0; c < 8; ++c) D[cg][c] = 0.f;
     const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
-    uint2 cur = head;
+    uint2 cur = make_uint2(head8.x, head8.y);
     for (int k0 = 0; k0 < cnt; k0 += 4) {
-        const uint2 nxt = k0 + 4 < cnt ? l4[(k0 >> 2) + 1] : make_uint2(0u, 0u);
+        const uint2 nxt = k0 + 4 >= cnt ? make_uint2(0u, 0u) : k0 == 0 ? make_uint2(head8.z, head8.w) : l4[(k0 >> 2) + 1];
 #pragma unroll
         for (int cg = 0; cg < 4; ++cg)
             if (cg < ncg) gather4rows(cur, k0, cnt, S.xpost, p.ls, 8 * cg, p.B, p.reduce, D[cg], prec_d);
@@ -429,7 +429,7 @@ __device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S
 // The same with the depression sums gathered per column group (each group
 // walks the sample list; fewer registers, for the persistent kernel).
 template <bool Coherent, int XR>
-__device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds &S, int i, int cnt, uint2 head,
+__device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds &S, int i, int cnt, uint4 head,
                                                   const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
                                                   int prec, int prec_d)
 {
@@ -475,7 +475,8 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
             }
         }
         float D[8];
-        gather8(ltrow, cnt, head, head, 4, S.xpost, p.ls, c0, p.B, p.reduce, D, prec_d);
+        gather8(ltrow, cnt, make_uint2(head.x, head.y), make_uint2(head.z, head.w), 8, S.xpost, p.ls, c0, p.B,
+                p.reduce, D, prec_d);
         float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
         const float4 w0 = wr[0], w1 = wr[1];
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
@@ -503,18 +504,18 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
     for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
     int i = tid;
     uint32_t cnt_n = 0u;
-    uint2 head_n = make_uint2(0u, 0u);
+    uint4 head_n = make_uint4(0u, 0u, 0u, 0u);
     if (i < p.n_in) {
         cnt_n = ct[i];
-        head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)i * p.lt_stride);
+        head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)i * p.lt_stride);
     }
     while (i < p.n_in) {
         const uint32_t cnt = cnt_n;
-        const uint2 head = head_n;
+        const uint4 head = head_n;
         const int in = i + nt;
         if (in < p.n_in) {
             cnt_n = ct[in];
-            head_n = *reinterpret_cast<const uint2 *>(lt + (size_t)in * p.lt_stride);
+            head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)in * p.lt_stride);
         }
         if constexpr (OneWalk)
             plasticity_row<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
