@@ -494,7 +494,85 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
 
 // Phase C over all input rows of the block; a thread loads its next row's
 // list head before working on the current row.
-template <bool Coherent, int XR, bool OneWalk>
+// Plasticity of column groups [cg0, cg0 + ng) of row i (ng <= 2): one walk
+// over the input's sample list for both groups (the row split over two
+// threads).
+template <bool Coherent, int XR>
+__device__ __forceinline__ void plasticity_row_half(const Params &p, const StepLds &S, int i, int cg0, int ng,
+                                                    int cnt, uint4 head8, const uint16_t *ltrow, const float *xpre,
+                                                    int ucnt, uint32_t colany, int prec, int prec_d)
+{
+    float x[XR];
+    uint32_t cm[XR];
+#pragma unroll
+    for (int v = 0; v < XR; ++v) {
+        cm[v] = 0u;
+        x[v] = 0.f;
+        if (v < ucnt) {
+            const int b = (int)S.ulist[v];
+            cm[v] = S.colmask[b];
+            if ((cm[v] >> (8 * cg0)) & 0xFFFFu)
+                x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+        }
+    }
+    float D[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) D[h][c] = 0.f;
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
+    uint2 cur = make_uint2(head8.x, head8.y);
+    for (int k0 = 0; k0 < cnt; k0 += 4) {
+        const uint2 nxt = k0 + 4 >= cnt ? make_uint2(0u, 0u) : k0 == 0 ? make_uint2(head8.z, head8.w) : l4[(k0 >> 2) + 1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (h < ng) gather4rows(cur, k0, cnt, S.xpost, p.ls, 8 * (cg0 + h), p.B, p.reduce, D[h], prec_d);
+        cur = nxt;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= ng) break;
+        const int c0 = 8 * (cg0 + h);
+        float P[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) P[c] = 0.f;
+        const uint32_t grp = (colany >> c0) & 0xFFu;
+        if (grp) {
+#pragma unroll
+            for (int v = 0; v < XR; ++v) {
+                const uint32_t m = __builtin_amdgcn_readfirstlane((cm[v] >> c0) & 0xFFu);
+                if (m) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
+                }
+            }
+            for (int u = XR; u < ucnt; ++u) {
+                const int b = (int)S.ulist[u];
+                const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
+                if (!m) continue;
+                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
+            }
+        }
+        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
+        const float4 w0 = wr[0], w1 = wr[1];
+        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float xw = (float)((double)w[c] * S.scale[c0 + c]);
+            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
+            const float d = p.reduce == RED_MEAN ? D[h][c] * p.inv_B : D[h][c];
+            w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
+        }
+        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
+    }
+}
+
+template <bool Coherent, int XR, bool OneWalk, bool Halves = false>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const float *xpre, int tid, int nt, int prec,
                                                int prec_d)
@@ -502,6 +580,20 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
     const int ucnt = (int)S.ulist[p.B];
     uint32_t colany = 0u;
     for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
+    const int ncg = p.jbp >> 3;
+    if (Halves && ncg >= 2) {
+        // item q: row q / 2, column groups 2 (q % 2) .. +1
+        for (int q = tid; q < 2 * p.n_in; q += nt) {
+            const int i = q >> 1, cg0 = 2 * (q & 1);
+            const int ng = min(2, ncg - cg0);
+            if (ng <= 0) continue;
+            const uint32_t cnt = ct[i];
+            const uint4 head = *reinterpret_cast<const uint4 *>(lt + (size_t)i * p.lt_stride);
+            plasticity_row_half<Coherent, XR>(p, S, i, cg0, ng, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre,
+                                              ucnt, colany, prec, prec_d);
+        }
+        return;
+    }
     int i = tid;
     uint32_t cnt_n = 0u;
     uint4 head_n = make_uint4(0u, 0u, 0u, 0u);

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     }
     __syncthreads();
 
-    plasticity_all<false, 16, false>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
+    plasticity_all<false, 16, false, true>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);
