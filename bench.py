@@ -161,25 +161,26 @@ def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0) -> dict:
 
 
 def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
-    """Wall time of `steps` episodic trials after `warmup` untimed ones, with
-    no per-kernel events in the timed region; with `profile`, one more trial
-    with HIP events around every launch gives the per-kernel times."""
+    """Wall time of `steps` episodic trials after `warmup` untimed ones.  With
+    `profile`, the library brackets each run of consecutive launches of one
+    kernel in the timed trials with a pair of HIP events on its stream (a few
+    events per trial, none between the launches of a run), which gives the
+    per-kernel times of the timed region itself."""
     import torch
     for _ in range(warmup):
         net.snn_run(imgs_d, ids_d, T, reset=True, record=())
     torch.cuda.synchronize()
+    net.snn_sync()
+    if profile:
+        net.snn_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         net.snn_run(imgs_d, ids_d, T, reset=True, record=())
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
     net.snn_sync()
+    el = time.perf_counter() - t0
     prof = {}
     if profile:
-        net.snn_profile_enable(True)
-        net.snn_run(imgs_d, ids_d, T, reset=True, record=())
-        torch.cuda.synchronize()
-        net.snn_sync()
         prof = net.snn_profile_get()
         net.snn_profile_enable(False)
     return el, prof

@@ -206,10 +206,12 @@ snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, uint32_t ba
 /* Block until all work queued on the handle's stream has finished. */
 snn_status snn_sync(snn_net *net);
 
-/* Per-kernel timing: with profiling on, every kernel launch of the handle is
- * bracketed by two HIP events recorded on the handle's stream, and elapsed
- * times are accumulated per kernel name (cleared when profiling is turned
- * on).  snn_profile_get returns entry idx (SNN_ENOTFOUND past the last one):
+/* Per-kernel timing: with profiling on, each run of consecutive launches of
+ * one kernel on the handle's stream is bracketed by two HIP events recorded
+ * on that stream (no events between the launches of a run), and the elapsed
+ * times and launch counts are accumulated per kernel name (cleared when
+ * profiling is turned on); a kernel's average is thus the run time per
+ * launch, back-to-back gaps included.  snn_profile_get returns entry idx (SNN_ENOTFOUND past the last one):
  * its name (copied into name[name_len]), launch count and total milliseconds.
  * Reading synchronises the stream. */
 snn_status snn_profile_enable(snn_net *net, int32_t on);

@@ -31,6 +31,8 @@ namespace snn {
 constexpr int kFusedThreads = 1024;   // fused per-step kernel: 16 waves
 constexpr int kPersistThreads = 512;  // persistent kernel: 8 waves, with
 constexpr int kPersistTasks = 2;      //   two (sample, 8 columns) tasks each
+constexpr int kListHead = 4;          // 16-byte words of a spike list read ahead
+static_assert(kFusedThreads % 128 == 0 && kPersistThreads % 128 == 0, "split-row plasticity needs nt % 128 == 0");
 
 // Per-network pointers (state and parameters owned by the handle).
 struct FusedArgs {
@@ -253,6 +255,34 @@ __device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int c
     for (int k0 = 8; k0 < cnt; k0 += 4) gather4rows(l4[k0 >> 2], k0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
 }
 
+// The same with the first 8 * NH entries of the list in h[0 .. NH) (16-byte
+// words loaded together ahead of time, so a list of up to 8 * NH entries costs
+// one memory round trip); entries past those are read from `list`.
+template <int NH>
+__device__ __forceinline__ void gather_pre(const uint16_t *__restrict__ list, int cnt, const uint4 *h, const float *rows,
+                                           int jbp, int c0, int zero_row, int mode, float *acc, int prec)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+        if (8 * q < cnt) gather4rows(make_uint2(h[q].x, h[q].y), 8 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+        if (8 * q + 4 < cnt)
+            gather4rows(make_uint2(h[q].z, h[q].w), 8 * q + 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    }
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
+    for (int k0 = 8 * NH; k0 < cnt; k0 += 4) gather4rows(l4[k0 >> 2], k0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+}
+
+// Load the first 8 * NH entries of a list (NH 16-byte words, all in flight).
+template <int NH>
+__device__ __forceinline__ void load_heads(const uint16_t *list, uint4 *h)
+{
+    const uint4 *l = reinterpret_cast<const uint4 *>(list);
+#pragma unroll
+    for (int q = 0; q < NH; ++q) h[q] = l[q];
+}
+
 // Step phase A: C(t-1) and per-step scratch in LDS, threshold offsets.
 // theta64 holds the workgroup's thresholds (FP64).
 template <bool Coherent>
@@ -346,88 +376,8 @@ __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, 
 //   D[c] = R over the samples in input i's spike list of x_post[b, c]
 //   w = clamp(float(w * scale[c]) + nu_post * P[c] - nu_pre * D[c])
 // The x_pre values of the first XR spiking samples are loaded once into
-// registers (all in flight together) and reused by every column group.
-template <bool Coherent, int XR>
-__device__ __forceinline__ void plasticity_row(const Params &p, const StepLds &S, int i, int cnt, uint4 head8,
-                                               const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
-                                               int prec, int prec_d)
-{
-    const int ncg = p.jbp >> 3;
-    float x[XR];
-    uint32_t cm[XR];
-#pragma unroll
-    for (int v = 0; v < XR; ++v) {
-        cm[v] = 0u;
-        x[v] = 0.f;
-        if (v < ucnt) {
-            const int b = (int)S.ulist[v];
-            cm[v] = S.colmask[b];
-            if (cm[v]) x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
-        }
-    }
-    // D of all column groups in one walk over the input's sample list, four
-    // entries at a time, the next four loaded while these are summed
-    float D[4][8];
-#pragma unroll
-    for (int cg = 0; cg < 4; ++cg)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) D[cg][c] = 0.f;
-    const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
-    uint2 cur = make_uint2(head8.x, head8.y);
-    for (int k0 = 0; k0 < cnt; k0 += 4) {
-        const uint2 nxt = k0 + 4 >= cnt ? make_uint2(0u, 0u) : k0 == 0 ? make_uint2(head8.z, head8.w) : l4[(k0 >> 2) + 1];
-#pragma unroll
-        for (int cg = 0; cg < 4; ++cg)
-            if (cg < ncg) gather4rows(cur, k0, cnt, S.xpost, p.ls, 8 * cg, p.B, p.reduce, D[cg], prec_d);
-        cur = nxt;
-    }
-#pragma unroll
-    for (int cg = 0; cg < 4; ++cg) {
-        if (cg >= ncg) break;
-        const int c0 = 8 * cg;
-        float P[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) P[c] = 0.f;
-        const uint32_t grp = (colany >> c0) & 0xFFu;
-        if (grp) {
-            // the spike masks are the same in every lane: scalar branches skip
-            // the samples and columns that did not fire
-#pragma unroll
-            for (int v = 0; v < XR; ++v) {
-                const uint32_t m = __builtin_amdgcn_readfirstlane((cm[v] >> c0) & 0xFFu);
-                if (m) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
-                }
-            }
-            for (int u = XR; u < ucnt; ++u) {
-                const int b = (int)S.ulist[u];
-                const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
-                if (!m) continue;
-                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
-            }
-        }
-        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
-        const float4 w0 = wr[0], w1 = wr[1];
-        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            float xw = (float)((double)w[c] * S.scale[c0 + c]);
-            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
-            const float d = p.reduce == RED_MEAN ? D[cg][c] * p.inv_B : D[cg][c];
-            w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
-        }
-        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
-        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
-    }
-}
-
-// The same with the depression sums gathered per column group (each group
-// walks the sample list; fewer registers, for the persistent kernel).
+// registers (all in flight together) and reused by every column group; each
+// group walks the sample list for its depression sums.
 template <bool Coherent, int XR>
 __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds &S, int i, int cnt, uint4 head,
                                                   const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
@@ -492,79 +442,81 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
     }
 }
 
-// Phase C over all input rows of the block; a thread loads its next row's
-// list head before working on the current row.
-// Plasticity of column groups [cg0, cg0 + ng) of row i (ng <= 2): one walk
-// over the input's sample list for both groups (the row split over two
-// threads).
-template <bool Coherent, int XR>
+// Plasticity of column groups [cg0, cg0 + ng) of row i (ng <= 2; cg0 the
+// same in every lane of the wave): one walk over the input's sample list for
+// both groups (the row split over two threads).  The potentiation terms are
+// taken 8 listed spiking samples at a time: sample numbers and column masks
+// are the same in every lane (scalar branches); the 8 x_pre loads go out
+// together, the first 8 before the depression walk, which hides them.
+template <bool Coherent, int NH>
 __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepLds &S, int i, int cg0, int ng,
-                                                    int cnt, uint4 head8, const uint16_t *ltrow, const float *xpre,
-                                                    int ucnt, uint32_t colany, int prec, int prec_d)
+                                                    int cnt, const uint4 *h, const uint16_t *ltrow, const float *xpre,
+                                                    int ucnt, int prec, int prec_d)
 {
-    float x[XR];
-    uint32_t cm[XR];
+    float P[2][8], D[2][8];
 #pragma unroll
-    for (int v = 0; v < XR; ++v) {
-        cm[v] = 0u;
-        x[v] = 0.f;
-        if (v < ucnt) {
-            const int b = (int)S.ulist[v];
-            cm[v] = S.colmask[b];
-            if ((cm[v] >> (8 * cg0)) & 0xFFFFu)
-                x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) P[g][c] = 0.f, D[g][c] = 0.f;
+    uint32_t m8[8];
+    float x8[8];
+    auto fetch = [&](int u0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int u = u0 + v;
+            const int b = u < ucnt ? (int)S.ulist[u] : 0;
+            m8[v] = u < ucnt ? (S.colmask[b] >> (8 * cg0)) & 0xFFFFu : 0u;
+            x8[v] = ld_x<Coherent>(xpre + (m8[v] ? (size_t)b * p.n_in_pad : 0) + i);
+        }
+    };
+    auto accumulate = [&]() {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const uint32_t m = __builtin_amdgcn_readfirstlane(m8[v]);
+            if (m) {
+                const float xv = operand_value(prec, x8[v]);
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if ((m >> c) & 1u) P[c >> 3][c & 7] = reduce2(p.reduce, P[c >> 3][c & 7], xv);
+            }
+        }
+    };
+    if (ucnt > 0) fetch(0);
+#pragma unroll
+    for (int q = 0; q < 2 * NH; ++q) {
+        if (4 * q < cnt) {
+            const uint2 e = (q & 1) ? make_uint2(h[q >> 1].z, h[q >> 1].w) : make_uint2(h[q >> 1].x, h[q >> 1].y);
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+                if (g < ng) gather4rows(e, 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
         }
     }
-    float D[2][8];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) D[h][c] = 0.f;
     const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
-    uint2 cur = make_uint2(head8.x, head8.y);
-    for (int k0 = 0; k0 < cnt; k0 += 4) {
-        const uint2 nxt = k0 + 4 >= cnt ? make_uint2(0u, 0u) : k0 == 0 ? make_uint2(head8.z, head8.w) : l4[(k0 >> 2) + 1];
+    for (int k0 = 8 * NH; k0 < cnt; k0 += 4) {
+        const uint2 e = l4[k0 >> 2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-            if (h < ng) gather4rows(cur, k0, cnt, S.xpost, p.ls, 8 * (cg0 + h), p.B, p.reduce, D[h], prec_d);
-        cur = nxt;
+        for (int g = 0; g < 2; ++g)
+            if (g < ng) gather4rows(e, k0, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
+    }
+    if (ucnt > 0) {
+        accumulate();
+        for (int u0 = 8; u0 < ucnt; u0 += 8) {
+            fetch(u0);
+            accumulate();
+        }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h >= ng) break;
-        const int c0 = 8 * (cg0 + h);
-        float P[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) P[c] = 0.f;
-        const uint32_t grp = (colany >> c0) & 0xFFu;
-        if (grp) {
-#pragma unroll
-            for (int v = 0; v < XR; ++v) {
-                const uint32_t m = __builtin_amdgcn_readfirstlane((cm[v] >> c0) & 0xFFu);
-                if (m) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], x[v]);
-                }
-            }
-            for (int u = XR; u < ucnt; ++u) {
-                const int b = (int)S.ulist[u];
-                const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
-                if (!m) continue;
-                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
-            }
-        }
+    for (int g = 0; g < 2; ++g) {
+        if (g >= ng) break;
+        const int c0 = 8 * (cg0 + g);
         float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
         const float4 w0 = wr[0], w1 = wr[1];
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             float xw = (float)((double)w[c] * S.scale[c0 + c]);
-            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
-            const float d = p.reduce == RED_MEAN ? D[h][c] * p.inv_B : D[h][c];
+            xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[g][c] * p.inv_B : P[g][c]);
+            const float d = p.reduce == RED_MEAN ? D[g][c] * p.inv_B : D[g][c];
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
         }
         wr[0] = make_float4(w[0], w[1], w[2], w[3]);
@@ -572,28 +524,34 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
     }
 }
 
-template <bool Coherent, int XR, bool OneWalk, bool Halves = false>
+// Phase C over all input rows of the block: split rows (Halves, blocks of
+// two or more column groups) or whole rows per thread; a thread loads its
+// next row's list head before working on the current row.
+template <bool Coherent, int XR, bool Halves, int NH = kListHead>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const float *xpre, int tid, int nt, int prec,
                                                int prec_d)
 {
     const int ucnt = (int)S.ulist[p.B];
-    uint32_t colany = 0u;
-    for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
     const int ncg = p.jbp >> 3;
     if (Halves && ncg >= 2) {
-        // item q: row q / 2, column groups 2 (q % 2) .. +1
-        for (int q = tid; q < 2 * p.n_in; q += nt) {
-            const int i = q >> 1, cg0 = 2 * (q & 1);
+        const int nrow = (p.n_in + 63) & ~63;
+        for (int q = tid; q < 2 * nrow; q += nt) {
+            const int hf = (q >> 6) & 1;
+            const int i = ((q >> 7) << 6) | (q & 63);
+            const int cg0 = 2 * hf;
             const int ng = min(2, ncg - cg0);
-            if (ng <= 0) continue;
+            if (i >= p.n_in || ng <= 0) continue;
             const uint32_t cnt = ct[i];
-            const uint4 head = *reinterpret_cast<const uint4 *>(lt + (size_t)i * p.lt_stride);
-            plasticity_row_half<Coherent, XR>(p, S, i, cg0, ng, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre,
-                                              ucnt, colany, prec, prec_d);
+            uint4 h[NH];
+            load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
+            plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
+                                              ucnt, prec, prec_d);
         }
         return;
     }
+    uint32_t colany = 0u;
+    for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
     int i = tid;
     uint32_t cnt_n = 0u;
     uint4 head_n = make_uint4(0u, 0u, 0u, 0u);
@@ -609,18 +567,12 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             cnt_n = ct[in];
             head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)in * p.lt_stride);
         }
-        if constexpr (OneWalk)
-            plasticity_row<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
-                                         prec, prec_d);
-        else
-            plasticity_row_cg<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt,
-                                            colany, prec, prec_d);
+        plasticity_row_cg<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
+                                        prec, prec_d);
         i = in;
     }
 }
 
-// Phase C3: FP64 column sums of the updated block, the pending
-// normalisation scale, the threshold update.  Two workgroup barriers.
 // Apply the pending column scale to the LDS block (w <- float(w * scale))
 // and reset it: the reduced-precision forms round the normalised weight.
 __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, int tid, int nt)
@@ -635,6 +587,8 @@ __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, i
     __syncthreads();
 }
 
+// Phase C3: FP64 column sums of the updated block, the pending
+// normalisation scale, the threshold update.  Two workgroup barriers.
 __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, int tid, int nt)
 {
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
@@ -706,7 +660,6 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
     }
 }
 
-// Epilogue of a learning launch: the block, normalised, and the thresholds.
 // The block's FP32 weights into LDS again (after a contraction on rounded
 // weights), the rows of load_block without the thresholds.
 __device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S, const float *Wg, int tid, int nt)
@@ -729,6 +682,7 @@ __device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S
     }
 }
 
+// Epilogue of a learning launch: the block, normalised, and the thresholds.
 __device__ __forceinline__ void store_block(const Params &p, const StepLds &S, float *Wg, double *theta, int g,
                                             int tid, int nt)
 {

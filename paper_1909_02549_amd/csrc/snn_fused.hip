@@ -56,9 +56,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
         uint32_t rw[4];
         const uint32_t cnt = s.cin[b];
         const uint16_t *row = s.lin + (size_t)b * p.n_in_pad;
-        const uint4 h = *reinterpret_cast<const uint4 *>(row);
+        uint4 h[kListHead];
+        load_heads<kListHead>(row, h);
         load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
-        gather8(row, (int)cnt, make_uint2(h.x, h.y), make_uint2(h.z, h.w), 8, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, 0);
+        gather_pre<kListHead>(row, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, 0);
         neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, ve, vi, rw);
         store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         if (PREC != PREC_FP32 && p.learn) {
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     }
     __syncthreads();
 
-    plasticity_all<false, 16, false, true>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
+    plasticity_all<false, 16, true>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);

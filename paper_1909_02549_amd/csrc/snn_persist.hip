@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
         if (p.learn) {
             __syncthreads();
-            plasticity_all<true, 16, false, PREC != PREC_FP8>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
+            plasticity_all<true, 16, true, 2>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
                                      ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC);
             __syncthreads();
             colsums_theta(p, S, tid, nt);

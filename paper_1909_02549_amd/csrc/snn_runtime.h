@@ -47,19 +47,27 @@ struct snn_net {
     uint32_t cap_chunk = kChunk; // steps the buffers hold at capacity
     uint8_t *flags_mask = nullptr;
 
-    // optional per-kernel timing with HIP events on the handle's stream
+    // optional per-kernel timing with HIP events on the handle's stream: one
+    // event pair brackets each run of consecutive launches of one kernel (a
+    // span), so the events add nothing between those launches
     struct KStat {
         std::string name;
         uint64_t launches = 0;
         double total_ms = 0.0;
     };
+    struct Span {
+        int kid = -1;  // kernel of the open span, -1: none open
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        uint64_t launches = 0;
+    };
     bool prof = false;
     std::vector<KStat> kstats;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    Span span;
+    std::vector<Span> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
     int kstat_id(const char *name);
-    std::pair<hipEvent_t, hipEvent_t> prof_begin();
-    void prof_end(int id, std::pair<hipEvent_t, hipEvent_t> ev);
+    void prof_open(int kid);  // before a launch of kernel kid
+    void prof_close();        // before stream work that is not such a launch
     snn_status prof_flush();
 
     uint64_t gstep = 0;  // steps since the state was initialised

@@ -35,17 +35,17 @@ static snn_status fail(snn_status st, const std::string &msg)
             return fail(SNN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
-// Launch a kernel on the handle's stream; with profiling on, bracket it with
-// a pair of HIP events on the same stream and account it under `name`.
+// Launch a kernel on the handle's stream; with profiling on, account it under
+// `name` (the launch joins the open span of that kernel or opens a new one).
 #define SNN_LAUNCH(kname_, kern, grid, block, shmem, ...)                                                  \
     do {                                                                                                \
         if (this->prof) {                                                                               \
             static thread_local int kid_ = -1;                                                          \
             if (kid_ < 0 || kid_ >= (int)this->kstats.size() || this->kstats[kid_].name != (kname_))      \
                 kid_ = this->kstat_id(kname_);                                                            \
-            auto ev_ = this->prof_begin();                                                              \
+            this->prof_open(kid_);                                                                      \
             hipLaunchKernelGGL(kern, grid, block, shmem, this->stream, __VA_ARGS__);                    \
-            this->prof_end(kid_, ev_);                                                                  \
+            this->span.launches += 1;                                                                   \
         } else {                                                                                        \
             hipLaunchKernelGGL(kern, grid, block, shmem, this->stream, __VA_ARGS__);                    \
         }                                                                                               \
@@ -212,43 +212,45 @@ int snn_net::kstat_id(const char *name)
     return (int)kstats.size() - 1;
 }
 
-std::pair<hipEvent_t, hipEvent_t> snn_net::prof_begin()
+void snn_net::prof_open(int kid)
 {
+    if (span.kid == kid) return;
+    prof_close();
+    if (evpool.empty() && pending.size() >= 4096) prof_flush();
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (!evpool.empty()) {
         ev = evpool.back();
         evpool.pop_back();
     } else {
-        if (pending.size() >= 4096) prof_flush();
-        if (!evpool.empty()) {
-            ev = evpool.back();
-            evpool.pop_back();
-        } else {
-            (void)hipEventCreate(&ev.first);
-            (void)hipEventCreate(&ev.second);
-        }
+        (void)hipEventCreate(&ev.first);
+        (void)hipEventCreate(&ev.second);
     }
     (void)hipEventRecord(ev.first, stream);
-    return ev;
+    span.kid = kid;
+    span.ev = ev;
+    span.launches = 0;
 }
 
-void snn_net::prof_end(int id, std::pair<hipEvent_t, hipEvent_t> ev)
+void snn_net::prof_close()
 {
-    (void)hipEventRecord(ev.second, stream);
-    pending.push_back({id, ev});
+    if (span.kid < 0) return;
+    (void)hipEventRecord(span.ev.second, stream);
+    pending.push_back(span);
+    span.kid = -1;
 }
 
 snn_status snn_net::prof_flush()
 {
+    prof_close();
     if (pending.empty()) return SNN_OK;
     HIP_TRY(hipStreamSynchronize(stream));
-    for (auto &pe : pending) {
+    for (auto &sp : pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
-            kstats[pe.first].launches += 1;
-            kstats[pe.first].total_ms += ms;
+        if (hipEventElapsedTime(&ms, sp.ev.first, sp.ev.second) == hipSuccess) {
+            kstats[sp.kid].launches += sp.launches;
+            kstats[sp.kid].total_ms += ms;
         }
-        evpool.push_back(pe.second);
+        evpool.push_back(sp.ev);
     }
     pending.clear();
     return SNN_OK;
@@ -497,7 +499,9 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&bitsT, (size_t)(ch + 1) * p.n_in_pad * bw * 4);
         A((void **)&lin, (size_t)(ch + 1) * B * p.n_in_pad * 2);
         A((void **)&cin, (size_t)(ch + 1) * B * 4);
-        A((void **)&lt, (size_t)(ch + 1) * p.n_in_pad * lts * 2);
+        // (+64 bytes: list heads are read as 64-byte runs, also from the
+        // last list when lists hold fewer than 32 entries)
+        A((void **)&lt, (size_t)(ch + 1) * p.n_in_pad * lts * 2 + 64);
         A((void **)&ct, (size_t)(ch + 1) * p.n_in_pad * 4);
         A((void **)&flags_mask, B);
         if (e != hipSuccess) {
@@ -755,6 +759,7 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
 {
     const int slot = pargs_next;
     pargs_next = (pargs_next + 1) % kArgSlots;
+    if (prof) prof_close();
     HIP_TRY(hipEventSynchronize(pargs_ev[slot]));
     PersistArgs *h = reinterpret_cast<PersistArgs *>(pargs_host) + slot;
     PersistArgs *d = reinterpret_cast<PersistArgs *>(pargs_dev) + slot;
@@ -786,15 +791,10 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
         persist_attr_bytes[p.prec] = lds;
     }
     void *kargs[] = {(void *)&d};
-    std::pair<hipEvent_t, hipEvent_t> ev{};
-    int kid = -1;
-    if (prof) {
-        kid = kstat_id("persistent");
-        ev = prof_begin();
-    }
+    if (prof) prof_open(kstat_id("persistent"));
     HIP_TRY(hipLaunchCooperativeKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
                                        (unsigned)lds, stream));
-    if (prof) prof_end(kid, ev);
+    if (prof) span.launches += 1;
     gstep += (uint64_t)steps;
     return SNN_OK;
 }
