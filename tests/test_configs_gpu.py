@@ -1,0 +1,169 @@
+"""GPU parity on the other workloads at their largest sizes.
+
+- Batch scaling: 1000 Poisson inputs at 20 Hz -> 1000 LIF neurons, dense
+  W ~ N(0.05, 0.02^2), no learning, T = 1000, B = 4096 (the top of the sweep):
+  every path runs the whole batch; the oracle runs a sample of it (samples are
+  independent without learning).
+- 784 -> 400/400 Diehl & Cook at B = 1024 (the top of its sweep) with each
+  batch reduction: the whole batch in the oracle through the first spike
+  burst, weights and thresholds compared on every column whose excitatory
+  raster agrees everywhere.
+- Serving: the frozen 784 -> 1600/1600 network, requests of T in
+  {100, 250, 500} served concurrently; each request's spike counts against
+  the oracle run of that sample alone.
+"""
+import numpy as np
+import pytest
+
+from paper_1909_02549_amd import inputs
+from test_parity_gpu import RASTER_AGREE, V_RTOL, V_TOL, W_ATOL, W_RTOL, first_divergence, torch_cuda  # noqa: F401
+from test_serve_gpu import wait_all
+
+pytestmark = pytest.mark.gpu
+
+SCALE_SEL = np.array([0, 1, 777, 2048, 4095])
+
+
+@pytest.fixture(scope="module")
+def scaling_oracle(oracle_mod):
+    wl = inputs.workload("scale")
+    W = inputs.normal_weights(1000, 1000, wl["wmean"], wl["wstd"], 0)
+    ids = inputs.sample_ids(4096)
+    ref = oracle_mod.OracleNet(wl["cfg"], W.astype(np.float64)).run(None, ids[SCALE_SEL], 1000,
+                                                                       record=("exc", "v_exc", "counts"))
+    return wl, W, ids, ref
+
+
+@pytest.mark.parametrize("path", ["auto", "plain", "fused", "persistent", "mfma"])
+def test_scaling_b4096_sampled(torch_cuda, scaling_oracle, path):
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    wl, W, ids, ref = scaling_oracle
+    cfg, T = wl["cfg"], 1000
+    net = Net(cfg, max_batch=4096, path=path)
+    net.snn_set_weights(W)
+    out = net.snn_run(None, torch.from_numpy(ids.astype(np.int64)).cuda(), T, record=("exc", "counts"))
+    torch.cuda.synchronize()
+    used = net.snn_last_path()
+    sel_d = torch.from_numpy(SCALE_SEL).cuda()
+    gexc = unpack_bits(out["exc"].index_select(1, sel_d).cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2)
+    gcounts = out["counts"].index_select(0, sel_d).cpu().numpy()
+    net.close()
+    if path in ("plain", "fused", "mfma"):
+        assert used == path
+    assert ref["exc"].sum() > 1000
+    agree = (gexc == ref["exc"]).mean()
+    assert agree >= RASTER_AGREE, f"raster agreement {agree}"
+    count_agree = (gcounts == ref["counts"]).mean()
+    assert count_agree >= RASTER_AGREE, f"spike-count agreement {count_agree}"
+
+
+@pytest.mark.parametrize("path", ["auto", "plain", "fused", "persistent", "mfma"])
+def test_scaling_voltages(torch_cuda, oracle_mod, scaling_oracle, path):
+    """Voltages of the sampled samples up to their first raster divergence
+    (B = 512, T = 200: the recorded voltages stay small)."""
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    wl, W, ids_all, ref_all = scaling_oracle
+    cfg, T, B = wl["cfg"], 200, 512
+    ids = ids_all[:B]
+    sel = np.array([0, 1, 300, 511])
+    net = Net(cfg, max_batch=B, path=path)
+    net.snn_set_weights(W)
+    out = net.snn_run(None, torch.from_numpy(ids.astype(np.int64)).cuda(), T, record=("exc", "v_exc"))
+    torch.cuda.synchronize()
+    net.close()
+    gexc = unpack_bits(out["exc"].cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2)[sel]
+    gv = out["v_exc"].cpu().numpy().transpose(1, 0, 2)[sel]
+    ref = oracle_mod.OracleNet(cfg, W.astype(np.float64)).run(None, ids[sel], T, record=("exc", "v_exc"))
+    for r in range(len(sel)):
+        d = np.nonzero((gexc[r] != ref["exc"][r]).any(axis=1))[0]
+        t_div = int(d[0]) if len(d) else T
+        assert t_div > 20
+        vr = ref["v_exc"][r, :t_div]
+        dv = np.abs(gv[r, :t_div] - vr)
+        assert not (dv > V_TOL + V_RTOL * np.abs(vr)).any(), f"sample {sel[r]}: voltage error {dv.max()} mV"
+
+
+DC400_T = 30
+
+
+@pytest.fixture(scope="module")
+def dc400_inputs():
+    wl = inputs.workload("dc400")
+    B = 1024
+    return wl, inputs.stroke_images(B, 5, wl["density"]), inputs.sample_ids(B), inputs.uniform_weights(
+        784, 400, wl["wlo"], wl["whi"], 3)
+
+
+_dc400_refs = {}
+
+
+@pytest.mark.parametrize("path", ["auto", "plain", "fused", "persistent", "mfma"])
+@pytest.mark.parametrize("reduce", ["mean", "sum", "max"])
+def test_dc400_b1024_learning(torch_cuda, oracle_mod, dc400_inputs, reduce, path):
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    wl, imgs, ids, W = dc400_inputs
+    cfg = inputs.dc_config(400, reduce=reduce)
+    if reduce not in _dc400_refs:
+        orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
+        ref = orc.run(imgs, ids, DC400_T, record=("in", "exc", "inh", "v_exc"))
+        ref["W"], ref["theta"] = orc.W, orc.theta
+        _dc400_refs[reduce] = ref
+    ref = _dc400_refs[reduce]
+    net = Net(cfg, max_batch=len(ids), path=path)
+    net.snn_set_weights(W)
+    out = net.snn_run(torch.from_numpy(imgs).cuda(), torch.from_numpy(ids.astype(np.int64)).cuda(), DC400_T,
+                      record=("in", "exc", "inh", "v_exc"))
+    torch.cuda.synchronize()
+    g = {"in": unpack_bits(out["in"].cpu().numpy(), 784).transpose(1, 0, 2),
+         "exc": unpack_bits(out["exc"].cpu().numpy(), 400).transpose(1, 0, 2),
+         "inh": unpack_bits(out["inh"].cpu().numpy(), 400).transpose(1, 0, 2),
+         "v_exc": out["v_exc"].cpu().numpy().transpose(1, 0, 2),
+         "W": net.snn_get_weights(), "theta": net.snn_get_theta()}
+    used = net.snn_last_path()
+    net.close()
+    if path != "auto":
+        assert used == path
+    assert np.array_equal(g["in"], ref["in"]), "input spikes not bit-exact"
+    assert ref["exc"].sum() > 10000
+    for k in ("exc", "inh"):
+        agree = (g[k] == ref[k]).mean()
+        assert agree >= RASTER_AGREE, f"{k} raster agreement {agree}"
+    t_div = first_divergence(g, ref)
+    if t_div > 0:
+        vr = ref["v_exc"][:, :t_div]
+        dv = np.abs(g["v_exc"][:, :t_div] - vr)
+        assert not (dv > V_TOL + V_RTOL * np.abs(vr)).any(), f"voltage error {dv.max()} mV before step {t_div}"
+    same = (g["exc"] == ref["exc"]).all(axis=(0, 1))
+    assert same.mean() >= 0.9, f"only {same.mean():.3f} of the columns agree in every entry"
+    err = np.abs(g["W"][:, same] - ref["W"][:, same])
+    bad = err > W_RTOL * np.abs(ref["W"][:, same]) + W_ATOL
+    assert not bad.any(), f"weights of agreeing columns: max err {err.max()}"
+    np.testing.assert_allclose(g["theta"][same], ref["theta"][same], rtol=1e-6, atol=1e-12)
+
+
+def test_serving_dc1600_requests_against_oracle(torch_cuda, oracle_mod):
+    from paper_1909_02549_amd.snn import Net, Server
+    wl = inputs.workload("serve")
+    cfg = wl["cfg"]
+    W = inputs.column_scaled(inputs.uniform_weights(cfg["n_in"], cfg["n_exc"], wl["wlo"], wl["whi"], 0), 78.4)
+    net = Net(cfg, max_batch=1, path="auto")
+    net.snn_set_weights(W)
+    n = 24
+    imgs = inputs.stroke_images(n, 4242, wl["density"])
+    Ts = inputs.request_durations(n, seed=1)
+    assert set(int(t) for t in Ts) <= {100, 250, 500}
+    srv = Server(net, max_slots=64, chunk_steps=25)
+    rids = [srv.snn_serve_submit(imgs[k], 7000 + k, int(Ts[k])) for k in range(n)]
+    res = wait_all(srv, rids, timeout=120.0)
+    st = srv.snn_serve_stats()
+    srv.snn_serve_destroy()
+    assert st["completed"] == n and st["peak_active"] > 1
+    agree = []
+    for k, r in enumerate(rids):
+        orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
+        ref = orc.run(imgs[k:k + 1], np.array([7000 + k], np.uint64), int(Ts[k]), record=("counts",))
+        agree.append((ref["counts"][0] == res[r][0]).mean())
+    assert min(agree) >= 0.99, agree
