@@ -13,7 +13,7 @@
 //   input spikes of step t: bits[t * bits_stride + b * in_words + w] (bit
 //   i % 32 of word i / 32) and the transpose bitsT[t][i][bw] (bit b % 32 of
 //   word b / 32).
-//   presynaptic traces x_pre[t & 1][b][i] (buffer stride Bs rows);
+//   presynaptic traces x_pre[t % 3][b][i] (buffer stride Bs rows);
 //   inhibitory spike counts per sample C[t % 3][b] (slot stride Bs).
 #pragma once
 #include <stdint.h>

@@ -66,11 +66,11 @@ struct ChunkPtrs {
     const uint32_t *cin;
     const uint16_t *lt;
     const uint32_t *ct;
-    float *xpre;           // 2 x B x n_in_pad, x_pre(s) in buffer s & 1
+    float *xpre;           // 3 x B x n_in_pad, x_pre(s) in buffer s % 3
     uint32_t *C;           // 3 x B, inhibitory counts of step s in slot s % 3
     int steps;             // steps to run
     int has_next;          // inputs of step `steps` are encoded (x_pre ahead)
-    int par0, mod0;        // (s & 1), (s % 3) of the first step
+    int mod0;              // s % 3 of the first step
     int k0;                // output index of the first step
 };
 
@@ -216,10 +216,12 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
     const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
     const int i2 = k0 + 2 < cnt ? (int)(q.y & 0xFFFFu) : zero_row;
     const int i3 = k0 + 3 < cnt ? (int)(q.y >> 16) : zero_row;
-    const float4 *r0 = reinterpret_cast<const float4 *>(rows + i0 * jbp + c0);
-    const float4 *r1 = reinterpret_cast<const float4 *>(rows + i1 * jbp + c0);
-    const float4 *r2 = reinterpret_cast<const float4 *>(rows + i2 * jbp + c0);
-    const float4 *r3 = reinterpret_cast<const float4 *>(rows + i3 * jbp + c0);
+    // row offsets with the 24-bit multiply (full rate; indices and strides
+    // are far below 2^24)
+    const float4 *r0 = reinterpret_cast<const float4 *>(rows + __mul24(i0, jbp) + c0);
+    const float4 *r1 = reinterpret_cast<const float4 *>(rows + __mul24(i1, jbp) + c0);
+    const float4 *r2 = reinterpret_cast<const float4 *>(rows + __mul24(i2, jbp) + c0);
+    const float4 *r3 = reinterpret_cast<const float4 *>(rows + __mul24(i3, jbp) + c0);
     const float4 a0 = round4(prec, r0[0]), b0 = round4(prec, r0[1]);
     const float4 a1 = round4(prec, r1[0]), b1 = round4(prec, r1[1]);
     const float4 a2 = round4(prec, r2[0]), b2 = round4(prec, r2[1]);

@@ -316,6 +316,7 @@ __global__ void k_reset(Params p, float *__restrict__ v_exc, float *__restrict__
         if (!mask || mask[b]) {
             x_pre[t] = 0.f;
             x_pre[(size_t)p.Bs * p.n_in_pad + t] = 0.f;
+            x_pre[2 * (size_t)p.Bs * p.n_in_pad + t] = 0.f;
         }
     }
     if (t < (size_t)p.B) {

@@ -6,9 +6,16 @@
 // state of its 8 neurons of one sample in registers for the whole launch
 // (so B * JBP / 8 <= threads per block).  The
 // only cross-workgroup exchange per step is the per-sample inhibitory spike
-// count (device atomics) and the presynaptic traces of the next step; a grid
-// barrier separates the steps.  Its wait is bounded: a wait that exceeds the
-// bound sets an error flag and ends the launch instead of spinning forever.
+// count (device atomics) and the presynaptic traces of the next step.  A
+// grid barrier separates the steps, split in two: a workgroup arrives as soon
+// as it has published both for step t, then runs step t's plasticity (which
+// reads only its own block, its own neurons' traces and x_pre(t), complete
+// since the previous barrier) and waits before step t + 1's neuron update.
+// So the plasticity hides the barrier's latency and most of the imbalance
+// between workgroups.  No workgroup can then be more than one step ahead of
+// another, which three x_pre buffers and three count slots cover.  The wait
+// is bounded: a wait that exceeds the bound sets an error flag and ends the
+// launch instead of spinning forever.
 #include <hip/hip_runtime.h>
 
 #include "snn_dev.h"
@@ -22,17 +29,22 @@ constexpr uint32_t kSpinLimit = 1u << 25;  // about a second of s_sleep(1) polls
 
 size_t persist_lds_bytes(const Params &p) { return FusedLds(p, kPersistThreads).total; }
 
-// Grid-wide barrier between steps.  Data another workgroup reads after the
-// barrier is written with agent-scope atomic stores or atomic RMWs; every
-// wave waits until its memory operations have completed, then one thread per
-// workgroup arrives and polls the counter.  Returns false if the wait timed
-// out (the launch must end).
-__device__ __forceinline__ bool grid_barrier(const PersistSync &sy, uint32_t target, int *abort_lds)
+// Grid-wide barrier between steps, in two halves.  Arrive: every wave waits
+// until its memory operations have completed (data another workgroup reads
+// after the barrier is written with agent-scope atomic stores or RMWs), then
+// one thread per workgroup increments the counter.  Wait: one thread polls
+// until the counter reaches target; returns false if the wait timed out (the
+// launch must end).
+__device__ __forceinline__ void grid_arrive(const PersistSync &sy)
 {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(sy.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool grid_wait(const PersistSync &sy, uint32_t target, int *abort_lds)
+{
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(sy.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
         int ok = 1;
         while (__hip_atomic_load(sy.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -100,11 +112,12 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
     __syncthreads();
 
     for (int k = 0; k < ch.steps; ++k) {
-        const int par = (ch.par0 + k) & 1;
         const int mod = (ch.mod0 + k) % 3;
-        const float *xpre = ch.xpre + (size_t)par * p.Bs * p.n_in_pad;
-        float *xpre_nx = ch.xpre + (size_t)(par ^ 1) * p.Bs * p.n_in_pad;
+        const float *xpre = ch.xpre + (size_t)mod * p.Bs * p.n_in_pad;
+        float *xpre_nx = ch.xpre + (size_t)((mod + 1) % 3) * p.Bs * p.n_in_pad;
 
+        // counts of step t - 1 and x_pre(t) from every workgroup
+        if (k > 0 && !grid_wait(sy, (uint32_t)k * gridDim.x, &abort_lds)) return;
         step_begin<true>(p, S, ch.C + (size_t)((mod + 2) % 3) * p.Bs, tid, nt);
         __syncthreads();
 #pragma unroll
@@ -118,15 +131,15 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
+        if (p.learn && (k + 1 < ch.steps || ch.has_next))
+            xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
+        grid_arrive(sy);
         if (p.learn) {
-            __syncthreads();
             plasticity_all<true, 16, true, 2>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
-                                     ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC);
+                                              ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC);
             __syncthreads();
             colsums_theta(p, S, tid, nt);
             if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);
-            if (k + 1 < ch.steps || ch.has_next)
-                xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
         }
         if (k + 1 < ch.steps) {
 #pragma unroll
@@ -136,7 +149,6 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
                 hin[u] = *reinterpret_cast<const uint4 *>(ch.lin + ((size_t)(k + 1) * p.B + tb[u]) * p.n_in_pad);
             }
         }
-        if (!grid_barrier(sy, (uint32_t)(k + 1) * gridDim.x, &abort_lds)) return;
     }
 
     // epilogue: state, weights (normalised) and thresholds back to HBM

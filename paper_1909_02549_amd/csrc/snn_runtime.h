@@ -35,7 +35,7 @@ struct snn_net {
     uint32_t cap_B = 0, cur_B = 0;
     float *v_exc = nullptr, *v_inh = nullptr, *x_post = nullptr, *I = nullptr;
     uint16_t *rf = nullptr;
-    float *x_pre = nullptr;      // 2 x B x n_in_pad
+    float *x_pre = nullptr;      // 3 x B x n_in_pad (x_pre of step s in buffer s % 3)
     uint32_t *C = nullptr;       // 3 x B
     uint32_t *bits = nullptr;    // (chunk + 1) steps of input spikes, per sample
     uint32_t *bitsT = nullptr;   //   and per input

@@ -112,7 +112,7 @@ static size_t state_bytes(const Params &p, uint32_t B)
     s += (size_t)(chunk + 1) * ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2;  // lists
     s += (size_t)(chunk + 1) * ((size_t)B + p.n_in_pad) * 4;                                       // lengths
     s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
-    s += 2 * (size_t)B * p.n_in_pad * 4;            // x_pre
+    s += 3 * (size_t)B * p.n_in_pad * 4;            // x_pre (three steps)
     s += 3 * (size_t)B * 4;                         // C
     s += (size_t)(chunk + 1) * (B * p.in_words + 3) * 4;  // bits
     s += (size_t)(chunk + 1) * p.n_in_pad * bw * 4; // bitsT
@@ -491,7 +491,7 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&x_post, ns * 4);
         A((void **)&I, ns * 4);
         A((void **)&rf, ns * 2);
-        A((void **)&x_pre, 2 * (size_t)B * p.n_in_pad * 4);
+        A((void **)&x_pre, 3 * (size_t)B * p.n_in_pad * 4);
         A((void **)&C, 3 * (size_t)B * 4);
         const uint32_t ch = chunk_steps(p, B);
         const size_t lts = (B + 7) & ~7u;
@@ -564,9 +564,8 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o, bool mfma)
 {
     const uint32_t *bits_t = bits + (size_t)kk * p.bits_stride;
     const uint32_t *bitsT_t = bitsT + (size_t)kk * p.n_in_pad * p.bwords;
-    const int cur = (int)(gstep & 1);
-    float *xcur = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
-    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
+    float *xcur = x_pre + (size_t)(gstep % 3) * p.Bs * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)((gstep + 2) % 3) * p.Bs * p.n_in_pad;
     uint32_t *Ccur = C + (size_t)(gstep % 3) * p.Bs;
     uint32_t *Cprev = C + (size_t)((gstep + 2) % 3) * p.Bs;
     uint32_t *Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
@@ -695,9 +694,8 @@ snn_status snn_net::episode_body(int path, const uint8_t *images, const uint64_t
 
 snn_status snn_net::xpre_first(const uint32_t *bits_t)
 {
-    const int cur = (int)(gstep & 1);
-    float *xcur = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
-    const float *xprev = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
+    float *xcur = x_pre + (size_t)(gstep % 3) * p.Bs * p.n_in_pad;
+    const float *xprev = x_pre + (size_t)((gstep + 2) % 3) * p.Bs * p.n_in_pad;
     SNN_LAUNCH("xpre", k_xpre, dim3(blocks_for((size_t)p.B * p.n_in_pad, 256)), dim3(256), 0, p, bits_t, xprev, xcur);
     HIP_TRY(hipGetLastError());
     return SNN_OK;
@@ -710,7 +708,6 @@ bool snn_net::fused_ok() const
 
 snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
 {
-    const int cur = (int)(gstep & 1);
     StepPtrs s;
     s.bits = bits + (size_t)kk * p.bits_stride;
     s.bits_next = has_next ? bits + (size_t)(kk + 1) * p.bits_stride : nullptr;
@@ -718,8 +715,8 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.cin = cin + (size_t)kk * p.B;
     s.lt = lt + (size_t)kk * p.n_in_pad * p.lt_stride;
     s.ct = ct + (size_t)kk * p.n_in_pad;
-    s.xpre = x_pre + (size_t)cur * p.Bs * p.n_in_pad;
-    s.xpre_next = x_pre + (size_t)(cur ^ 1) * p.Bs * p.n_in_pad;
+    s.xpre = x_pre + (size_t)(gstep % 3) * p.Bs * p.n_in_pad;
+    s.xpre_next = x_pre + (size_t)((gstep + 1) % 3) * p.Bs * p.n_in_pad;
     s.Ccur = C + (size_t)(gstep % 3) * p.Bs;
     s.Cprev = C + (size_t)((gstep + 2) % 3) * p.Bs;
     s.Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
@@ -775,7 +772,6 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     c.C = C;
     c.steps = steps;
     c.has_next = has_next ? 1 : 0;
-    c.par0 = (int)(gstep & 1);
     c.mod0 = (int)(gstep % 3);
     c.k0 = k0;
     h->sy = PersistSync{bar, err};
