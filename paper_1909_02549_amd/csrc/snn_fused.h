@@ -51,6 +51,8 @@ struct StepPtrs {
     const uint32_t *cin;        //   and their lengths
     const uint16_t *lt;         // per-input sample spike lists of step t
     const uint32_t *ct;         //   and their lengths
+    const uint16_t *ord_s;      // samples by decreasing list length (step t)
+    const uint16_t *ord_in;     // inputs by decreasing list length (step t)
     const float *xpre;          // x_pre(t), B x n_in_pad
     float *xpre_next;           // x_pre(t + 1)
     const uint32_t *Cprev;      // inhibitory spike counts of step t - 1
@@ -66,6 +68,7 @@ struct ChunkPtrs {
     const uint32_t *cin;
     const uint16_t *lt;
     const uint32_t *ct;
+    const uint16_t *ord_in;  // per step: inputs by decreasing list length
     float *xpre;           // 3 x B x n_in_pad, x_pre(s) in buffer s % 3
     uint32_t *C;           // 3 x B, inhibitory counts of step s in slot s % 3
     int steps;             // steps to run
@@ -97,6 +100,10 @@ template <int PREC>
 __global__ void k_persist(const PersistArgs *args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 1024;
+__global__ void k_order(Params p, const uint32_t *cin, const uint32_t *ct, uint16_t *ord_s, uint16_t *ord_in,
+                        int with_t);
 
 // ---------------------------------------------------------------------------
 // device building blocks
@@ -528,22 +535,28 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 
 // Phase C over all input rows of the block: split rows (Halves, blocks of
 // two or more column groups) or whole rows per thread; a thread loads its
-// next row's list head before working on the current row.
+// next row's list head before working on the current row.  Rows are taken in
+// the order `ord` (inputs by decreasing sample-list length), so the lanes of
+// a wave walk lists of similar length.
 template <bool Coherent, int XR, bool Halves, int NH = kListHead>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
-                                               const uint32_t *ct, const float *xpre, int tid, int nt, int prec,
-                                               int prec_d)
+                                               const uint32_t *ct, const uint16_t *ord, const float *xpre, int tid,
+                                               int nt, int prec, int prec_d)
 {
     const int ucnt = (int)S.ulist[p.B];
     const int ncg = p.jbp >> 3;
     if (Halves && ncg >= 2) {
+        // item q: row ord[(q / 128) * 64 + q % 64], column groups 2 hf and
+        // 2 hf + 1 with hf = (q / 64) % 2, the same in every lane of a wave
+        // (nt is a multiple of 128)
         const int nrow = (p.n_in + 63) & ~63;
         for (int q = tid; q < 2 * nrow; q += nt) {
             const int hf = (q >> 6) & 1;
-            const int i = ((q >> 7) << 6) | (q & 63);
+            const int r = ((q >> 7) << 6) | (q & 63);
             const int cg0 = 2 * hf;
             const int ng = min(2, ncg - cg0);
-            if (i >= p.n_in || ng <= 0) continue;
+            if (r >= p.n_in || ng <= 0) continue;
+            const int i = ord[r];
             const uint32_t cnt = ct[i];
             uint4 h[NH];
             load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
@@ -554,24 +567,28 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
     }
     uint32_t colany = 0u;
     for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
-    int i = tid;
+    int r = tid;
     uint32_t cnt_n = 0u;
     uint4 head_n = make_uint4(0u, 0u, 0u, 0u);
-    if (i < p.n_in) {
-        cnt_n = ct[i];
-        head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)i * p.lt_stride);
+    int i_n = 0;
+    if (r < p.n_in) {
+        i_n = ord[r];
+        cnt_n = ct[i_n];
+        head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)i_n * p.lt_stride);
     }
-    while (i < p.n_in) {
+    while (r < p.n_in) {
+        const int i = i_n;
         const uint32_t cnt = cnt_n;
         const uint4 head = head_n;
-        const int in = i + nt;
-        if (in < p.n_in) {
-            cnt_n = ct[in];
-            head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)in * p.lt_stride);
+        const int rn = r + nt;
+        if (rn < p.n_in) {
+            i_n = ord[rn];
+            cnt_n = ct[i_n];
+            head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)i_n * p.lt_stride);
         }
         plasticity_row_cg<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
                                         prec, prec_d);
-        i = in;
+        r = rn;
     }
 }
 

@@ -49,8 +49,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     const size_t sbase = (size_t)g * p.Bs * JBP;
     const int nv_blk = min(JB, p.n_exc - g * JB);
     for (int q = tid; q < p.B * ncg; q += nt) {
-        const int b = q / ncg;
-        const int c0 = 8 * (q - b * ncg);
+        const int qb = q / ncg;
+        const int b = s.ord_s[qb];
+        const int c0 = 8 * (q - qb * ncg);
         const size_t n0 = sbase + (size_t)b * JBP + c0;
         float ve[8], vi[8], acc[8];
         uint32_t rw[4];
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     }
     __syncthreads();
 
-    plasticity_all<false, 16, true>(p, S, s.lt, s.ct, s.xpre, tid, nt, PREC, 0);
+    plasticity_all<false, 16, true>(p, S, s.lt, s.ct, s.ord_in, s.xpre, tid, nt, PREC, 0);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);
@@ -122,6 +123,53 @@ __global__ void k_lists(Params p, const uint32_t *__restrict__ bits, const uint3
             }
         }
         ct[(size_t)t * p.n_in_pad + q] = n;
+    }
+}
+
+}  // namespace snn
+
+namespace snn {
+
+// Work order of one step's list walks: the samples by decreasing input-list
+// length cin and the inputs by decreasing sample-list length ct (a counting
+// sort, lengths above kOrderBins - 2 sharing the first bin; order within a
+// bin is arbitrary).  A wave of the step kernels takes consecutive entries,
+// so its lanes walk lists of similar length.  Which thread handles which
+// sample or input changes nothing in the results.  One workgroup per step.
+__global__ __launch_bounds__(kOrderThreads) void k_order(Params p, const uint32_t *__restrict__ cin,
+                                                          const uint32_t *__restrict__ ct, uint16_t *__restrict__ ord_s,
+                                                          uint16_t *__restrict__ ord_in, int with_t)
+{
+    __shared__ uint32_t hist[kOrderBins];
+    __shared__ uint32_t wsum[kOrderThreads / 64];
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    auto bin = [](uint32_t c) { return kOrderBins - 1 - (int)min(c, (uint32_t)(kOrderBins - 1)); };
+    for (int pass = 0; pass < (with_t ? 2 : 1); ++pass) {
+        const int n = pass == 0 ? p.B : p.n_in;
+        const uint32_t *len = pass == 0 ? cin + (size_t)t * p.B : ct + (size_t)t * p.n_in_pad;
+        uint16_t *out = pass == 0 ? ord_s + (size_t)t * p.B : ord_in + (size_t)t * p.n_in_pad;
+        for (int q = tid; q < kOrderBins; q += kOrderThreads) hist[q] = 0u;
+        __syncthreads();
+        for (int q = tid; q < n; q += kOrderThreads) atomicAdd(&hist[bin(len[q])], 1u);
+        __syncthreads();
+        // exclusive prefix sum over the bins (one bin per thread)
+        const uint32_t v = hist[tid];
+        uint32_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        uint32_t base = 0u;
+        for (int w = 0; w < wv; ++w) base += wsum[w];
+        hist[tid] = base + x - v;
+        __syncthreads();
+        for (int q = tid; q < n; q += kOrderThreads) out[atomicAdd(&hist[bin(len[q])], 1u)] = (uint16_t)q;
+        __syncthreads();
     }
 }
 

@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
         grid_arrive(sy);
         if (p.learn) {
             plasticity_all<true, 16, true, 2>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
-                                              ch.ct + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC);
+                                              ch.ct + (size_t)k * p.n_in_pad, ch.ord_in + (size_t)k * p.n_in_pad,
+                                              xpre, tid, nt, PREC, PREC);
             __syncthreads();
             colsums_theta(p, S, tid, nt);
             if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);

@@ -43,6 +43,8 @@ struct snn_net {
     uint32_t *cin = nullptr;
     uint16_t *lt = nullptr;      // (chunk + 1) x n_in_pad x lt_stride sample lists
     uint32_t *ct = nullptr;
+    uint16_t *ord_s = nullptr;   // (chunk + 1) x B samples by decreasing cin
+    uint16_t *ord_in = nullptr;  // (chunk + 1) x n_in_pad inputs by decreasing ct
     uint32_t chunk = kChunk;     // steps per encoder launch for the current batch
     uint32_t cap_chunk = kChunk; // steps the buffers hold at capacity
     uint8_t *flags_mask = nullptr;

@@ -111,6 +111,7 @@ static size_t state_bytes(const Params &p, uint32_t B)
     size_t s = 0;
     s += (size_t)(chunk + 1) * ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2;  // lists
     s += (size_t)(chunk + 1) * ((size_t)B + p.n_in_pad) * 4;                                       // lengths
+    s += (size_t)(chunk + 1) * ((size_t)B + p.n_in_pad) * 2;                                       // orders
     s += ns * (4 + 4 + 4 + 4 + 2);                 // v_exc, v_inh, x_post, I, rf
     s += 3 * (size_t)B * p.n_in_pad * 4;            // x_pre (three steps)
     s += 3 * (size_t)B * 4;                         // C
@@ -280,11 +281,12 @@ snn_net::~snn_net()
 void snn_net::free_state()
 {
     for (void *q : {(void *)v_exc, (void *)v_inh, (void *)x_post, (void *)I, (void *)rf, (void *)x_pre, (void *)C,
-                    (void *)bits, (void *)bitsT, (void *)flags_mask, (void *)lin, (void *)cin, (void *)lt, (void *)ct})
+                    (void *)bits, (void *)bitsT, (void *)flags_mask, (void *)lin, (void *)cin, (void *)lt, (void *)ct,
+                    (void *)ord_s, (void *)ord_in})
         if (q) (void)hipFree(q);
     v_exc = v_inh = x_post = I = x_pre = nullptr;
     rf = nullptr;
-    lin = lt = nullptr;
+    lin = lt = ord_s = ord_in = nullptr;
     C = bits = bitsT = cin = ct = nullptr;
     flags_mask = nullptr;
     cap_B = 0;
@@ -503,6 +505,8 @@ snn_status snn_net::ensure_state(uint32_t B)
         // last list when lists hold fewer than 32 entries)
         A((void **)&lt, (size_t)(ch + 1) * p.n_in_pad * lts * 2 + 64);
         A((void **)&ct, (size_t)(ch + 1) * p.n_in_pad * 4);
+        A((void **)&ord_s, (size_t)(ch + 1) * B * 2);
+        A((void **)&ord_in, (size_t)(ch + 1) * p.n_in_pad * 2);
         A((void **)&flags_mask, B);
         if (e != hipSuccess) {
             free_state();
@@ -715,6 +719,8 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.cin = cin + (size_t)kk * p.B;
     s.lt = lt + (size_t)kk * p.n_in_pad * p.lt_stride;
     s.ct = ct + (size_t)kk * p.n_in_pad;
+    s.ord_s = ord_s + (size_t)kk * p.B;
+    s.ord_in = ord_in + (size_t)kk * p.n_in_pad;
     s.xpre = x_pre + (size_t)(gstep % 3) * p.Bs * p.n_in_pad;
     s.xpre_next = x_pre + (size_t)((gstep + 1) % 3) * p.Bs * p.n_in_pad;
     s.Ccur = C + (size_t)(gstep % 3) * p.Bs;
@@ -768,6 +774,7 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     c.cin = cin;
     c.lt = lt;
     c.ct = ct;
+    c.ord_in = ord_in;
     c.xpre = x_pre;
     c.C = C;
     c.steps = steps;
@@ -848,6 +855,8 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
             const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
             SNN_LAUNCH("lists", k_lists, dim3((unsigned)((nq + 255) / 256), (unsigned)enc_steps), dim3(256), 0, p,
                        (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, p.learn);
+            SNN_LAUNCH("order", k_order, dim3((unsigned)enc_steps), dim3(kOrderThreads), 0, p, (const uint32_t *)cin,
+                       (const uint32_t *)ct, ord_s, ord_in, p.learn);
             HIP_TRY(hipGetLastError());
             if (k0 == 0 && p.learn) {
                 st = xpre_first(bits);
