@@ -310,7 +310,8 @@ __device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, co
 // acc: column sums of the sample's input spikes over the LDS block (raw,
 // before the pending scale).  Updates the register state, the post traces in
 // LDS, the spike masks and the inhibitory count; writes requested outputs.
-__device__ __forceinline__ void neuron_task(const Params &p, const StepLds &S, const Outs &o, int k, int b, int c0,
+template <class PP>
+__device__ __forceinline__ void neuron_task(const PP &p, const StepLds &S, const Outs &o, int k, int b, int c0,
                                             int j0, int nv, const float *acc, float *ve, float *vi, uint32_t *rw)
 {
     float xp[8];
@@ -323,33 +324,34 @@ __device__ __forceinline__ void neuron_task(const Params &p, const StepLds &S, c
 #pragma unroll
         for (int c = 0; c < 8; ++c) xp[c] = 0.f;
     }
-    uint32_t cm = 0u, se_m = 0u, si_m = 0u;
+    // padding columns (c >= nv) keep their state and never spike; per-lane
+    // conditions are selects, not branches
+    const uint32_t cp = S.cprev[b];
+    uint32_t se_m = 0u, si_m = 0u;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int jl = c0 + c;
-        if (c < nv) {
-            const float I = (float)((double)acc[c] * S.scale[jl]);
-            NeuronState st{ve[c], vi[c], (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu, xp[c]};
-            bool se, si;
-            neuron_update(p, I, S.cprev[b], S.th[jl], st, se, si);
-            ve[c] = st.ve;
-            vi[c] = st.vi;
-            xp[c] = st.xpost;
-            rw[c >> 1] = (rw[c >> 1] & ~(0xFFFFu << (16 * (c & 1)))) | (st.rf << (16 * (c & 1)));
-            se_m |= (se ? 1u : 0u) << c;
-            si_m |= (si ? 1u : 0u) << c;
-            if (p.learn && se) {
-                atomicOr(&S.spk[jl * p.bwords + (b >> 5)], 1u << (b & 31));
-                cm |= 1u << jl;
-            }
-        } else {
-            xp[c] = 0.f;
-        }
+        const float I = (float)((double)acc[c] * S.scale[jl]);
+        NeuronState st{ve[c], vi[c], (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu, xp[c]};
+        bool se, si;
+        neuron_update(p, I, cp, S.th[jl], st, se, si);
+        const bool real = c < nv;
+        ve[c] = real ? st.ve : ve[c];
+        vi[c] = real ? st.vi : vi[c];
+        xp[c] = real ? st.xpost : 0.f;
+        const uint32_t sh = 16u * (uint32_t)(c & 1);
+        rw[c >> 1] = real ? (rw[c >> 1] & ~(0xFFFFu << sh)) | (st.rf << sh) : rw[c >> 1];
+        se_m |= (real && se ? 1u : 0u) << c;
+        si_m |= (real && si ? 1u : 0u) << c;
     }
     if (p.learn) {
         *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0) = make_float4(xp[0], xp[1], xp[2], xp[3]);
         *reinterpret_cast<float4 *>(S.xpost + b * p.ls + c0 + 4) = make_float4(xp[4], xp[5], xp[6], xp[7]);
-        if (cm) atomicOr(&S.colmask[b], cm);
+        if (se_m) {
+            atomicOr(&S.colmask[b], se_m << c0);
+            for (uint32_t m = se_m; m; m &= m - 1u)
+                atomicOr(&S.spk[(c0 + __builtin_ctz(m)) * p.bwords + (b >> 5)], 1u << (b & 31));
+        }
     }
     if (si_m) atomicAdd(&S.cinh[b], (uint32_t)__builtin_popcount(si_m));
     write_outputs8(p, o, k, b, j0, nv, se_m, si_m, ve, vi);

@@ -88,6 +88,21 @@ struct NeuronState {
     float xpost;
 };
 
+// The parameters of the neuron update and its outputs, copied out of Params
+// once per launch by kernels that keep Params in memory, so that the per-neuron
+// code reads them from registers (same member names as Params).
+struct NeuronK {
+    int has_inh, learn, trace_add, n_exc, B, ls, bwords;
+    LifP exc, inh;
+    float w_ei, w_ie, lam_post;
+};
+
+__device__ __forceinline__ NeuronK neuron_consts(const Params &p)
+{
+    return NeuronK{p.has_inh, p.learn, p.trace_add, p.n_exc, p.B, p.ls, p.bwords, p.exc, p.inh, p.w_ei, p.w_ie,
+                   p.lam_post};
+}
+
 // One step of the excitatory adaptive-LIF neuron j and its inhibitory
 // partner for one sample:
 //   I_exc = I_ff + w_ie * (C_inh(t-1) - s_inh(t-1)[j])   (all-but-self)
@@ -95,44 +110,37 @@ struct NeuronState {
 //   v <- v_rest + (v - v_rest) * alpha; if refractory: count down, input
 //   discarded; else v += I, spike when v >= v_th (+ theta), then v_reset and
 //   refrac steps.  Post trace decays and is set on an exc spike.
-__device__ __forceinline__ void neuron_update(const Params &p, float I_ff, uint32_t Cprev, float th_off,
+template <class PP>
+__device__ __forceinline__ void neuron_update(const PP &p, float I_ff, uint32_t Cprev, float th_off,
                                               NeuronState &st, bool &se, bool &si)
 {
+    // both outcomes are computed and selected (no branches on per-lane
+    // conditions); the arithmetic of the taken outcome is unchanged
     const uint32_t re = st.rf & 0xFFu, ri = (st.rf >> 8) & 0xFFu;
     const bool se_prev = (re & RF_SPIKE) != 0u;
     const bool si_prev = (ri & RF_SPIKE) != 0u;
-    uint32_t ce = re & RF_COUNT, ci = ri & RF_COUNT;
+    const uint32_t ce = re & RF_COUNT, ci = ri & RF_COUNT;
     float Ie = I_ff;
     if (p.has_inh) Ie += p.w_ie * (float)((int)Cprev - (int)si_prev);
-    st.ve = p.exc.v_rest + (st.ve - p.exc.v_rest) * p.exc.alpha;
-    se = false;
-    if (ce > 0u) {
-        ce -= 1u;
-    } else {
-        st.ve += Ie;
-        if (st.ve >= p.exc.v_th + th_off) {
-            se = true;
-            st.ve = p.exc.v_reset;
-            ce = (uint32_t)p.exc.refrac;
-        }
-    }
+    const float ved = p.exc.v_rest + (st.ve - p.exc.v_rest) * p.exc.alpha;
+    const float vei = ved + Ie;
+    const bool e_free = ce == 0u;
+    se = e_free && vei >= p.exc.v_th + th_off;
+    st.ve = e_free ? (se ? p.exc.v_reset : vei) : ved;
+    const uint32_t ce2 = e_free ? (se ? (uint32_t)p.exc.refrac : 0u) : ce - 1u;
     si = false;
+    uint32_t ci2 = ci;
     if (p.has_inh) {
         const float Ii = se_prev ? p.w_ei : 0.f;
-        st.vi = p.inh.v_rest + (st.vi - p.inh.v_rest) * p.inh.alpha;
-        if (ci > 0u) {
-            ci -= 1u;
-        } else {
-            st.vi += Ii;
-            if (st.vi >= p.inh.v_th) {
-                si = true;
-                st.vi = p.inh.v_reset;
-                ci = (uint32_t)p.inh.refrac;
-            }
-        }
+        const float vid = p.inh.v_rest + (st.vi - p.inh.v_rest) * p.inh.alpha;
+        const float vii = vid + Ii;
+        const bool i_free = ci == 0u;
+        si = i_free && vii >= p.inh.v_th;
+        st.vi = i_free ? (si ? p.inh.v_reset : vii) : vid;
+        ci2 = i_free ? (si ? (uint32_t)p.inh.refrac : 0u) : ci - 1u;
     }
     if (p.learn) st.xpost = trace_step(st.xpost, p.lam_post, se, p.trace_add);
-    st.rf = (ce | (se ? RF_SPIKE : 0u)) | ((ci | (si ? RF_SPIKE : 0u)) << 8);
+    st.rf = (ce2 | (se ? RF_SPIKE : 0u)) | ((ci2 | (si ? RF_SPIKE : 0u)) << 8);
 }
 
 // Optional per-call outputs of neuron (b, j) at step k of the call.
@@ -152,7 +160,8 @@ __device__ __forceinline__ void write_outputs(const Params &p, const Outs &o, in
 // Outputs of a group of 8 consecutive neurons j0 .. j0+7 of sample b at
 // step k; nv of them are real (the rest padding, never set in the masks).
 // se_m / si_m hold their exc / inh spikes as bits 0..7.
-__device__ __forceinline__ void write_outputs8(const Params &p, const Outs &o, int k, int b, int j0, int nv,
+template <class PP>
+__device__ __forceinline__ void write_outputs8(const PP &p, const Outs &o, int k, int b, int j0, int nv,
                                                uint32_t se_m, uint32_t si_m, const float *ve, const float *vi)
 {
     const int words = (p.n_exc + 31) >> 5;

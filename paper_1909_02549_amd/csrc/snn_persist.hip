@@ -88,7 +88,10 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
     float ve[kPersistTasks][8], vi[kPersistTasks][8];
     uint32_t rw[kPersistTasks][4];
     uint32_t hin_cnt[kPersistTasks];
-    uint4 hin[kPersistTasks];
+    // list words read ahead (fewer for FP8, whose rounding in the gathers
+    // takes the registers)
+    constexpr int NHP = PREC == PREC_FP8 ? 1 : 2;
+    uint4 hin[kPersistTasks][NHP];
 #pragma unroll
     for (int u = 0; u < kPersistTasks; ++u) {
         const int q = tid + u * nt;
@@ -97,20 +100,25 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
         tc0[u] = 8 * (q - tb[u] * ncg);
         tnv[u] = max(0, min(8, min(JB, p.n_exc - g * JB) - tc0[u]));
         hin_cnt[u] = 0u;
-        hin[u] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int w = 0; w < NHP; ++w) hin[u][w] = make_uint4(0u, 0u, 0u, 0u);
         if (has_task[u]) {
             load_task_state(p, S, a, (size_t)g * p.Bs * JBP + (size_t)tb[u] * JBP + tc0[u], tb[u], tc0[u], ve[u],
                             vi[u], rw[u]);
             // the spike lists are read-only during the launch: the next
-            // step's list head is fetched before each barrier
+            // step's list length and first 8 * NHP entries are fetched
+            // before each barrier wait
             if (ch.steps > 0) {
                 hin_cnt[u] = ch.cin[tb[u]];
-                hin[u] = *reinterpret_cast<const uint4 *>(ch.lin + (size_t)tb[u] * p.n_in_pad);
+                load_heads<NHP>(ch.lin + (size_t)tb[u] * p.n_in_pad, hin[u]);
             }
         }
     }
     __syncthreads();
 
+    // neuron parameters and output pointers in registers for the step loop
+    const NeuronK nk = neuron_consts(p);
+    const Outs outs = a.o;
     for (int k = 0; k < ch.steps; ++k) {
         const int mod = (ch.mod0 + k) % 3;
         const float *xpre = ch.xpre + (size_t)mod * p.Bs * p.n_in_pad;
@@ -125,9 +133,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             if (!has_task[u]) continue;
             float acc[8];
             const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
-            gather8(row, (int)hin_cnt[u], make_uint2(hin[u].x, hin[u].y), make_uint2(hin[u].z, hin[u].w), 8, S.W, p.ls,
-                    tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
-            neuron_task(p, S, a.o, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, ve[u], vi[u], rw[u]);
+            gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
+            neuron_task(nk, S, outs, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, ve[u], vi[u], rw[u]);
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             for (int u = 0; u < kPersistTasks; ++u) {
                 if (!has_task[u]) continue;
                 hin_cnt[u] = ch.cin[(size_t)(k + 1) * p.B + tb[u]];
-                hin[u] = *reinterpret_cast<const uint4 *>(ch.lin + ((size_t)(k + 1) * p.B + tb[u]) * p.n_in_pad);
+                load_heads<NHP>(ch.lin + ((size_t)(k + 1) * p.B + tb[u]) * p.n_in_pad, hin[u]);
             }
         }
     }
