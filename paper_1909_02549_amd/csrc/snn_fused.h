@@ -471,19 +471,26 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
         for (int c = 0; c < 8; ++c) P[g][c] = 0.f, D[g][c] = 0.f;
     uint32_t m8[8];
     float x8[8];
+    // masks of this thread's 16 columns and x_pre values of listed samples
+    // u0 .. u0 + 8 (loads only for samples that fired in these columns)
     auto fetch = [&](int u0) {
+        uint32_t b8[8];
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
             const int u = u0 + v;
-            const int b = u < ucnt ? (int)S.ulist[u] : 0;
-            m8[v] = u < ucnt ? (S.colmask[b] >> (8 * cg0)) & 0xFFFFu : 0u;
-            x8[v] = ld_x<Coherent>(xpre + (m8[v] ? (size_t)b * p.n_in_pad : 0) + i);
+            b8[v] = u < ucnt ? S.ulist[u] : 0u;
+            m8[v] = __builtin_amdgcn_readfirstlane(u < ucnt ? (S.colmask[b8[v]] >> (8 * cg0)) & 0xFFFFu : 0u);
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            x8[v] = 0.f;
+            if (m8[v]) x8[v] = ld_x<Coherent>(xpre + (size_t)b8[v] * p.n_in_pad + i);
         }
     };
     auto accumulate = [&]() {
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-            const uint32_t m = __builtin_amdgcn_readfirstlane(m8[v]);
+            const uint32_t m = m8[v];
             if (m) {
                 const float xv = operand_value(prec, x8[v]);
 #pragma unroll
