@@ -16,9 +16,10 @@
 //
 // Column normalisation is kept lazily: after a learning step the block holds
 // the clamped, not yet normalised weights and scale[c] = norm / sum_i W[i, c]
-// (FP64); the next step applies it (w <- float(w * scale)) when it updates
-// the weight, the contraction multiplies its column sum by it, and the block
-// is written back to HBM normalised.
+// (FP64 sum and quotient, also kept rounded to FP32); the next step applies
+// the FP32 scale (w <- w * scale, within one rounding of the FP64 product)
+// when it updates the weight, the contraction multiplies its column sum by it,
+// and the block is written back to HBM normalised with the FP64 scale.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -138,7 +139,7 @@ __device__ __forceinline__ void st_x(T *ptr, T v)
 
 // LDS carve-up shared by host (size) and device (offsets).
 struct FusedLds {
-    size_t w, xpost, cprev, cinh, spk, colmask, ulist, part, scale, theta, theta64, total;
+    size_t w, xpost, cprev, cinh, spk, colmask, ulist, part, scale, scalef, theta, theta64, total;
     // share_part: the column-sum partials reuse the post-trace rows (the
     // fused kernel, whose post traces are dead by then)
     __host__ __device__ FusedLds(const Params &p, int nthreads, bool share_part = false)
@@ -167,6 +168,8 @@ struct FusedLds {
         }
         scale = o;
         o += 32 * 8;
+        scalef = o;
+        o += 32 * 4;
         theta = o;
         o += 32 * 4;
         theta64 = o;
@@ -177,12 +180,13 @@ struct FusedLds {
 
 // Named views of the LDS regions.
 struct StepLds {
-    float *W, *xpost, *th;
+    float *W, *xpost, *th, *scalef;
     uint32_t *cprev, *cinh, *spk, *colmask, *ulist;
     double *part, *scale, *th64;
     __device__ StepLds(unsigned char *smem, const FusedLds &L)
         : W(reinterpret_cast<float *>(smem + L.w)), xpost(reinterpret_cast<float *>(smem + L.xpost)),
-          th(reinterpret_cast<float *>(smem + L.theta)), cprev(reinterpret_cast<uint32_t *>(smem + L.cprev)),
+          th(reinterpret_cast<float *>(smem + L.theta)), scalef(reinterpret_cast<float *>(smem + L.scalef)),
+          cprev(reinterpret_cast<uint32_t *>(smem + L.cprev)),
           cinh(reinterpret_cast<uint32_t *>(smem + L.cinh)), spk(reinterpret_cast<uint32_t *>(smem + L.spk)),
           colmask(reinterpret_cast<uint32_t *>(smem + L.colmask)),
           ulist(reinterpret_cast<uint32_t *>(smem + L.ulist)), part(reinterpret_cast<double *>(smem + L.part)),
@@ -331,7 +335,7 @@ __device__ __forceinline__ void neuron_task(const PP &p, const StepLds &S, const
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int jl = c0 + c;
-        const float I = (float)((double)acc[c] * S.scale[jl]);
+        const float I = acc[c] * S.scalef[jl];
         NeuronState st{ve[c], vi[c], (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu, xp[c]};
         bool se, si;
         neuron_update(p, I, cp, S.th[jl], st, se, si);
@@ -443,7 +447,7 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            float xw = (float)((double)w[c] * S.scale[c0 + c]);
+            float xw = w[c] * S.scalef[c0 + c];
             if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
             const float d = p.reduce == RED_MEAN ? D[c] * p.inv_B : D[c];
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
@@ -532,7 +536,7 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            float xw = (float)((double)w[c] * S.scale[c0 + c]);
+            float xw = w[c] * S.scalef[c0 + c];
             xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[g][c] * p.inv_B : P[g][c]);
             const float d = p.reduce == RED_MEAN ? D[g][c] * p.inv_B : D[g][c];
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
@@ -611,7 +615,7 @@ __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, i
         for (int i = rg; i < p.n_in; i += nrg) S.W[i * p.ls + jj] = (float)((double)S.W[i * p.ls + jj] * sc);
     }
     __syncthreads();
-    if (tid < 32) S.scale[tid] = 1.0;
+    if (tid < 32) S.scale[tid] = 1.0, S.scalef[tid] = 1.f;
     __syncthreads();
 }
 
@@ -629,6 +633,7 @@ __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S,
         double c = 0.0;
         for (int r = 0; r < nrg; ++r) c += S.part[r * 32 + tid];
         S.scale[tid] = (p.norm > 0.0 && c > 0.0 && tid < p.jb) ? p.norm / c : 1.0;
+        S.scalef[tid] = (float)S.scale[tid];
         if (p.adaptive && tid < p.jb) {
             int cnt = 0;
             for (int bw = 0; bw < p.bwords; ++bw) cnt += __builtin_popcount(S.spk[tid * p.bwords + bw]);
@@ -685,6 +690,7 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
         const int jt = g * JB + tid;
         S.th64[tid] = (tid < JB && jt < p.n_exc) ? theta[jt] : 0.0;
         S.scale[tid] = 1.0;
+        S.scalef[tid] = 1.f;
     }
 }
 
