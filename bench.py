@@ -12,9 +12,12 @@ value = B * T * steps / elapsed seconds (sample-steps/s).
 Also reported on the same JSON line:
   paths         the same workload on each execution path (plain per-step
                 launches, fused per-step kernel, persistent kernel);
-  roofline      the dominant kernel's algorithmic HBM bytes per launch divided
-                by its average launch time, measured with HIP events recorded
-                on the library's stream during the timed region;
+  roofline      the dominant kernel's roofline from its average launch time
+                (HIP events on the library's stream over the timed region):
+                algorithmic HBM bytes per launch against the 8 TB/s HBM peak,
+                matrix-core flops against the MFMA peak (matrix kernels), and
+                algorithmic vector operations against the 157.3 TFLOP/s vector
+                peak (gather kernels); `bound` names the largest fraction;
   serving       frozen 784 -> 1600 network, Poisson arrivals, T in
                 {100, 250, 500}: p50 / p99 latency and sample-steps/s;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
@@ -47,11 +50,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def dims(cfg, B):
+def dims(cfg, B, imgs=None):
+    """Sizes of a workload; s_in is the expected number of input spikes per
+    step over the batch (rate pixel / 255 x max_rate, or the uniform rate)."""
     n_in = cfg["n_in"]
     n_in_pad = 32 * ((n_in + 31) // 32)
+    p = cfg["max_rate_hz"] * cfg["dt_ms"] * 1e-3
+    if imgs is not None:
+        s_in = float(np.minimum(imgs.astype(np.float64) / 255.0 * p, 1.0).sum())
+    else:
+        s_in = B * n_in * min(p, 1.0)
     return dict(n_in=n_in, n_in_pad=n_in_pad, n_exc=cfg["n_exc"], B=B, in_words=n_in_pad // 32,
-                bwords=(B + 31) // 32, learn=cfg["learn"], has_inh=cfg["n_inh"] > 0)
+                bwords=(B + 31) // 32, learn=cfg["learn"], has_inh=cfg["n_inh"] > 0, s_in=s_in)
 
 
 def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: float = 1.0):
@@ -84,6 +94,15 @@ def algorithmic_bytes(kernel: str, d: dict, steps_per_launch: float = 1.0):
 
 
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+# vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
+VALU_PEAK_TFLOPS = 157.3
+# algorithmic vector operations per unit of the gather kernels (FP32
+# equivalents; an FP64 add counts 2, an FMA 2, a compare or min/max 1)
+ALU_PER_SPIKE_COL = 1      # contraction: one add per (input spike, column)
+ALU_PER_SPIKE_COL_D = 1    # depression sums: one add per (input spike, column)
+ALU_PER_NEURON = 11        # exc: decay FMA, input add, inhibition FMA, threshold; inh: decay FMA, add,
+                           # threshold; post trace multiply
+ALU_PER_WEIGHT = 7         # scale multiply, depression FMA, clamp (2), FP64 column-sum add (2)
 # matrix-core operations per algorithmic product: the FP32 form multiplies
 # three bfloat16 parts of each operand value
 MFMA_PLANES = {"fp32": 3, "bf16": 1, "fp8": 1}
@@ -99,6 +118,18 @@ def algorithmic_flops(kernel: str, d: dict):
     if kernel == "mfma_plastic":
         return 4.0 * d["B"] * d["n_in"] * d["n_exc"]
     return None
+
+
+def alu_ops(kernel: str, d: dict, steps_per_launch: float = 1.0):
+    """Algorithmic vector operations of one launch of the gather kernels
+    (one step for the fused kernel, a chunk for the persistent one)."""
+    if kernel not in ("fused_step", "persistent"):
+        return None
+    N = d["n_exc"]
+    per_step = ALU_PER_SPIKE_COL * d["s_in"] * N + ALU_PER_NEURON * d["B"] * N
+    if d["learn"]:
+        per_step += ALU_PER_SPIKE_COL_D * d["s_in"] * N + ALU_PER_WEIGHT * d["n_in"] * N
+    return per_step * steps_per_launch
 
 
 def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms: float, spl: float):
@@ -123,6 +154,14 @@ def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms
                      "flops_per_launch": fl, "mfma_ops_per_product": MFMA_PLANES[precision], "dtype": dt}
         if mfrac > r["frac"]:
             r.update(bound="mfma", achieved=tf, peak=MFMA_PEAK_TFLOPS[dt], unit="TFLOP/s", frac=mfrac)
+    ops = alu_ops(kname, d, spl)
+    if ops is not None:
+        tf = ops / avg_s / 1e12
+        afrac = tf / VALU_PEAK_TFLOPS
+        r["alu"] = {"achieved": tf, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": afrac, "ops_per_launch": ops,
+                    "hbm_frac": r["frac"]}
+        if afrac > r["frac"]:
+            r.update(bound="alu", achieved=tf, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=afrac)
     return r
 
 
@@ -344,7 +383,7 @@ def main():
     used_path = net.snn_last_path()
     value = B * T * args.steps / el
 
-    d = dims(cfg, B)
+    d = dims(cfg, B, imgs)
     roof = None
     kroofs = {}
     if prof:
@@ -374,6 +413,8 @@ def main():
                     ke["hbm_frac"] = kr["bytes_per_launch"] / (kr["avg_launch_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
                     if "mfma" in kr:
                         ke["mfma_frac"] = kr["mfma"]["frac"]
+                    if "alu" in kr:
+                        ke["alu_frac"] = kr["alu"]["frac"]
                 entry["kernels"][kn] = ke
             paths[pth] = entry
             pnet.close()
