@@ -33,6 +33,7 @@ constexpr int kFusedThreads = 1024;   // fused per-step kernel: 16 waves
 constexpr int kPersistThreads = 512;  // persistent kernel: 8 waves, with
 constexpr int kPersistTasks = 2;      //   two (sample, 8 columns) tasks each
 constexpr int kListHead = 4;          // 16-byte words of a spike list read ahead
+constexpr int kMfmaPotentiation = 0;  // spiking samples above which potentiation runs on the matrix cores
 static_assert(kFusedThreads % 128 == 0 && kPersistThreads % 128 == 0, "split-row plasticity needs nt % 128 == 0");
 
 // Per-network pointers (state and parameters owned by the handle).
@@ -466,8 +467,10 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
 template <bool Coherent, int NH>
 __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepLds &S, int i, int cg0, int ng,
                                                     int cnt, const uint4 *h, const uint16_t *ltrow, const float *xpre,
-                                                    int ucnt, int prec, int prec_d)
+                                                    int ucnt, uint32_t pdone, int prec, int prec_d)
 {
+    // pdone: columns whose weights already hold w * scale + potentiation
+    // (the matrix-core pass); then ucnt is 0 here
     float P[2][8], D[2][8];
 #pragma unroll
     for (int g = 0; g < 2; ++g)
@@ -536,13 +539,93 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            float xw = w[c] * S.scalef[c0 + c];
+            float xw = ((pdone >> (c0 + c)) & 1u) ? w[c] : w[c] * S.scalef[c0 + c];
             xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[g][c] * p.inv_B : P[g][c]);
             const float d = p.reduce == RED_MEAN ? D[g][c] * p.inv_B : D[g][c];
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
         }
         wr[0] = make_float4(w[0], w[1], w[2], w[3]);
         wr[1] = make_float4(w[4], w[5], w[6], w[7]);
+    }
+}
+
+// Potentiation on the matrix cores, for the sum and mean reductions:
+//   P[i, c] = sum over the listed spiking samples b of q(x_pre[b, i]) s[b, c]
+// as a 32 x 32 tile product per 32 input rows, K = the listed samples in
+// chunks of 16 (x_pre operands straight from memory, the FP32 form in three
+// exact bfloat16 planes, BF16 / FP8 in one; the spike masks are exact 0 / 1).
+// Writes w <- w * scale[c] + nu_post * P[i, c] (P / B for mean) for the fired
+// columns (colany); the depression pass then leaves their scale alone.  Its
+// cost grows with the number of spiking samples over 16, not with the
+// samples times the row items, which keeps blocks whose neurons fire in many
+// samples of a step from holding up the others.
+template <bool Coherent>
+__device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds &S, const float *xpre, int ucnt,
+                                                  uint32_t colany, int prec, int tid, int nt)
+{
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int col = lane & 31, kh = lane >> 5;
+    const int nrt = (p.n_in + 31) >> 5;
+    const bool fired_col = ((colany >> col) & 1u) != 0u && col < p.jb;
+    for (int rt = wv; rt < nrt; rt += nw) {
+        const int row = rt * 32 + col;  // this lane's A row (the A layout puts row lane % 32)
+        f32x16_t acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        // two K chunks (32 listed samples) per pass: 16 loads in flight
+        for (int k0 = 0; k0 < ucnt; k0 += 32) {
+            float x[2][8];
+            uint32_t bits[2] = {0u, 0u};
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int u = k0 + 16 * h + 8 * kh + e;
+                    const uint32_t b = u < ucnt ? S.ulist[u] : 0u;
+                    x[h][e] = (u < ucnt && row < p.n_in) ? ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + row) : 0.f;
+                    bits[h] |= (u < ucnt ? (S.colmask[b] >> col) & 1u : 0u) << e;
+                }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (k0 + 16 * h >= ucnt) break;
+                const uint4 bop = ones_bf16(bits[h]);
+                uint32_t c0[8], c1[8], c2[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (prec == PREC_FP32) {
+                        uint32_t c[3];
+                        split<PREC_FP32>(x[h][e], c);
+                        c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
+                    } else {
+                        c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
+                        c1[e] = c2[e] = 0u;
+                    }
+                }
+                const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
+                                            c0[6] | (c0[7] << 16));
+                acc = mfma<PREC_BF16>(a0, bop, acc);
+                if (prec == PREC_FP32) {
+                    const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16),
+                                                c1[4] | (c1[5] << 16), c1[6] | (c1[7] << 16));
+                    const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16),
+                                                c2[4] | (c2[5] << 16), c2[6] | (c2[7] << 16));
+                    acc = mfma<PREC_BF16>(a1, bop, acc);
+                    acc = mfma<PREC_BF16>(a2, bop, acc);
+                }
+            }
+        }
+        // accumulator r: row 8 (r / 4) + 4 kh + r % 4 of the tile, column col
+        if (fired_col) {
+            const float sc = S.scalef[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (i < p.n_in) {
+                    float *w = S.W + i * p.ls + col;
+                    *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
+                }
+            }
+        }
     }
 }
 
@@ -559,6 +642,19 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
     const int ucnt = (int)S.ulist[p.B];
     const int ncg = p.jbp >> 3;
     if (Halves && ncg >= 2) {
+        uint32_t pdone = 0u;
+        int ucnt_items = ucnt;
+        // many spiking samples: potentiation on the matrix cores first (few:
+        // in the row items, no extra pass)
+        if (p.reduce != RED_MAX && ucnt > kMfmaPotentiation) {
+            uint32_t colany = 0u;
+            for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
+            colany = __builtin_amdgcn_readfirstlane(colany);
+            potentiation_mfma<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
+            __syncthreads();
+            pdone = colany;
+            ucnt_items = 0;
+        }
         // item q: row ord[(q / 128) * 64 + q % 64], column groups 2 hf and
         // 2 hf + 1 with hf = (q / 64) % 2, the same in every lane of a wave
         // (nt is a multiple of 128)
@@ -574,7 +670,7 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             uint4 h[NH];
             load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
             plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
-                                              ucnt, prec, prec_d);
+                                              ucnt_items, pdone, prec, prec_d);
         }
         return;
     }

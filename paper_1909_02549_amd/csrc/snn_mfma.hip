@@ -28,84 +28,6 @@
 
 namespace snn {
 
-typedef __bf16 bf16x8_t __attribute__((__vector_size__(8 * sizeof(__bf16))));
-typedef float f32x16_t __attribute__((__vector_size__(16 * sizeof(float))));
-
-template <int PREC>
-struct Form {
-    static constexpr int planes = PREC == PREC_FP32 ? 3 : 1;
-    static constexpr int esize = PREC == PREC_FP8 ? 1 : 2;  // bytes per element
-    static constexpr int vbytes = 8 * esize;                 // bytes per lane operand
-    using vec = typename std::conditional<PREC == PREC_FP8, uint2, uint4>::type;
-    static constexpr int batch = PREC == PREC_FP32 ? 2 : 5;   // k-steps whose operands are read ahead
-    static constexpr int batch8 = PREC == PREC_FP32 ? 2 : 4;  // the same within 8-step windows
-};
-
-// 8 spike bits -> 8 operand elements equal to 1 or 0.
-__device__ __forceinline__ uint4 ones_bf16(uint32_t byte)
-{
-    uint4 r;
-    r.x = ((byte & 1u) * 0x3F80u) | (((byte >> 1) & 1u) * 0x3F800000u);
-    r.y = (((byte >> 2) & 1u) * 0x3F80u) | (((byte >> 3) & 1u) * 0x3F800000u);
-    r.z = (((byte >> 4) & 1u) * 0x3F80u) | (((byte >> 5) & 1u) * 0x3F800000u);
-    r.w = (((byte >> 6) & 1u) * 0x3F80u) | (((byte >> 7) & 1u) * 0x3F800000u);
-    return r;
-}
-
-__device__ __forceinline__ uint2 ones_fp8(uint32_t byte)
-{
-    // E4M3 1.0 = 0x38
-    uint2 r;
-    r.x = ((byte & 1u) * 0x38u) | (((byte >> 1) & 1u) * 0x3800u) | (((byte >> 2) & 1u) * 0x380000u) |
-          (((byte >> 3) & 1u) * 0x38000000u);
-    r.y = (((byte >> 4) & 1u) * 0x38u) | (((byte >> 5) & 1u) * 0x3800u) | (((byte >> 6) & 1u) * 0x380000u) |
-          (((byte >> 7) & 1u) * 0x38000000u);
-    return r;
-}
-
-// One MFMA step on raw operand registers.
-template <int PREC>
-__device__ __forceinline__ f32x16_t mfma(uint4 a, uint4 b, f32x16_t c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
-                                                   0, 0, 0);
-}
-template <int PREC>
-__device__ __forceinline__ f32x16_t mfma8(uint2 a, uint2 b, f32x16_t c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0,
-                                                      0, 0);
-}
-
-// One MFMA step of the form PREC on raw operand registers.
-template <int PREC>
-__device__ __forceinline__ f32x16_t mma(uint4 a, uint4 b, f32x16_t c)
-{
-    return mfma<PREC>(a, b, c);
-}
-template <int PREC>
-__device__ __forceinline__ f32x16_t mma(uint2 a, uint2 b, f32x16_t c)
-{
-    return mfma8<PREC>(a, b, c);
-}
-
-// Operand codes of one value x in the form PREC (plane 0 first).
-template <int PREC>
-__device__ __forceinline__ void split(float x, uint32_t c[3])
-{
-    if constexpr (PREC == PREC_FP32) {
-        c[0] = bf16_code(x);
-        const float r1 = x - bf16_value(c[0]);
-        c[1] = bf16_code(r1);
-        const float r2 = r1 - bf16_value(c[1]);
-        c[2] = bf16_code(r2);
-    } else if constexpr (PREC == PREC_BF16) {
-        c[0] = bf16_code(x);
-    } else {
-        c[0] = e4m3_code(x);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // one step's front half: presynaptic traces, synaptic current, neurons
 // ---------------------------------------------------------------------------
