@@ -389,7 +389,7 @@ def main():
     if prof:
         gpu_ms = sum(v[1] for v in prof.values())
         for kn, (ln, ms) in prof.items():
-            kr = kernel_roofline(kn, d, args.precision, ln, ms, T / max(ln, 1))
+            kr = kernel_roofline(kn, d, args.precision, ln, ms, T * args.steps / max(ln, 1))
             if kr is not None:
                 kr["share_of_gpu_time"] = ms / gpu_ms
                 kroofs[kn] = kr
@@ -407,7 +407,7 @@ def main():
             entry = {"value": B * T * n / pel, "ms_per_step": pel * 1e3 / n, "used": pnet.snn_last_path()}
             entry["kernels"] = {}
             for kn, (ln, ms) in pprof.items():
-                kr = kernel_roofline(kn, d, args.precision, ln, ms, T / max(ln, 1))
+                kr = kernel_roofline(kn, d, args.precision, ln, ms, T * n / max(ln, 1))
                 ke = {"launches": ln, "avg_us": ms * 1e3 / max(ln, 1)}
                 if kr is not None:
                     ke["hbm_frac"] = kr["bytes_per_launch"] / (kr["avg_launch_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
