@@ -3,12 +3,14 @@
 //
 // Step t in workgroup g (building blocks in snn_fused.h):
 //   A  stage the weight block, thresholds, C(t-1)
-//   B  task (b, 8 columns): neuron state from HBM; I = sum over the inputs in
-//      sample b's spike list (increasing i) of W[i, cols]; recurrent
-//      currents; exc adaptive-LIF and inh LIF update; post trace; state back
-//   C  (learning) task (i, 8 columns): potentiation from the presynaptic
-//      traces of the samples whose neurons fired, depression from the post
-//      traces of the samples in which input i fired, clamp
+//   B  task (b, 8 columns), samples in the step's work order: neuron state
+//      from HBM; I = sum over the inputs in sample b's spike list (increasing
+//      i) of W[i, cols]; recurrent currents; exc adaptive-LIF and inh LIF
+//      update; post trace; state back
+//   C  (learning) potentiation from the presynaptic traces of the samples
+//      whose neurons fired (matrix cores for sum / mean), then per input row
+//      (in the step's work order) depression from the post traces of the
+//      samples in which input i fired, clamp
 //   C3 (learning) FP64 column sums, normalisation scale, theta update
 //   E  (learning) x_pre(t+1) for this workgroup's share of the samples, the
 //      block back to HBM normalised
