@@ -103,6 +103,27 @@ __device__ __forceinline__ NeuronK neuron_consts(const Params &p)
                    p.lam_post};
 }
 
+// The same with the floating-point constants held in vector registers: in
+// kernels short of scalar registers they would otherwise be spilled and read
+// back lane by lane at every use.  (An empty asm statement with a "+v"
+// operand only fixes the register class.)
+__device__ __forceinline__ void in_vgpr(float &x) { asm volatile("" : "+v"(x)); }
+
+__device__ __forceinline__ NeuronK neuron_consts_v(const Params &p)
+{
+    NeuronK k = neuron_consts(p);
+    for (LifP *l : {&k.exc, &k.inh}) {
+        in_vgpr(l->v_rest);
+        in_vgpr(l->v_reset);
+        in_vgpr(l->v_th);
+        in_vgpr(l->alpha);
+    }
+    in_vgpr(k.w_ei);
+    in_vgpr(k.w_ie);
+    in_vgpr(k.lam_post);
+    return k;
+}
+
 // One step of the excitatory adaptive-LIF neuron j and its inhibitory
 // partner for one sample:
 //   I_exc = I_ff + w_ie * (C_inh(t-1) - s_inh(t-1)[j])   (all-but-self)

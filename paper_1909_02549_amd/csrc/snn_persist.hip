@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
     __syncthreads();
 
     // neuron parameters and output pointers in registers for the step loop
-    const NeuronK nk = neuron_consts(p);
+    const NeuronK nk = PREC == PREC_FP8 ? neuron_consts(p) : neuron_consts_v(p);
     const Outs outs = a.o;
     for (int k = 0; k < ch.steps; ++k) {
         const int mod = (ch.mod0 + k) % 3;
