@@ -559,74 +559,79 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 // cost grows with the number of spiking samples over 16, not with the
 // samples times the row items, which keeps blocks whose neurons fire in many
 // samples of a step from holding up the others.
+// One 32-row tile rt of the potentiation product (one wave; lane = lane index).
+template <bool Coherent>
+__device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds &S, const float *xpre, int ucnt,
+                                                  uint32_t colany, int prec, int rt, int lane)
+{
+    const int col = lane & 31, kh = lane >> 5;
+    const bool fired_col = ((colany >> col) & 1u) != 0u && col < p.jb;
+    const int row = rt * 32 + col;  // this lane's A row (the A layout puts row lane % 32)
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    // two K chunks (32 listed samples) per pass: 16 loads in flight
+    for (int k0 = 0; k0 < ucnt; k0 += 32) {
+        float x[2][8];
+        uint32_t bits[2] = {0u, 0u};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int u = k0 + 16 * h + 8 * kh + e;
+                const uint32_t b = u < ucnt ? S.ulist[u] : 0u;
+                x[h][e] = (u < ucnt && row < p.n_in) ? ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + row) : 0.f;
+                bits[h] |= (u < ucnt ? (S.colmask[b] >> col) & 1u : 0u) << e;
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (k0 + 16 * h >= ucnt) break;
+            const uint4 bop = ones_bf16(bits[h]);
+            uint32_t c0[8], c1[8], c2[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                if (prec == PREC_FP32) {
+                    uint32_t c[3];
+                    split<PREC_FP32>(x[h][e], c);
+                    c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
+                } else {
+                    c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
+                    c1[e] = c2[e] = 0u;
+                }
+            }
+            const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
+                                        c0[6] | (c0[7] << 16));
+            acc = mfma<PREC_BF16>(a0, bop, acc);
+            if (prec == PREC_FP32) {
+                const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16),
+                                            c1[4] | (c1[5] << 16), c1[6] | (c1[7] << 16));
+                const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16),
+                                            c2[4] | (c2[5] << 16), c2[6] | (c2[7] << 16));
+                acc = mfma<PREC_BF16>(a1, bop, acc);
+                acc = mfma<PREC_BF16>(a2, bop, acc);
+            }
+        }
+    }
+    // accumulator r: row 8 (r / 4) + 4 kh + r % 4 of the tile, column col
+    if (fired_col) {
+        const float sc = S.scalef[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            if (i < p.n_in) {
+                float *w = S.W + i * p.ls + col;
+                *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
+            }
+        }
+    }
+}
+
 template <bool Coherent>
 __device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds &S, const float *xpre, int ucnt,
                                                   uint32_t colany, int prec, int tid, int nt)
 {
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int col = lane & 31, kh = lane >> 5;
     const int nrt = (p.n_in + 31) >> 5;
-    const bool fired_col = ((colany >> col) & 1u) != 0u && col < p.jb;
-    for (int rt = wv; rt < nrt; rt += nw) {
-        const int row = rt * 32 + col;  // this lane's A row (the A layout puts row lane % 32)
-        f32x16_t acc;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-        // two K chunks (32 listed samples) per pass: 16 loads in flight
-        for (int k0 = 0; k0 < ucnt; k0 += 32) {
-            float x[2][8];
-            uint32_t bits[2] = {0u, 0u};
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int u = k0 + 16 * h + 8 * kh + e;
-                    const uint32_t b = u < ucnt ? S.ulist[u] : 0u;
-                    x[h][e] = (u < ucnt && row < p.n_in) ? ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + row) : 0.f;
-                    bits[h] |= (u < ucnt ? (S.colmask[b] >> col) & 1u : 0u) << e;
-                }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (k0 + 16 * h >= ucnt) break;
-                const uint4 bop = ones_bf16(bits[h]);
-                uint32_t c0[8], c1[8], c2[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if (prec == PREC_FP32) {
-                        uint32_t c[3];
-                        split<PREC_FP32>(x[h][e], c);
-                        c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
-                    } else {
-                        c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
-                        c1[e] = c2[e] = 0u;
-                    }
-                }
-                const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
-                                            c0[6] | (c0[7] << 16));
-                acc = mfma<PREC_BF16>(a0, bop, acc);
-                if (prec == PREC_FP32) {
-                    const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16),
-                                                c1[4] | (c1[5] << 16), c1[6] | (c1[7] << 16));
-                    const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16),
-                                                c2[4] | (c2[5] << 16), c2[6] | (c2[7] << 16));
-                    acc = mfma<PREC_BF16>(a1, bop, acc);
-                    acc = mfma<PREC_BF16>(a2, bop, acc);
-                }
-            }
-        }
-        // accumulator r: row 8 (r / 4) + 4 kh + r % 4 of the tile, column col
-        if (fired_col) {
-            const float sc = S.scalef[col];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (i < p.n_in) {
-                    float *w = S.W + i * p.ls + col;
-                    *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
-                }
-            }
-        }
-    }
+    for (int rt = tid >> 6; rt < nrt; rt += nt >> 6) potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, tid & 63);
 }
 
 // Phase C over all input rows of the block: split rows (Halves, blocks of
@@ -634,13 +639,45 @@ __device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds
 // next row's list head before working on the current row.  Rows are taken in
 // the order `ord` (inputs by decreasing sample-list length), so the lanes of
 // a wave walk lists of similar length.
-template <bool Coherent, int XR, bool Halves, int NH = kListHead>
+template <bool Coherent, int XR, bool Halves, int NH = kListHead, bool Interleave = true>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const uint16_t *ord, const float *xpre, int tid,
                                                int nt, int prec, int prec_d)
 {
     const int ucnt = (int)S.ulist[p.B];
     const int ncg = p.jbp >> 3;
+    if (Interleave && Halves && ncg >= 2 && p.reduce != RED_MAX) {
+        // sum / mean: per 32-row tile, one wave takes the potentiation tile
+        // product and then the depression items of the same rows (lane l:
+        // row l % 32, column groups 2 (l / 32) and 2 (l / 32) + 1), so the
+        // two need no workgroup barrier between them
+        uint32_t colany = 0u;
+        for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
+        colany = __builtin_amdgcn_readfirstlane(colany);
+        const int lane = tid & 63, nrt = (p.n_in + 31) >> 5;
+        const int hf = lane >> 5, cg0 = 2 * hf, ng = min(2, ncg - cg0);
+        for (int rt = tid >> 6; rt < nrt; rt += nt >> 6) {
+            const int i = rt * 32 + (lane & 31);
+            const bool item = i < p.n_in && ng > 0;
+            if (ucnt > 0) {
+                potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, lane);
+                // the tile's weights, written by other lanes of this wave
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            uint32_t cnt = 0u;
+            uint4 h[NH];
+            if (item) {
+                cnt = ct[i];
+                load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
+            }
+            if (item)
+                plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
+                                                  0, colany, prec, prec_d);
+        }
+        return;
+    }
     if (Halves && ncg >= 2) {
         uint32_t pdone = 0u;
         int ucnt_items = ucnt;

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     }
     __syncthreads();
 
-    plasticity_all<false, 16, true>(p, S, s.lt, s.ct, s.ord_in, s.xpre, tid, nt, PREC, 0);
+    plasticity_all<false, 16, true, kListHead, PREC == PREC_FP32>(p, S, s.lt, s.ct, s.ord_in, s.xpre, tid, nt,
+                                                                 PREC, 0);
     __syncthreads();
     colsums_theta(p, S, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);

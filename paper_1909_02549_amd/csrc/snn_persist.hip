@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
         grid_arrive(sy);
         if (p.learn) {
-            plasticity_all<true, 16, true, 2>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
+            plasticity_all<true, 16, true, 2, PREC == PREC_FP32>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
                                               ch.ct + (size_t)k * p.n_in_pad, ch.ord_in + (size_t)k * p.n_in_pad,
                                               xpre, tid, nt, PREC, PREC);
             __syncthreads();
