@@ -12,7 +12,7 @@
 
 // Steps encoded per encoder launch (bounds the input-spike buffers; one extra
 // step is encoded so the last step of a chunk sees its successor's inputs).
-constexpr uint32_t kChunk = 256;
+constexpr uint32_t kChunk = 512;
 // LDS a workgroup may use on gfx950 (160 KiB per CU).
 constexpr size_t kMaxLds = 160 * 1024;
 

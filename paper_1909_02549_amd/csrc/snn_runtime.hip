@@ -79,11 +79,11 @@ static int choose_jb(uint32_t n_exc, int cus)
 }
 
 // Steps per encoder chunk: the sparse lists take B * n_in_pad and
-// n_in_pad * round8(B) u16 per step; keep one chunk under 256 MiB.
+// n_in_pad * round8(B) u16 per step; keep one chunk under 1 GiB.
 static uint32_t chunk_steps(const Params &p, uint32_t B)
 {
     const size_t per = ((size_t)B * p.n_in_pad + (size_t)p.n_in_pad * ((B + 7) & ~7u)) * 2 + 16 * (size_t)B;
-    size_t c = ((size_t)256 << 20) / std::max<size_t>(per, 1);
+    size_t c = ((size_t)1 << 30) / std::max<size_t>(per, 1);
     c = std::min<size_t>(std::max<size_t>(c, 8), kChunk);
     return (uint32_t)c;
 }
