@@ -101,6 +101,41 @@ def column_scaled(w: np.ndarray, col_sum: float) -> np.ndarray:
     return (w64 * (col_sum / c)[None, :]).astype(np.float32)
 
 
+def conversion_mlp(sizes=(784, 256, 128, 10), seed: int = 0, calib_images: np.ndarray | None = None,
+                   percentile: float = 99.9) -> list:
+    """Stand-in for the trained MLP of the conversion experiment (ANN to SNN
+    conversion section), prepared for IF neurons with threshold 1.
+
+    No trained network exists here, so the weights are random: He-normal
+    N(0, 2 / fan_in) and biases N(0, 0.01^2), float64 draws.  They are then
+    rescaled layer by layer as the conversion method prescribes (data-based
+    normalisation, Rueckauer et al. 2017): lambda_l is the given percentile
+    of layer l's ReLU activations on calibration images (pixels / 255), and
+    W_l, b_l become W_l * lambda_{l-1} / lambda_l and b_l / lambda_l
+    (lambda_0 = 1; the output layer keeps lambda_L = 1).  Returns
+    [(W_l float32 (n_{l-1}, n_l), b_l float32 (n_l,)), ...].
+    """
+    rng = np.random.default_rng([int(seed), 0x434E])
+    raw = []
+    for n0, n1 in zip(sizes[:-1], sizes[1:]):
+        raw.append((rng.normal(0.0, np.sqrt(2.0 / n0), size=(n0, n1)), rng.normal(0.0, 0.01, size=n1)))
+    if calib_images is None:
+        calib_images = stroke_images(256, 0xCA1B, 0.19)
+    a = np.asarray(calib_images, np.float64) / 255.0
+    lam_prev, out = 1.0, []
+    for l, (W, b) in enumerate(raw):
+        z = a @ W + b
+        if l == len(raw) - 1:
+            lam = 1.0
+        else:
+            a = np.maximum(z, 0.0)
+            pos = a[a > 0]
+            lam = float(np.percentile(pos, percentile)) if pos.size else 1.0
+        out.append(((W * (lam_prev / lam)).astype(np.float32), (b / lam).astype(np.float32)))
+        lam_prev = lam
+    return out
+
+
 def sample_ids(n: int, base: int = 0) -> np.ndarray:
     """Per-sample ids; the Poisson encoder is keyed by id, not batch slot."""
     return (np.arange(n, dtype=np.uint64) + np.uint64(base)).astype(np.uint64)
@@ -174,6 +209,7 @@ def workload(name: str) -> dict:
     dc400   784->400/400, T=250, learning, reduction sum/mean/max
     dc6400  784->6400/6400, B=256, T=350, learning, 10-30 % nonzero images
     serve   frozen 784->1600/1600 inference, T in {100,250,500}
+    conv    converted IF network 784-256-128-10, B=1024, T=10, 10000 images
     """
     if name == "dc100":
         return dict(cfg=dc_config(100), B=4, T=100, density=0.19, wlo=0.0, whi=0.3)
@@ -185,4 +221,7 @@ def workload(name: str) -> dict:
         return dict(cfg=dc_config(6400), B=256, T=350, density=(0.10, 0.30), wlo=0.0, whi=0.3)
     if name == "serve":
         return dict(cfg=dc_config(1600, learn=False), B=4096, T=None, density=0.19, wlo=0.0, whi=0.3)
+    if name == "conv":
+        return dict(sizes=(784, 256, 128, 10), thresholds=(1.0, 1.0), B=1024, T=10, n_images=10000,
+                    density=0.19, seed=0)
     raise KeyError(name)
