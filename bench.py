@@ -20,6 +20,8 @@ Also reported on the same JSON line:
                 peak (gather kernels); `bound` names the largest fraction;
   serving       frozen 784 -> 1600 network, Poisson arrivals, T in
                 {100, 250, 500}: p50 / p99 latency and sample-steps/s;
+  conversion    the converted 784-256-128-10 IF network (ANN to SNN
+                conversion section) at B = 1024 and B = 1, T = 10;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -270,6 +272,68 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
             "peak_active": st["peak_active"]}
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+
+
+def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> dict:
+    """The converted feed-forward IF network of the ANN to SNN conversion
+    section: 784-256-128-10, analog input, T = 10, B = 1024 (and B = 1, the
+    serial case the paper compares against).  Random weights after data-based
+    normalisation, synthetic stroke images.  Times whole runs (both kernels)
+    with HIP events on the handle's stream."""
+    import torch
+    from paper_1909_02549_amd import inputs
+    from paper_1909_02549_amd.snn import IFNet
+    wl = inputs.workload("conv")
+    sizes, T, B = wl["sizes"], wl["T"], wl["B"]
+    layers = inputs.conversion_mlp(sizes, wl["seed"])
+    imgs = inputs.stroke_images(B, 21, wl["density"])
+    imgs_d = torch.from_numpy(imgs).cuda()
+
+    def timed(batch):
+        net = IFNet(sizes, wl["thresholds"], max_batch=batch)
+        net.set_layers(layers)
+        x = imgs_d[:batch].contiguous()
+        out = None
+        for _ in range(warmup):
+            out = net.snn_ifnet_run(x, T, record=("pred",))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(runs):
+            net.snn_ifnet_run(x, T, record=("pred",))
+        e1.record()
+        torch.cuda.synchronize()
+        net.close()
+        return e0.elapsed_time(e1) / runs, out["pred"].cpu().numpy()
+
+    ms, pred = timed(B)
+    ms1, _ = timed(1)
+    n_in, h1, h2, n_out = sizes
+    flops = 2.0 * B * (n_in * h1 + T * (h1 * h2 + h2 * n_out))
+    pad = lambda n, m: m * ((n + m - 1) // m)  # noqa: E731
+    issued = 3 * 2.0 * pad(B, 32) * (pad(n_in, 16) * pad(h1, 32) + T * (pad(h1, 16) * pad(h2, 32) + pad(h2, 16) * 32))
+    res = {"workload": f"converted IF net {n_in}-{h1}-{h2}-{n_out}, analog input, reset by subtraction, T={T}, "
+                       f"B={B}, random weights with data-based normalisation, synthetic stroke images",
+           "value": B * T / (ms * 1e-3), "unit": "sample·steps/s", "us_per_batch": ms * 1e3,
+           "images_per_s": B / (ms * 1e-3), "test_set_10k_ms": 10000 / (B / ms),
+           "b1_us_per_image": ms1 * 1e3, "b1_value": T / (ms1 * 1e-3),
+           "batch_speedup_b1024_vs_b1": (B / ms) / (1 / ms1),
+           "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
+                        "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                        "frac": flops / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"],
+                        "flops_per_run": flops,
+                        "issued_bf16_frac": issued / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"]}}
+    if oracle:
+        from oracle.ifnet import OracleIFNet
+        t0 = time.perf_counter()
+        ref = OracleIFNet([(W.astype(np.float64), b.astype(np.float64)) for W, b in layers],
+                          wl["thresholds"]).run(imgs, T)
+        res["oracle_ms_per_batch"] = (time.perf_counter() - t0) * 1e3
+        res["pred_agree_with_oracle"] = float((ref["pred"] == pred).mean())
+    return res
+
+
 def sweep(name: str, trials: int) -> dict:
     """Throughput sweeps (not part of the default run):
     scale  1000 uniform 20 Hz inputs -> 1000 LIF, no learning, T=1000, over
@@ -339,6 +403,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--no-conversion", action="store_true", help="skip the converted IF network run")
     ap.add_argument("--sweep", choices=["scale", "dc400"], default=None,
                     help="print a throughput sweep instead of the benchmark line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -423,6 +488,8 @@ def main():
     if not args.no_serve:
         serving = serving_run(args.serve_requests, args.serve_rate, max_slots=1024, chunk=25)
 
+    conversion = None if args.no_conversion else conversion_run(oracle=not args.no_cpu)
+
     cpu = None if args.no_cpu else cpu_baseline(wl, imgs, ids, W)
 
     line = {
@@ -435,7 +502,7 @@ def main():
                                f"{['sum', 'mean', 'max'][cfg['reduce']]}, synthetic stroke images",
                    "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},
-        "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving, "conversion": conversion,
         "vs_plain_path": (value / paths["plain"]["value"]) if "plain" in paths else None,
         "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1),
                         **({"roofline": kroofs[k]} if k in kroofs else {})} for k, v in prof.items()},

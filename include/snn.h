@@ -251,6 +251,81 @@ snn_status snn_serve_stats(snn_server *srv, uint64_t *completed, uint64_t *slot_
 /* Drain queued and running requests, then stop; later polls are invalid. */
 snn_status snn_serve_destroy(snn_server *srv);
 
+/* ------------------------------------------------------------------------
+ * Converted feed-forward network of integrate-and-fire neurons (ANN to SNN
+ * conversion section): a ReLU multi-layer perceptron whose non-linearities are
+ * replaced by the firing rates of non-leaky IF neurons with reset by
+ * subtraction.
+ *   - The image is a constant analog input: pixel p enters as p / 255 at
+ *     every step.
+ *   - Hidden layers h1 and h2: at each step a neuron's voltage gains
+ *     I = a W + b (a = the previous layer's output of the same step: the
+ *     analog input for h1, the 0/1 spikes of h1 for h2); a neuron whose
+ *     voltage reaches its layer's threshold spikes and has the threshold
+ *     subtracted (at most one spike per step; no leak, no lower bound).
+ *   - Readout: the output layer's input s_h2 W_3 + b_3 summed over the run;
+ *     the predicted class is its argmax (the first maximum on ties).
+ * Every run starts from zero voltages; samples are independent.  Sums are
+ * FP32: the matrix cores take each FP32 weight as three bfloat16 parts that
+ * add up to it exactly, and pixels and spikes are exact operands.
+ * Sizes: 1 <= n_h1 <= 256, 1 <= n_h2 <= 128, 1 <= n_out <= 32,
+ * 1 <= n_in <= 65536. */
+typedef struct snn_ifnet snn_ifnet; /* opaque converted-network handle */
+
+typedef struct {
+    uint32_t abi_version;            /* must be SNN_ABI_VERSION            */
+    uint32_t n_in, n_h1, n_h2, n_out;
+    uint32_t max_batch;              /* largest batch snn_ifnet_run takes  */
+    double theta_h1, theta_h2;       /* thresholds, > 0                    */
+} snn_ifnet_config;
+
+/* Device outputs of snn_ifnet_run; any NULL pointer is skipped.
+ *   out_sum    batch x n_out f32, output-layer input summed over the run
+ *   pred       batch i32, argmax of out_sum
+ *   counts_h1  batch x n_h1 u32 spike counts of the run, counts_h2 likewise
+ *   raster_h1  T x batch x ceil(n_h1/32) u32 spikes (bit layout of
+ *              snn_outputs), raster_h2 likewise
+ *   v_h1       T x batch x n_h1 f32 voltage after each step, v_h2 likewise */
+typedef struct {
+    float *out_sum;
+    int32_t *pred;
+    uint32_t *counts_h1;
+    uint32_t *counts_h2;
+    uint32_t *raster_h1;
+    uint32_t *raster_h2;
+    float *v_h1;
+    float *v_h2;
+} snn_ifnet_outputs;
+
+/* Create a converted network on the current HIP device, work ordered on
+ * `stream` (a hipStream_t, NULL = default stream).  Every layer must be set
+ * with snn_ifnet_set_layer before the first run.
+ * Errors: SNN_EINVAL (sizes out of range, thresholds not > 0, ABI version),
+ *         SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream, snn_ifnet **out);
+
+/* Wait for outstanding work and release the handle. */
+void snn_ifnet_destroy(snn_ifnet *net);
+
+/* Weights and biases of layer 1 (input -> h1), 2 (h1 -> h2) or 3 (h2 ->
+ * output), host memory: w_host n_prev x n_this row-major f32 (n_w elements),
+ * b_host n_this f32 (n_b elements).  Copied; returns when the copy is done.
+ * Errors: SNN_EINVAL (NULL handle or pointer, layer out of range, wrong
+ *         element counts), SNN_EDEVICE. */
+snn_status snn_ifnet_set_layer(snn_ifnet *net, uint32_t layer, const float *w_host, size_t n_w,
+                               const float *b_host, size_t n_b);
+
+/* Simulate `batch` images_dev (batch x n_in u8, device) for T steps from zero
+ * voltages; stream-ordered and asynchronous like snn_run.
+ * Errors: SNN_EINVAL (NULL handle or images, batch = 0, T = 0 or T > 65535,
+ *         a layer not set), SNN_ENOMEM (batch > max_batch; nothing runs),
+ *         SNN_EDEVICE. */
+snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                         const snn_ifnet_outputs *out);
+
+/* Block until the handle's stream has finished its queued work. */
+snn_status snn_ifnet_sync(snn_ifnet *net);
+
 #ifdef __cplusplus
 }
 #endif

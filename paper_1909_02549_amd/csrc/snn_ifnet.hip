@@ -1,0 +1,520 @@
+// snn_ifnet.hip -- the converted feed-forward network of integrate-and-fire
+// neurons with reset by subtraction (ANN to SNN conversion section): analog
+// input, two hidden IF layers, output-layer input summed over the run.
+//
+// Two launches per run:
+//  k_if_input  the analog input's current I1 = (p / 255) W1 + b1, the same at
+//              every step, computed once for the whole batch on a grid of
+//              (32-sample tile) x (32-neuron tile) workgroups;
+//  k_if_net    one workgroup (4 waves) per 32-sample tile runs all T steps:
+//              voltages in registers, the h1 -> h2 contraction and the h2 ->
+//              output contraction on the matrix cores, spikes exchanged
+//              through LDS bit masks; one workgroup barrier per step.
+// All contractions are v_mfma_f32_32x32x16_bf16 with the FP32 weights split
+// into three bfloat16 planes that sum to them exactly; pixels (integers up to
+// 255) and spikes are exact bfloat16 operands, so every product is exact and
+// only the FP32 accumulation rounds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+#include "snn_mfma.h"
+#include "snn_runtime.h"
+
+using namespace snn;
+
+namespace {
+
+constexpr int kMaxH1 = 256, kMaxH2 = 128, kMaxOut = 32;
+constexpr int kMaxK2 = kMaxH1 / 16;  // 16-deep chunks of the h1 -> h2 contraction
+constexpr int kNetThreads = 256;     // 4 waves: h2 tile w, h1 tiles w and w + 4
+constexpr int kM1 = 9;               // LDS words per sample row of the h1 mask (8 + pad)
+constexpr int kM2 = 5;               // the same for h2 (4 + pad)
+
+struct IfDims {
+    int n_in, h1, h2, n_out;
+    int k1, n1t;  // layer 1: 16-deep chunks of n_in, 32-wide tiles of h1
+    int k2, n2t;  // layer 2: chunks of h1, tiles of h2
+    int k3;       // layer 3: chunks of h2 (one tile of outputs)
+};
+
+// Weight fragments: for chunk c (rows 16c..16c+15) and tile q (columns
+// 32q..32q+31) lane l holds column 32q + l % 32, rows 16c + 8 (l / 32) + e,
+// e = 0..7, as 8 bfloat16 codes in a uint4 (element e in half e % 2 of
+// dword e / 2): the B operand of v_mfma_f32_32x32x16_bf16.  Plane p of
+// fragment (c, q) is at P[((c * Nt + q) * 3 + p) * 64 + lane].
+__global__ void k_if_pack(const float *__restrict__ W, int K, int N, int Kc, int Nt, uint4 *__restrict__ P)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Kc * Nt * 64) return;
+    const int lane = idx & 63, cq = idx >> 6;
+    const int c = cq / Nt, q = cq % Nt;
+    const int col = 32 * q + (lane & 31);
+    uint32_t code[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int row = 16 * c + 8 * (lane >> 5) + e;
+        const float w = (row < K && col < N) ? W[(size_t)row * N + col] : 0.f;
+        uint32_t cc[3];
+        split<PREC_FP32>(w, cc);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) code[p][e] = cc[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        uint4 v;
+        v.x = code[p][0] | (code[p][1] << 16);
+        v.y = code[p][2] | (code[p][3] << 16);
+        v.z = code[p][4] | (code[p][5] << 16);
+        v.w = code[p][6] | (code[p][7] << 16);
+        P[(size_t)(cq * 3 + p) * 64 + lane] = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t px_bf16(uint32_t p) { return __float_as_uint((float)p) >> 16; }
+
+struct IfInArgs {
+    const uint8_t *img;  // B x n_in
+    const uint4 *P1;     // layer-1 fragments
+    const float *b1;     // n1t * 32, zero padded
+    float *I1;           // B x n1t * 32
+    int B;
+    int vec8;            // rows start on 8-byte boundaries: 8-pixel loads
+    IfDims d;
+};
+
+// First-layer current of one (32-sample, 32-neuron) tile; the 4 waves take
+// every fourth 16-pixel chunk and their partial sums are added in wave order.
+__global__ __launch_bounds__(256) void k_if_input(IfInArgs a)
+{
+    __shared__ float red[3][16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int s0 = blockIdx.x * 32, q = blockIdx.y;
+    const int srow = s0 + (lane & 31);
+    const bool rv = srow < a.B;
+    const uint8_t *im = a.img + (size_t)(rv ? srow : 0) * a.d.n_in;
+    f32x16_t acc = {};
+    for (int c = w; c < a.d.k1; c += 4) {
+        const int k0 = 16 * c + 8 * (lane >> 5);
+        uint32_t px[8];
+        if (a.vec8 && rv && k0 + 8 <= a.d.n_in) {
+            const uint2 raw = *reinterpret_cast<const uint2 *>(im + k0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                px[e] = (raw.x >> (8 * e)) & 0xFFu;
+                px[4 + e] = (raw.y >> (8 * e)) & 0xFFu;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) px[e] = (rv && k0 + e < a.d.n_in) ? im[k0 + e] : 0u;
+        }
+        uint4 A;
+        A.x = px_bf16(px[0]) | (px_bf16(px[1]) << 16);
+        A.y = px_bf16(px[2]) | (px_bf16(px[3]) << 16);
+        A.z = px_bf16(px[4]) | (px_bf16(px[5]) << 16);
+        A.w = px_bf16(px[6]) | (px_bf16(px[7]) << 16);
+        const uint4 *pb = a.P1 + (size_t)((c * a.d.n1t + q) * 3) * 64 + lane;
+        const uint4 h = pb[0], m = pb[64], l = pb[128];
+        acc = mfma<PREC_FP32>(A, h, acc);
+        acc = mfma<PREC_FP32>(A, m, acc);
+        acc = mfma<PREC_FP32>(A, l, acc);
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[w - 1][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (w == 0) {
+        const int n1p = 32 * a.d.n1t;
+        const int col = 32 * q + (lane & 31);
+        const float bias = a.b1[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float sum = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (s0 + row < a.B) a.I1[(size_t)(s0 + row) * n1p + col] = sum * (1.f / 255.f) + bias;
+        }
+    }
+}
+
+struct IfNetArgs {
+    const float *I1;  // B x n1t * 32
+    const uint4 *P2, *P3;
+    const float *b2, *b3;  // padded to 32-wide tiles
+    float th1, th2;
+    int B, T;
+    IfDims d;
+    snn_ifnet_outputs o;
+};
+
+// LDS of k_if_net: the staged h2 weights (planes 0 and 1; reused for the
+// readout's partial sums at the end), then the h1 masks (two steps) and the
+// h2 mask.
+__host__ __device__ inline size_t net_w2_region(const IfDims &d)
+{
+    const size_t w2 = (size_t)d.k2 * d.n2t * 2 * 64 * sizeof(uint4);
+    const size_t fin = (4 * 16 * 64 + 32 * 32) * sizeof(float);
+    return w2 > fin ? w2 : fin;
+}
+__host__ __device__ inline size_t net_lds_bytes(const IfDims &d)
+{
+    return net_w2_region(d) + (2 * 32 * kM1 + 32 * kM2) * sizeof(uint32_t);
+}
+
+// One 32-sample tile for all T steps.  Wave w owns h1 tiles w and w + 4 (C
+// layout: lane l holds neuron 32q + l % 32 of samples 8 (r / 4) + 4 (l / 32)
+// + r % 4, r = 0..15), h2 tile w, and output chunks 2w and 2w + 1 (the h2
+// neurons of its own tile), so only the h1 spikes cross waves.
+__global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
+{
+    extern __shared__ uint4 lds_if[];
+    const IfDims d = a.d;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s0 = blockIdx.x * 32;
+    const int w2n = d.k2 * d.n2t * 2 * 64;  // uint4 of the staged h2 weights (planes 0, 1)
+    const size_t w2_region = net_w2_region(d);
+    uint4 *w2s = lds_if;
+    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds_if) + w2_region);
+    uint32_t *mask2 = mask1 + 2 * 32 * kM1;
+
+    for (int i = tid; i < w2n; i += kNetThreads) {
+        const int g = i >> 6, ln = i & 63;
+        w2s[i] = a.P2[(size_t)((g >> 1) * 3 + (g & 1)) * 64 + ln];
+    }
+
+    const int n1p = 32 * d.n1t;
+    float I1[2][16], v1[2][16];
+    uint32_t cnt1[2][8];
+    bool has1[2];
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi) {
+        const int q1 = w + 4 * qi;
+        has1[qi] = q1 < d.n1t;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            I1[qi][r] = (has1[qi] && s < a.B) ? a.I1[(size_t)s * n1p + 32 * q1 + (lane & 31)] : 0.f;
+            v1[qi][r] = 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cnt1[qi][j] = 0;
+    }
+    const int q2 = w;
+    const bool has2 = q2 < d.n2t;
+    uint4 lo2[kMaxK2];
+#pragma unroll
+    for (int c = 0; c < kMaxK2; ++c)
+        lo2[c] = (has2 && c < d.k2) ? a.P2[(size_t)((c * d.n2t + q2) * 3 + 2) * 64 + lane] : make_uint4(0, 0, 0, 0);
+    const float bias2 = has2 ? a.b2[32 * q2 + (lane & 31)] : 0.f;
+    uint4 w3[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int c3 = 2 * w + j;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+            w3[j][p] = c3 < d.k3 ? a.P3[(size_t)(c3 * 3 + p) * 64 + lane] : make_uint4(0, 0, 0, 0);
+    }
+    float v2[16];
+    uint32_t cnt2[8];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v2[r] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cnt2[j] = 0;
+    f32x16_t acc3 = {};
+    const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
+    const int col_in = lane & 31;
+    __syncthreads();
+
+    for (int t = 0; t < a.T; ++t) {
+        uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
+        // hidden layer 1: integrate the constant current, spike, subtract
+#pragma unroll
+        for (int qi = 0; qi < 2; ++qi) {
+            if (!has1[qi]) continue;
+            const int q1 = w + 4 * qi, col = 32 * q1 + col_in;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float u = v1[qi][r] + I1[qi][r];
+                const bool s = u >= a.th1;
+                v1[qi][r] = s ? u - a.th1 : u;
+                cnt1[qi][r >> 1] += (uint32_t)s << (16 * (r & 1));
+                const uint64_t m = __builtin_amdgcn_ballot_w64(s);
+                const int row0 = 8 * (r >> 2) + (r & 3);
+                if (lane == 0) {
+                    m1[row0 * kM1 + q1] = (uint32_t)m;
+                    m1[(row0 + 4) * kM1 + q1] = (uint32_t)(m >> 32);
+                }
+                if (a.o.v_h1) {
+                    const int s_ = s0 + row0 + 4 * (lane >> 5);
+                    if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[qi][r];
+                }
+            }
+        }
+        __syncthreads();
+        if (a.o.raster_h1) {
+            for (int i = tid; i < 32 * h1w; i += kNetThreads) {
+                const int row = i / h1w, wd = i - row * h1w;
+                if (s0 + row < a.B) a.o.raster_h1[((size_t)t * a.B + s0 + row) * h1w + wd] = m1[row * kM1 + wd];
+            }
+        }
+        if (!has2) continue;
+        // hidden layer 2: current from this step's h1 spikes
+        f32x16_t acc2 = {};
+#pragma unroll
+        for (int c = 0; c < kMaxK2; ++c) {
+            if (c < d.k2) {
+                const uint32_t word = m1[col_in * kM1 + (c >> 1)];
+                const uint4 A = ones_bf16((word >> (16 * (c & 1) + 8 * (lane >> 5))) & 0xFFu);
+                const uint4 *wb = w2s + (size_t)((c * d.n2t + q2) * 2) * 64 + lane;
+                acc2 = mfma<PREC_FP32>(A, wb[0], acc2);
+                acc2 = mfma<PREC_FP32>(A, wb[64], acc2);
+                acc2 = mfma<PREC_FP32>(A, lo2[c], acc2);
+            }
+        }
+        const int col2 = 32 * q2 + col_in;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float u = v2[r] + (acc2[r] + bias2);
+            const bool s = u >= a.th2;
+            v2[r] = s ? u - a.th2 : u;
+            cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
+            const uint64_t m = __builtin_amdgcn_ballot_w64(s);
+            const int row0 = 8 * (r >> 2) + (r & 3);
+            if (lane == 0) {
+                mask2[row0 * kM2 + q2] = (uint32_t)m;
+                mask2[(row0 + 4) * kM2 + q2] = (uint32_t)(m >> 32);
+                if (a.o.raster_h2) {
+                    if (s0 + row0 < a.B) a.o.raster_h2[((size_t)t * a.B + s0 + row0) * h2w + q2] = (uint32_t)m;
+                    if (s0 + row0 + 4 < a.B)
+                        a.o.raster_h2[((size_t)t * a.B + s0 + row0 + 4) * h2w + q2] = (uint32_t)(m >> 32);
+                }
+            }
+            if (a.o.v_h2) {
+                const int s_ = s0 + row0 + 4 * (lane >> 5);
+                if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
+            }
+        }
+        // the wave reads back its own h2 spikes as the output layer's operand
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c3 = 2 * w + j;
+            if (c3 < d.k3) {
+                const uint32_t word = mask2[col_in * kM2 + (c3 >> 1)];
+                const uint4 A = ones_bf16((word >> (16 * (c3 & 1) + 8 * (lane >> 5))) & 0xFFu);
+                acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
+                acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
+                acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
+            }
+        }
+    }
+
+    // spike counts
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi) {
+        const int col = 32 * (w + 4 * qi) + col_in;
+        if (!a.o.counts_h1 || !has1[qi] || col >= d.h1) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (s < a.B) a.o.counts_h1[(size_t)s * d.h1 + col] = (cnt1[qi][r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+        }
+    }
+    if (a.o.counts_h2 && has2 && 32 * q2 + col_in < d.h2) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (s < a.B) a.o.counts_h2[(size_t)s * d.h2 + 32 * q2 + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+        }
+    }
+
+    // readout: the waves' partial sums, added in wave order, plus T * b3
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(lds_if);
+    float *fin = red + 4 * 16 * 64;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[(w * 16 + r) * 64 + lane] = acc3[r];
+    __syncthreads();
+    for (int i = tid; i < 16 * 64; i += kNetThreads) {
+        const int r = i >> 6, ln = i & 63;
+        const float sum = ((red[r * 64 + ln] + red[(16 + r) * 64 + ln]) + red[(32 + r) * 64 + ln]) +
+                          red[(48 + r) * 64 + ln];
+        const int col = ln & 31, row = 8 * (r >> 2) + 4 * (ln >> 5) + (r & 3);
+        const float val = sum + (float)a.T * a.b3[col];
+        fin[row * 32 + col] = val;
+        if (a.o.out_sum && col < d.n_out && s0 + row < a.B) a.o.out_sum[(size_t)(s0 + row) * d.n_out + col] = val;
+    }
+    __syncthreads();
+    if (a.o.pred && tid < 32 && s0 + tid < a.B) {
+        int best = 0;
+        float bv = fin[tid * 32];
+        for (int o = 1; o < d.n_out; ++o) {
+            const float x = fin[tid * 32 + o];
+            if (x > bv) {
+                bv = x;
+                best = o;
+            }
+        }
+        a.o.pred[s0 + tid] = best;
+    }
+}
+
+}  // namespace
+
+struct snn_ifnet {
+    snn_ifnet_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    IfDims d{};
+    uint4 *P[3] = {nullptr, nullptr, nullptr};
+    float *b[3] = {nullptr, nullptr, nullptr};
+    float *I1 = nullptr;
+    float *wtmp = nullptr;
+    size_t wtmp_n = 0;
+    bool set[3] = {false, false, false};
+    size_t lds = 0;
+    ~snn_ifnet()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        else (void)hipDeviceSynchronize();
+        for (int l = 0; l < 3; ++l) {
+            if (P[l]) (void)hipFree(P[l]);
+            if (b[l]) (void)hipFree(b[l]);
+        }
+        if (I1) (void)hipFree(I1);
+        if (wtmp) (void)hipFree(wtmp);
+    }
+    // rows K, columns N, 16-deep chunks, 32-wide tiles of layer l (0-based)
+    void shape(int l, int &K, int &N, int &Kc, int &Nt) const
+    {
+        K = l == 0 ? d.n_in : l == 1 ? d.h1 : d.h2;
+        N = l == 0 ? d.h1 : l == 1 ? d.h2 : d.n_out;
+        Kc = (K + 15) / 16;
+        Nt = (N + 31) / 32;
+    }
+};
+
+#define IF_TRY(call)                                                                                    \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return snn_net::error(SNN_EDEVICE, (std::string(#call) + ": " + hipGetErrorString(e_)).c_str()); \
+    } while (0)
+
+extern "C" snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream, snn_ifnet **out)
+{
+    if (!out) return snn_net::error(SNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return snn_net::error(SNN_EINVAL, "snn_ifnet_config is NULL");
+    if (cfg->abi_version != SNN_ABI_VERSION) return snn_net::error(SNN_EINVAL, "abi_version mismatch");
+    if (cfg->n_in < 1 || cfg->n_in > 65536) return snn_net::error(SNN_EINVAL, "n_in must be in [1, 65536]");
+    if (cfg->n_h1 < 1 || cfg->n_h1 > (uint32_t)kMaxH1) return snn_net::error(SNN_EINVAL, "n_h1 must be in [1, 256]");
+    if (cfg->n_h2 < 1 || cfg->n_h2 > (uint32_t)kMaxH2) return snn_net::error(SNN_EINVAL, "n_h2 must be in [1, 128]");
+    if (cfg->n_out < 1 || cfg->n_out > (uint32_t)kMaxOut) return snn_net::error(SNN_EINVAL, "n_out must be in [1, 32]");
+    if (!(cfg->theta_h1 > 0.0) || !(cfg->theta_h2 > 0.0) || cfg->theta_h1 > 1e30 || cfg->theta_h2 > 1e30)
+        return snn_net::error(SNN_EINVAL, "thresholds must be finite and > 0");
+    if (cfg->max_batch < 1 || cfg->max_batch > (1u << 24)) return snn_net::error(SNN_EINVAL, "max_batch must be in [1, 2^24]");
+    snn_ifnet *n = new (std::nothrow) snn_ifnet();
+    if (!n) return snn_net::error(SNN_ENOMEM, "host allocation failed");
+    n->cfg = *cfg;
+    n->stream = static_cast<hipStream_t>(stream);
+    IfDims &d = n->d;
+    d.n_in = cfg->n_in;
+    d.h1 = cfg->n_h1;
+    d.h2 = cfg->n_h2;
+    d.n_out = cfg->n_out;
+    d.k1 = (d.n_in + 15) / 16;
+    d.n1t = (d.h1 + 31) / 32;
+    d.k2 = (d.h1 + 15) / 16;
+    d.n2t = (d.h2 + 31) / 32;
+    d.k3 = (d.h2 + 15) / 16;
+    n->lds = net_lds_bytes(d);
+    auto bail = [&](hipError_t e, const char *what) {
+        delete n;
+        return snn_net::error(e == hipErrorOutOfMemory ? SNN_ENOMEM : SNN_EDEVICE,
+                              (std::string(what) + ": " + hipGetErrorString(e)).c_str());
+    };
+    hipError_t e = hipGetDevice(&n->device);
+    if (e != hipSuccess) return bail(e, "hipGetDevice");
+    size_t wmax = 0;
+    for (int l = 0; l < 3; ++l) {
+        int K, N, Kc, Nt;
+        n->shape(l, K, N, Kc, Nt);
+        wmax = std::max(wmax, (size_t)K * N);
+        if ((e = hipMalloc(&n->P[l], (size_t)Kc * Nt * 3 * 64 * sizeof(uint4))) != hipSuccess) return bail(e, "hipMalloc");
+        if ((e = hipMalloc(&n->b[l], (size_t)Nt * 32 * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc");
+    }
+    n->wtmp_n = wmax;
+    if ((e = hipMalloc(&n->wtmp, wmax * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&n->I1, (size_t)cfg->max_batch * 32 * d.n1t * sizeof(float))) != hipSuccess)
+        return bail(e, "hipMalloc");
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_if_net), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)n->lds)) != hipSuccess)
+        return bail(e, "hipFuncSetAttribute");
+    *out = n;
+    return SNN_OK;
+}
+
+extern "C" void snn_ifnet_destroy(snn_ifnet *net) { delete net; }
+
+extern "C" snn_status snn_ifnet_set_layer(snn_ifnet *net, uint32_t layer, const float *w_host, size_t n_w,
+                                          const float *b_host, size_t n_b)
+{
+    if (!net) return snn_net::error(SNN_EINVAL, "net is NULL");
+    if (layer < 1 || layer > 3) return snn_net::error(SNN_EINVAL, "layer must be 1, 2 or 3");
+    if (!w_host || !b_host) return snn_net::error(SNN_EINVAL, "weights or biases are NULL");
+    const int l = (int)layer - 1;
+    int K, N, Kc, Nt;
+    net->shape(l, K, N, Kc, Nt);
+    if (n_w != (size_t)K * N) return snn_net::error(SNN_EINVAL, "weight count does not match the layer sizes");
+    if (n_b != (size_t)N) return snn_net::error(SNN_EINVAL, "bias count does not match the layer size");
+    std::vector<float> bp((size_t)Nt * 32, 0.f);
+    std::memcpy(bp.data(), b_host, n_b * sizeof(float));
+    IF_TRY(hipMemcpyAsync(net->wtmp, w_host, n_w * sizeof(float), hipMemcpyHostToDevice, net->stream));
+    IF_TRY(hipMemcpyAsync(net->b[l], bp.data(), bp.size() * sizeof(float), hipMemcpyHostToDevice, net->stream));
+    const int items = Kc * Nt * 64;
+    hipLaunchKernelGGL(k_if_pack, dim3((items + 255) / 256), dim3(256), 0, net->stream, net->wtmp, K, N, Kc, Nt,
+                       net->P[l]);
+    IF_TRY(hipGetLastError());
+    IF_TRY(hipStreamSynchronize(net->stream));
+    net->set[l] = true;
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                                    const snn_ifnet_outputs *out)
+{
+    if (!net) return snn_net::error(SNN_EINVAL, "net is NULL");
+    if (!images_dev) return snn_net::error(SNN_EINVAL, "images_dev is NULL");
+    if (batch == 0) return snn_net::error(SNN_EINVAL, "batch must be > 0");
+    if (T == 0 || T > 65535) return snn_net::error(SNN_EINVAL, "T must be in [1, 65535]");
+    if (!net->set[0] || !net->set[1] || !net->set[2]) return snn_net::error(SNN_EINVAL, "every layer must be set first");
+    if (batch > net->cfg.max_batch) return snn_net::error(SNN_ENOMEM, "batch exceeds max_batch");
+    snn_ifnet_outputs o{};
+    if (out) o = *out;
+    const int tiles = (int)((batch + 31) / 32);
+    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch,
+                (net->d.n_in % 8 == 0 && (reinterpret_cast<uintptr_t>(images_dev) & 7) == 0) ? 1 : 0, net->d};
+    hipLaunchKernelGGL(k_if_input, dim3(tiles, net->d.n1t), dim3(256), 0, net->stream, ia);
+    IF_TRY(hipGetLastError());
+    IfNetArgs na{net->I1, net->P[1], net->P[2], net->b[1], net->b[2], (float)net->cfg.theta_h1,
+                 (float)net->cfg.theta_h2, (int)batch, (int)T, net->d, o};
+    hipLaunchKernelGGL(k_if_net, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
+    IF_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_ifnet_sync(snn_ifnet *net)
+{
+    if (!net) return snn_net::error(SNN_EINVAL, "net is NULL");
+    IF_TRY(hipStreamSynchronize(net->stream));
+    return SNN_OK;
+}

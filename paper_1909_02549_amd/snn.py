@@ -29,7 +29,8 @@ EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "s
             "snn_set_path", "snn_last_path", "snn_set_graphs", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
-            "snn_serve_destroy"]
+            "snn_serve_destroy", "snn_ifnet_create", "snn_ifnet_destroy", "snn_ifnet_set_layer", "snn_ifnet_run",
+            "snn_ifnet_sync"]
 
 
 class SnnError(RuntimeError):
@@ -59,6 +60,18 @@ class snn_config(C.Structure):
 class snn_outputs(C.Structure):
     _fields_ = [("counts", C.c_void_p), ("raster_in", C.c_void_p), ("raster_exc", C.c_void_p),
                 ("raster_inh", C.c_void_p), ("v_exc", C.c_void_p), ("v_inh", C.c_void_p)]
+
+
+class snn_ifnet_config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("n_in", C.c_uint32), ("n_h1", C.c_uint32), ("n_h2", C.c_uint32),
+                ("n_out", C.c_uint32), ("max_batch", C.c_uint32), ("theta_h1", C.c_double),
+                ("theta_h2", C.c_double)]
+
+
+class snn_ifnet_outputs(C.Structure):
+    _fields_ = [("out_sum", C.c_void_p), ("pred", C.c_void_p), ("counts_h1", C.c_void_p),
+                ("counts_h2", C.c_void_p), ("raster_h1", C.c_void_p), ("raster_h2", C.c_void_p),
+                ("v_h1", C.c_void_p), ("v_h2", C.c_void_p)]
 
 
 _lib = None
@@ -99,6 +112,11 @@ def load_library():
         "snn_serve_poll": ([VP, U64, VP, P(C.c_double)], I32),
         "snn_serve_stats": ([VP, P(U64), P(U64), P(U32), P(C.c_double)], I32),
         "snn_serve_destroy": ([VP], I32),
+        "snn_ifnet_create": ([P(snn_ifnet_config), VP, P(VP)], I32),
+        "snn_ifnet_destroy": ([VP], None),
+        "snn_ifnet_set_layer": ([VP, U32, VP, SZ, VP, SZ], I32),
+        "snn_ifnet_run": ([VP, VP, U32, U32, P(snn_ifnet_outputs)], I32),
+        "snn_ifnet_sync": ([VP], I32),
     }
     for name, (args, res) in sig.items():
         if not hasattr(lib, name):
@@ -321,6 +339,76 @@ class Server:
             self.snn_serve_destroy()
         except Exception:
             pass
+
+
+def make_ifnet_config(sizes, thresholds=(1.0, 1.0), max_batch: int = 1024) -> snn_ifnet_config:
+    c = snn_ifnet_config()
+    c.abi_version = SNN_ABI_VERSION
+    c.n_in, c.n_h1, c.n_h2, c.n_out = (int(x) for x in sizes)
+    c.max_batch = int(max_batch)
+    c.theta_h1, c.theta_h2 = (float(x) for x in thresholds)
+    return c
+
+
+class IFNet:
+    """Converted feed-forward IF network handle (``snn_ifnet_*`` calls)."""
+
+    def __init__(self, sizes, thresholds=(1.0, 1.0), max_batch: int = 1024, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP path has no CPU fallback")
+        self.lib = load_library()
+        self.sizes = tuple(int(x) for x in sizes)
+        self.c = make_ifnet_config(self.sizes, thresholds, max_batch)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        h = C.c_void_p()
+        _check(self.lib.snn_ifnet_create(C.byref(self.c), C.c_void_p(s.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.snn_ifnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def snn_ifnet_set_layer(self, layer: int, W: np.ndarray, b: np.ndarray):
+        w = np.ascontiguousarray(W, dtype=np.float32)
+        bb = np.ascontiguousarray(b, dtype=np.float32)
+        assert w.shape == (self.sizes[layer - 1], self.sizes[layer]) and bb.shape == (self.sizes[layer],)
+        _check(self.lib.snn_ifnet_set_layer(self.h, int(layer), w.ctypes.data, w.size, bb.ctypes.data, bb.size))
+
+    def set_layers(self, layers):
+        for l, (W, b) in enumerate(layers, start=1):
+            self.snn_ifnet_set_layer(l, W, b)
+
+    def snn_ifnet_run(self, images, T: int, record=("out_sum", "pred")):
+        """images: cuda uint8 (B, n_in).  Returns the requested device outputs
+        (asynchronous): out_sum, pred, counts_h1/h2, raster_h1/h2, v_h1/h2."""
+        import torch
+        B = int(images.shape[0])
+        assert images.is_cuda and images.dtype == torch.uint8 and images.is_contiguous()
+        assert images.shape == (B, self.sizes[0])
+        dev = images.device
+        n1, n2, no = self.sizes[1], self.sizes[2], self.sizes[3]
+        shapes = {"out_sum": ((B, no), torch.float32), "pred": ((B,), torch.int32),
+                  "counts_h1": ((B, n1), torch.int32), "counts_h2": ((B, n2), torch.int32),
+                  "raster_h1": ((T, B, (n1 + 31) // 32), torch.int32),
+                  "raster_h2": ((T, B, (n2 + 31) // 32), torch.int32),
+                  "v_h1": ((T, B, n1), torch.float32), "v_h2": ((T, B, n2), torch.float32)}
+        out = {k: torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev) for k in record}
+        o = snn_ifnet_outputs(*(_ptr(out.get(k)) for k in ("out_sum", "pred", "counts_h1", "counts_h2",
+                                                           "raster_h1", "raster_h2", "v_h1", "v_h2")))
+        _check(self.lib.snn_ifnet_run(self.h, _ptr(images), B, int(T), C.byref(o)))
+        return out
+
+    def snn_ifnet_sync(self):
+        _check(self.lib.snn_ifnet_sync(self.h))
 
 
 def unpack_bits(words, n: int) -> np.ndarray:

@@ -91,3 +91,21 @@ def test_bit_packing_roundtrip():
         assert w.shape == (3, 5, (n + 31) // 32)
         assert np.array_equal(unpack_bits(w, n), x)
     assert pack_bits(np.array([1, 0, 0, 0, 0, 1] + [0] * 26, np.uint8))[0] == (1 | 1 << 5)
+
+
+@pytest.mark.parametrize("field,value", [("abi_version", 7), ("n_in", 0), ("n_h1", 0), ("n_h1", 257),
+                                         ("n_h2", 129), ("n_out", 33), ("n_out", 0), ("max_batch", 0),
+                                         ("theta_h1", 0.0), ("theta_h2", -1.0)])
+def test_invalid_ifnet_config_rejected_without_gpu(lib, field, value):
+    from paper_1909_02549_amd import snn
+    c = snn.make_ifnet_config((784, 256, 128, 10), (1.0, 1.0), 16)
+    setattr(c, field, value)
+    h = C.c_void_p()
+    assert lib.snn_ifnet_create(C.byref(c), None, C.byref(h)) == -1 and not h.value
+    assert lib.snn_last_error().decode()
+
+
+def test_ifnet_null_handle_calls(lib):
+    assert lib.snn_ifnet_run(None, None, 1, 1, None) == -1
+    assert lib.snn_ifnet_sync(None) == -1
+    assert lib.snn_ifnet_set_layer(None, 1, None, 0, None, 0) == -1
