@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kMaxH1 = 256, kMaxH2 = 128, kMaxOut = 32;
 constexpr int kMaxK2 = kMaxH1 / 16;  // 16-deep chunks of the h1 -> h2 contraction
-constexpr int kNetThreads = 256;     // 4 waves: h2 tile w, h1 tiles w and w + 4
+constexpr int kNetThreads = 512;     // 8 waves: h2 tile w (w < 4), h1 tiles w - 4, w (w >= 4)
 constexpr int kM1 = 9;               // LDS words per sample row of the h1 mask (8 + pad)
 constexpr int kM2 = 5;               // the same for h2 (4 + pad)
 
@@ -89,41 +89,69 @@ struct IfInArgs {
     IfDims d;
 };
 
-// First-layer current of one (32-sample, 32-neuron) tile; the 4 waves take
-// every fourth 16-pixel chunk and their partial sums are added in wave order.
-__global__ __launch_bounds__(256) void k_if_input(IfInArgs a)
+// First-layer current of one (32-sample, 32-neuron) tile.  The 16 waves
+// take every sixteenth 16-pixel chunk, four chunks' operands loaded before
+// their products; the partial sums are added in wave order.
+constexpr int kInWaves = 16;
+
+// 8 pixels (bytes) of one sample as bfloat16 operand elements.
+template <bool VEC8>
+__device__ __forceinline__ uint4 pixels_bf16(const uint8_t *im, int k0, int n_in)
 {
-    __shared__ float red[3][16][64];
+    uint32_t px[8];
+    if constexpr (VEC8) {  // n_in % 8 == 0, k0 < n_in: the 8 bytes are in the row
+        const uint2 raw = *reinterpret_cast<const uint2 *>(im + k0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            px[e] = (raw.x >> (8 * e)) & 0xFFu;
+            px[4 + e] = (raw.y >> (8 * e)) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) px[e] = k0 + e < n_in ? im[k0 + e] : 0u;
+    }
+    uint4 A;
+    A.x = px_bf16(px[0]) | (px_bf16(px[1]) << 16);
+    A.y = px_bf16(px[2]) | (px_bf16(px[3]) << 16);
+    A.z = px_bf16(px[4]) | (px_bf16(px[5]) << 16);
+    A.w = px_bf16(px[6]) | (px_bf16(px[7]) << 16);
+    return A;
+}
+
+// Loads are unconditional (addresses clamped into range) so that a wave's
+// four chunks are in flight together; the operand of a chunk past the end
+// or of a sample past the batch is zeroed instead.
+template <bool VEC8>
+__global__ __launch_bounds__(64 * kInWaves) void k_if_input(IfInArgs a)
+{
+    __shared__ float red[kInWaves - 1][16][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int s0 = blockIdx.x * 32, q = blockIdx.y;
     const int srow = s0 + (lane & 31);
     const bool rv = srow < a.B;
-    const uint8_t *im = a.img + (size_t)(rv ? srow : 0) * a.d.n_in;
+    const uint8_t *im = a.img + (size_t)(rv ? srow : s0) * a.d.n_in;
+    const int k1 = a.d.k1, n1t = a.d.n1t;
+    const uint4 zero = make_uint4(0, 0, 0, 0);
     f32x16_t acc = {};
-    for (int c = w; c < a.d.k1; c += 4) {
-        const int k0 = 16 * c + 8 * (lane >> 5);
-        uint32_t px[8];
-        if (a.vec8 && rv && k0 + 8 <= a.d.n_in) {
-            const uint2 raw = *reinterpret_cast<const uint2 *>(im + k0);
+    for (int base = w; base < k1; base += 4 * kInWaves) {
+        uint4 A[4], Bh[4], Bm[4], Bl[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                px[e] = (raw.x >> (8 * e)) & 0xFFu;
-                px[4 + e] = (raw.y >> (8 * e)) & 0xFFu;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) px[e] = (rv && k0 + e < a.d.n_in) ? im[k0 + e] : 0u;
+        for (int j = 0; j < 4; ++j) {
+            const int c = base + j * kInWaves;
+            const int cc = c < k1 ? c : base;
+            A[j] = pixels_bf16<VEC8>(im, 16 * cc + 8 * (lane >> 5), a.d.n_in);
+            if (!(rv && c < k1)) A[j] = zero;
+            const uint4 *pb = a.P1 + (size_t)((cc * n1t + q) * 3) * 64 + lane;
+            Bh[j] = pb[0];
+            Bm[j] = pb[64];
+            Bl[j] = pb[128];
         }
-        uint4 A;
-        A.x = px_bf16(px[0]) | (px_bf16(px[1]) << 16);
-        A.y = px_bf16(px[2]) | (px_bf16(px[3]) << 16);
-        A.z = px_bf16(px[4]) | (px_bf16(px[5]) << 16);
-        A.w = px_bf16(px[6]) | (px_bf16(px[7]) << 16);
-        const uint4 *pb = a.P1 + (size_t)((c * a.d.n1t + q) * 3) * 64 + lane;
-        const uint4 h = pb[0], m = pb[64], l = pb[128];
-        acc = mfma<PREC_FP32>(A, h, acc);
-        acc = mfma<PREC_FP32>(A, m, acc);
-        acc = mfma<PREC_FP32>(A, l, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc = mfma<PREC_FP32>(A[j], Bh[j], acc);
+            acc = mfma<PREC_FP32>(A[j], Bm[j], acc);
+            acc = mfma<PREC_FP32>(A[j], Bl[j], acc);
+        }
     }
     if (w > 0) {
 #pragma unroll
@@ -131,12 +159,14 @@ __global__ __launch_bounds__(256) void k_if_input(IfInArgs a)
     }
     __syncthreads();
     if (w == 0) {
-        const int n1p = 32 * a.d.n1t;
+        const int n1p = 32 * n1t;
         const int col = 32 * q + (lane & 31);
         const float bias = a.b1[col];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const float sum = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+            float sum = acc[r];
+#pragma unroll
+            for (int v = 0; v < kInWaves - 1; ++v) sum += red[v][r][lane];
             const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             if (s0 + row < a.B) a.I1[(size_t)(s0 + row) * n1p + col] = sum * (1.f / 255.f) + bias;
         }
@@ -158,7 +188,7 @@ struct IfNetArgs {
 // h2 mask.
 __host__ __device__ inline size_t net_w2_region(const IfDims &d)
 {
-    const size_t w2 = (size_t)d.k2 * d.n2t * 2 * 64 * sizeof(uint4);
+    const size_t w2 = (size_t)(d.k2 * d.n2t * 2 * 64 + 1) * sizeof(uint4);  // + a slot for clamped stores
     const size_t fin = (4 * 16 * 64 + 32 * 32) * sizeof(float);
     return w2 > fin ? w2 : fin;
 }
@@ -167,15 +197,25 @@ __host__ __device__ inline size_t net_lds_bytes(const IfDims &d)
     return net_w2_region(d) + (2 * 32 * kM1 + 32 * kM2) * sizeof(uint32_t);
 }
 
-// One 32-sample tile for all T steps.  Wave w owns h1 tiles w and w + 4 (C
-// layout: lane l holds neuron 32q + l % 32 of samples 8 (r / 4) + 4 (l / 32)
-// + r % 4, r = 0..15), h2 tile w, and output chunks 2w and 2w + 1 (the h2
-// neurons of its own tile), so only the h1 spikes cross waves.
+// One 32-sample tile for all T steps, as a two-stage pipeline of 8 waves
+// (two per SIMD, so one wave's vector work overlaps the other's matrix-core
+// work).  In iteration i:
+//   waves 4..7 ("h1 waves") integrate step i of h1 tiles (w - 4) and
+//     (w - 4) + 4 and publish their spikes as bit masks in buffer i % 2;
+//   waves 0..3 ("h2 waves") run step i - 1 of h2 tile w from buffer
+//     (i - 1) % 2, then the output chunks 2w and 2w + 1 (the h2 neurons of
+//     their own tile, read back within the wave);
+// one workgroup barrier ends the iteration.  C layout of a tile: lane l
+// holds neuron 32q + l % 32 of samples 8 (r / 4) + 4 (l / 32) + r % 4,
+// r = 0..15.  REC: also record voltages and rasters (the parity outputs).
+template <bool REC>
 __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
 {
     extern __shared__ uint4 lds_if[];
     const IfDims d = a.d;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w & 3;
+    const bool h1wave = w >= 4;
     const int s0 = blockIdx.x * 32;
     const int w2n = d.k2 * d.n2t * 2 * 64;  // uint4 of the staged h2 weights (planes 0, 1)
     const size_t w2_region = net_w2_region(d);
@@ -183,168 +223,224 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds_if) + w2_region);
     uint32_t *mask2 = mask1 + 2 * 32 * kM1;
 
-    for (int i = tid; i < w2n; i += kNetThreads) {
-        const int g = i >> 6, ln = i & 63;
-        w2s[i] = a.P2[(size_t)((g >> 1) * 3 + (g & 1)) * 64 + ln];
-    }
-
-    const int n1p = 32 * d.n1t;
-    float I1[2][16], v1[2][16];
-    uint32_t cnt1[2][8];
-    bool has1[2];
+    // stage the h2 weights, 16 loads in flight per thread (loads past the end
+    // re-read element i0 and store it to the spare slot w2s[w2n])
+    for (int i0 = tid; i0 < w2n; i0 += 16 * kNetThreads) {
+        uint4 buf[16];
 #pragma unroll
-    for (int qi = 0; qi < 2; ++qi) {
-        const int q1 = w + 4 * qi;
-        has1[qi] = q1 < d.n1t;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            I1[qi][r] = (has1[qi] && s < a.B) ? a.I1[(size_t)s * n1p + 32 * q1 + (lane & 31)] : 0.f;
-            v1[qi][r] = 0.f;
+        for (int j = 0; j < 16; ++j) {
+            const int i = i0 + j * kNetThreads;
+            const int ii = i < w2n ? i : i0;
+            const int g = ii >> 6, ln = ii & 63;
+            buf[j] = a.P2[(size_t)((g >> 1) * 3 + (g & 1)) * 64 + ln];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) cnt1[qi][j] = 0;
+        for (int j = 0; j < 16; ++j) {
+            const int i = i0 + j * kNetThreads;
+            w2s[i < w2n ? i : w2n] = buf[j];
+        }
     }
-    const int q2 = w;
-    const bool has2 = q2 < d.n2t;
-    uint4 lo2[kMaxK2];
-#pragma unroll
-    for (int c = 0; c < kMaxK2; ++c)
-        lo2[c] = (has2 && c < d.k2) ? a.P2[(size_t)((c * d.n2t + q2) * 3 + 2) * 64 + lane] : make_uint4(0, 0, 0, 0);
-    const float bias2 = has2 ? a.b2[32 * q2 + (lane & 31)] : 0.f;
-    uint4 w3[2][3];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int c3 = 2 * w + j;
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-            w3[j][p] = c3 < d.k3 ? a.P3[(size_t)(c3 * 3 + p) * 64 + lane] : make_uint4(0, 0, 0, 0);
-    }
-    float v2[16];
-    uint32_t cnt2[8];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v2[r] = 0.f;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) cnt2[j] = 0;
-    f32x16_t acc3 = {};
-    const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
-    const int col_in = lane & 31;
-    __syncthreads();
 
-    for (int t = 0; t < a.T; ++t) {
-        uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
-        // hidden layer 1: integrate the constant current, spike, subtract
+    const int col_in = lane & 31;
+    const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+    float *red = reinterpret_cast<float *>(lds_if);  // readout partial sums (after the loop)
+
+    // Each role runs its own loop with one barrier per iteration (T + 1 in
+    // both), so that only its own state is live in registers.
+    if (h1wave) {
+        const int n1p = 32 * d.n1t;
+        float I1[2][16], v1[2][16];
+        uint32_t cnt1[2][8];
+        bool has1[2];
 #pragma unroll
         for (int qi = 0; qi < 2; ++qi) {
-            if (!has1[qi]) continue;
-            const int q1 = w + 4 * qi, col = 32 * q1 + col_in;
+            const int q1 = wr + 4 * qi;
+            has1[qi] = q1 < d.n1t;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float u = v1[qi][r] + I1[qi][r];
-                const bool s = u >= a.th1;
-                v1[qi][r] = s ? u - a.th1 : u;
-                cnt1[qi][r >> 1] += (uint32_t)s << (16 * (r & 1));
-                const uint64_t m = __builtin_amdgcn_ballot_w64(s);
-                const int row0 = 8 * (r >> 2) + (r & 3);
-                if (lane == 0) {
-                    m1[row0 * kM1 + q1] = (uint32_t)m;
-                    m1[(row0 + 4) * kM1 + q1] = (uint32_t)(m >> 32);
-                }
-                if (a.o.v_h1) {
-                    const int s_ = s0 + row0 + 4 * (lane >> 5);
-                    if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[qi][r];
-                }
+                const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const bool ok = has1[qi] && s < a.B;
+                const float x = a.I1[(size_t)(ok ? s : s0) * n1p + 32 * (has1[qi] ? q1 : 0) + col_in];
+                I1[qi][r] = ok ? x : 0.f;
+                v1[qi][r] = 0.f;
             }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cnt1[qi][j] = 0;
         }
         __syncthreads();
-        if (a.o.raster_h1) {
-            for (int i = tid; i < 32 * h1w; i += kNetThreads) {
-                const int row = i / h1w, wd = i - row * h1w;
-                if (s0 + row < a.B) a.o.raster_h1[((size_t)t * a.B + s0 + row) * h1w + wd] = m1[row * kM1 + wd];
-            }
-        }
-        if (!has2) continue;
-        // hidden layer 2: current from this step's h1 spikes
-        f32x16_t acc2 = {};
+        for (int i = 0; i <= a.T; ++i) {
+            if (i < a.T) {
+                const int t = i;
+                uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
 #pragma unroll
-        for (int c = 0; c < kMaxK2; ++c) {
-            if (c < d.k2) {
-                const uint32_t word = m1[col_in * kM1 + (c >> 1)];
-                const uint4 A = ones_bf16((word >> (16 * (c & 1) + 8 * (lane >> 5))) & 0xFFu);
-                const uint4 *wb = w2s + (size_t)((c * d.n2t + q2) * 2) * 64 + lane;
-                acc2 = mfma<PREC_FP32>(A, wb[0], acc2);
-                acc2 = mfma<PREC_FP32>(A, wb[64], acc2);
-                acc2 = mfma<PREC_FP32>(A, lo2[c], acc2);
-            }
-        }
-        const int col2 = 32 * q2 + col_in;
+                for (int qi = 0; qi < 2; ++qi) {
+                    if (!has1[qi]) continue;
+                    const int q1 = wr + 4 * qi, col = 32 * q1 + col_in;
+                    // the ballot of row r holds samples row0 (low half) and
+                    // row0 + 4 (high half); one lane stores the 32 words
+                    uint64_t mb[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float u = v2[r] + (acc2[r] + bias2);
-            const bool s = u >= a.th2;
-            v2[r] = s ? u - a.th2 : u;
-            cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
-            const uint64_t m = __builtin_amdgcn_ballot_w64(s);
-            const int row0 = 8 * (r >> 2) + (r & 3);
-            if (lane == 0) {
-                mask2[row0 * kM2 + q2] = (uint32_t)m;
-                mask2[(row0 + 4) * kM2 + q2] = (uint32_t)(m >> 32);
-                if (a.o.raster_h2) {
-                    if (s0 + row0 < a.B) a.o.raster_h2[((size_t)t * a.B + s0 + row0) * h2w + q2] = (uint32_t)m;
-                    if (s0 + row0 + 4 < a.B)
-                        a.o.raster_h2[((size_t)t * a.B + s0 + row0 + 4) * h2w + q2] = (uint32_t)(m >> 32);
+                    for (int r = 0; r < 16; ++r) {
+                        const float u = v1[qi][r] + I1[qi][r];
+                        const bool s = u >= a.th1;
+                        v1[qi][r] = s ? u - a.th1 : u;
+                        cnt1[qi][r >> 1] += (uint32_t)s << (16 * (r & 1));
+                        mb[r] = __builtin_amdgcn_ballot_w64(s);
+                        if (REC && a.o.v_h1) {
+                            const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
+                            if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[qi][r];
+                        }
+                    }
+                    if (lane == 0) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row0 = 8 * (r >> 2) + (r & 3);
+                            m1[row0 * kM1 + q1] = (uint32_t)mb[r];
+                            m1[(row0 + 4) * kM1 + q1] = (uint32_t)(mb[r] >> 32);
+                        }
+                    }
                 }
             }
-            if (a.o.v_h2) {
-                const int s_ = s0 + row0 + 4 * (lane >> 5);
-                if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
+            __syncthreads();
+        }
+        if (a.o.counts_h1) {
+#pragma unroll
+            for (int qi = 0; qi < 2; ++qi) {
+                const int col = 32 * (wr + 4 * qi) + col_in;
+                if (!has1[qi] || col >= d.h1) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (s < a.B)
+                        a.o.counts_h1[(size_t)s * d.h1 + col] = (cnt1[qi][r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+                }
             }
         }
-        // the wave reads back its own h2 spikes as the output layer's operand
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        const int q2 = wr;
+        const bool has2 = q2 < d.n2t;
+        uint4 lo2[kMaxK2], w3[2][3];
+        float v2[16];
+        uint32_t cnt2[8];
+        f32x16_t acc3 = {};
+#pragma unroll
+        for (int c = 0; c < kMaxK2; ++c)
+            lo2[c] = a.P2[(size_t)(((c < d.k2 ? c : 0) * d.n2t + (has2 ? q2 : 0)) * 3 + 2) * 64 + lane];
+#pragma unroll
+        for (int c = 0; c < kMaxK2; ++c)
+            if (!(has2 && c < d.k2)) lo2[c] = zero;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int c3 = 2 * w + j;
-            if (c3 < d.k3) {
-                const uint32_t word = mask2[col_in * kM2 + (c3 >> 1)];
-                const uint4 A = ones_bf16((word >> (16 * (c3 & 1) + 8 * (lane >> 5))) & 0xFFu);
-                acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
-                acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
-                acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
+            const int c3 = 2 * wr + j;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const uint4 x = a.P3[(size_t)((c3 < d.k3 ? c3 : 0) * 3 + p) * 64 + lane];
+                w3[j][p] = c3 < d.k3 ? x : zero;
             }
         }
+        float bias2 = a.b2[32 * (has2 ? q2 : 0) + col_in];
+        if (!has2) bias2 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v2[r] = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cnt2[j] = 0;
+        __syncthreads();
+        for (int i = 0; i <= a.T; ++i) {
+            if (i > 0) {
+                const int t = i - 1;
+                const uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
+                if (REC && a.o.raster_h1) {
+                    for (int k = tid; k < 32 * h1w; k += 256) {
+                        const int row = k / h1w, wd = k - row * h1w;
+                        if (s0 + row < a.B)
+                            a.o.raster_h1[((size_t)t * a.B + s0 + row) * h1w + wd] = m1[row * kM1 + wd];
+                    }
+                }
+                if (has2) {
+                    // h2: current from step t's h1 spikes.  Branch-free over
+                    // all 16 chunks: mask words past the h1 tiles read as 0,
+                    // so chunks past the layer add exact zeros (clamped
+                    // weight reads).
+                    uint32_t words[kMaxK2 / 2];
+#pragma unroll
+                    for (int j = 0; j < kMaxK2 / 2; ++j) {
+                        const uint32_t x = m1[col_in * kM1 + j];
+                        words[j] = j < d.n1t ? x : 0u;
+                    }
+                    f32x16_t acc2 = {};
+#pragma unroll
+                    for (int c = 0; c < kMaxK2; ++c) {
+                        const uint4 A = ones_bf16((words[c >> 1] >> (16 * (c & 1) + 8 * (lane >> 5))) & 0xFFu);
+                        const int cc = c < d.k2 ? c : 0;
+                        const uint4 *wb = w2s + (size_t)((cc * d.n2t + q2) * 2) * 64 + lane;
+                        acc2 = mfma<PREC_FP32>(A, wb[0], acc2);
+                        acc2 = mfma<PREC_FP32>(A, wb[64], acc2);
+                        acc2 = mfma<PREC_FP32>(A, lo2[c], acc2);
+                    }
+                    const int col2 = 32 * q2 + col_in;
+                    uint64_t mb[16];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float u = v2[r] + (acc2[r] + bias2);
+                        const bool s = u >= a.th2;
+                        v2[r] = s ? u - a.th2 : u;
+                        cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
+                        mb[r] = __builtin_amdgcn_ballot_w64(s);
+                        if (REC && a.o.v_h2) {
+                            const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
+                            if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
+                        }
+                    }
+                    if (lane == 0) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row0 = 8 * (r >> 2) + (r & 3);
+                            mask2[row0 * kM2 + q2] = (uint32_t)mb[r];
+                            mask2[(row0 + 4) * kM2 + q2] = (uint32_t)(mb[r] >> 32);
+                            if (REC && a.o.raster_h2) {
+                                if (s0 + row0 < a.B)
+                                    a.o.raster_h2[((size_t)t * a.B + s0 + row0) * h2w + q2] = (uint32_t)mb[r];
+                                if (s0 + row0 + 4 < a.B)
+                                    a.o.raster_h2[((size_t)t * a.B + s0 + row0 + 4) * h2w + q2] =
+                                        (uint32_t)(mb[r] >> 32);
+                            }
+                        }
+                    }
+                    // output layer: the wave reads back its own h2 spikes
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const uint32_t word2 = mask2[col_in * kM2 + q2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const uint4 A = ones_bf16((word2 >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
+                        acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
+                        acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
+                        acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (has2 && a.o.counts_h2 && 32 * q2 + col_in < d.h2) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (s < a.B)
+                    a.o.counts_h2[(size_t)s * d.h2 + 32 * q2 + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+            }
+        }
+        // the loop's last barrier has retired every use of the staged weights
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[(wr * 16 + r) * 64 + lane] = acc3[r];
     }
 
-    // spike counts
-#pragma unroll
-    for (int qi = 0; qi < 2; ++qi) {
-        const int col = 32 * (w + 4 * qi) + col_in;
-        if (!a.o.counts_h1 || !has1[qi] || col >= d.h1) continue;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (s < a.B) a.o.counts_h1[(size_t)s * d.h1 + col] = (cnt1[qi][r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-        }
-    }
-    if (a.o.counts_h2 && has2 && 32 * q2 + col_in < d.h2) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (s < a.B) a.o.counts_h2[(size_t)s * d.h2 + 32 * q2 + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-        }
-    }
-
-    // readout: the waves' partial sums, added in wave order, plus T * b3
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(lds_if);
+    // readout: the h2 waves' partial sums, added in wave order, plus T * b3
     float *fin = red + 4 * 16 * 64;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) red[(w * 16 + r) * 64 + lane] = acc3[r];
     __syncthreads();
-    for (int i = tid; i < 16 * 64; i += kNetThreads) {
-        const int r = i >> 6, ln = i & 63;
+    for (int k = tid; k < 16 * 64; k += kNetThreads) {
+        const int r = k >> 6, ln = k & 63;
         const float sum = ((red[r * 64 + ln] + red[(16 + r) * 64 + ln]) + red[(32 + r) * 64 + ln]) +
                           red[(48 + r) * 64 + ln];
         const int col = ln & 31, row = 8 * (r >> 2) + 4 * (ln >> 5) + (r & 3);
@@ -456,8 +552,10 @@ extern "C" snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream
     if ((e = hipMalloc(&n->wtmp, wmax * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = hipMalloc(&n->I1, (size_t)cfg->max_batch * 32 * d.n1t * sizeof(float))) != hipSuccess)
         return bail(e, "hipMalloc");
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_if_net), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)n->lds)) != hipSuccess)
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_if_net<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds)) != hipSuccess ||
+        (e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_if_net<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds)) != hipSuccess)
         return bail(e, "hipFuncSetAttribute");
     *out = n;
     return SNN_OK;
@@ -501,13 +599,19 @@ extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, u
     snn_ifnet_outputs o{};
     if (out) o = *out;
     const int tiles = (int)((batch + 31) / 32);
-    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch,
-                (net->d.n_in % 8 == 0 && (reinterpret_cast<uintptr_t>(images_dev) & 7) == 0) ? 1 : 0, net->d};
-    hipLaunchKernelGGL(k_if_input, dim3(tiles, net->d.n1t), dim3(256), 0, net->stream, ia);
+    const bool vec8 = net->d.n_in % 8 == 0 && (reinterpret_cast<uintptr_t>(images_dev) & 7) == 0;
+    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch, vec8 ? 1 : 0, net->d};
+    if (vec8)
+        hipLaunchKernelGGL(k_if_input<true>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
+    else
+        hipLaunchKernelGGL(k_if_input<false>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
     IF_TRY(hipGetLastError());
     IfNetArgs na{net->I1, net->P[1], net->P[2], net->b[1], net->b[2], (float)net->cfg.theta_h1,
                  (float)net->cfg.theta_h2, (int)batch, (int)T, net->d, o};
-    hipLaunchKernelGGL(k_if_net, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
+    if (o.raster_h1 || o.raster_h2 || o.v_h1 || o.v_h2)
+        hipLaunchKernelGGL(k_if_net<true>, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
+    else
+        hipLaunchKernelGGL(k_if_net<false>, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
     IF_TRY(hipGetLastError());
     return SNN_OK;
 }
