@@ -183,18 +183,19 @@ struct IfNetArgs {
     snn_ifnet_outputs o;
 };
 
-// LDS of k_if_net: the staged h2 weights (planes 0 and 1; reused for the
-// readout's partial sums at the end), then the h1 masks (two steps) and the
-// h2 mask.
+// LDS of k_if_net: the staged h2 weights' plane 0 (+ one spare slot; the
+// region is reused for the readout's partial sums at the end), the h2
+// operand fragments of two steps' h1 spikes, then the h1 and h2 spike words.
 __host__ __device__ inline size_t net_w2_region(const IfDims &d)
 {
-    const size_t w2 = (size_t)(d.k2 * d.n2t * 2 * 64 + 1) * sizeof(uint4);  // + a slot for clamped stores
+    const size_t w2 = (size_t)(d.k2 * d.n2t * 64 + 1) * sizeof(uint4);
     const size_t fin = (4 * 16 * 64 + 32 * 32) * sizeof(float);
     return w2 > fin ? w2 : fin;
 }
+constexpr size_t kAbufBytes = 2 * kMaxK2 * 64 * sizeof(uint4);
 __host__ __device__ inline size_t net_lds_bytes(const IfDims &d)
 {
-    return net_w2_region(d) + (2 * 32 * kM1 + 32 * kM2) * sizeof(uint32_t);
+    return net_w2_region(d) + kAbufBytes + (32 * kM1 + 32 * kM2) * sizeof(uint32_t);
 }
 
 // One 32-sample tile for all T steps, as a two-stage pipeline of 8 waves
@@ -217,28 +218,34 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     const int wr = w & 3;
     const bool h1wave = w >= 4;
     const int s0 = blockIdx.x * 32;
-    const int w2n = d.k2 * d.n2t * 2 * 64;  // uint4 of the staged h2 weights (planes 0, 1)
+    const int w2n = d.k2 * d.n2t * 64;  // uint4 of the staged h2 weights (plane 0)
     const size_t w2_region = net_w2_region(d);
     uint4 *w2s = lds_if;
-    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds_if) + w2_region);
-    uint32_t *mask2 = mask1 + 2 * 32 * kM1;
+    uint4 *abuf = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(lds_if) + w2_region);
+    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(abuf) + kAbufBytes);
+    uint32_t *mask2 = mask1 + 32 * kM1;
 
-    // stage the h2 weights, 16 loads in flight per thread (loads past the end
-    // re-read element i0 and store it to the spare slot w2s[w2n])
+    // stage plane 0 of the h2 weights, 16 loads in flight per thread (loads
+    // past the end re-read element i0 and store it to the spare slot w2s[w2n])
     for (int i0 = tid; i0 < w2n; i0 += 16 * kNetThreads) {
         uint4 buf[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int i = i0 + j * kNetThreads;
             const int ii = i < w2n ? i : i0;
-            const int g = ii >> 6, ln = ii & 63;
-            buf[j] = a.P2[(size_t)((g >> 1) * 3 + (g & 1)) * 64 + ln];
+            buf[j] = a.P2[(size_t)((ii >> 6) * 3) * 64 + (ii & 63)];
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int i = i0 + j * kNetThreads;
             w2s[i < w2n ? i : w2n] = buf[j];
         }
+    }
+    // operand fragments of the chunks no h1 tile writes (c >= 2 n1t) stay zero
+    const int nz = (kMaxK2 - 2 * d.n1t) * 64;
+    for (int k = tid; k < 2 * nz; k += kNetThreads) {
+        const int bf = k / nz, rest = k - bf * nz;
+        abuf[bf * kMaxK2 * 64 + 2 * d.n1t * 64 + rest] = make_uint4(0, 0, 0, 0);
     }
 
     const int col_in = lane & 31;
@@ -272,7 +279,8 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
         for (int i = 0; i <= a.T; ++i) {
             if (i < a.T) {
                 const int t = i;
-                uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
+                uint32_t *m1 = mask1;
+                uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
 #pragma unroll
                 for (int qi = 0; qi < 2; ++qi) {
                     if (!has1[qi]) continue;
@@ -300,6 +308,18 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                             m1[(row0 + 4) * kM1 + q1] = (uint32_t)(mb[r] >> 32);
                         }
                     }
+                    // read the tile's words back per sample (lane: sample
+                    // l % 32, units 8 (l / 32)..+7 of each chunk) and publish
+                    // the h2 operand fragments of chunks 2 q1 and 2 q1 + 1
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const uint32_t word = m1[col_in * kM1 + q1];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        ab[(2 * q1 + j) * 64 + lane] = ones_bf16((word >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
+                    if (REC && a.o.raster_h1 && lane < 32 && s0 + lane < a.B)
+                        a.o.raster_h1[((size_t)t * a.B + s0 + lane) * h1w + q1] = word;
                 }
             }
             __syncthreads();
@@ -320,16 +340,23 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     } else {
         const int q2 = wr;
         const bool has2 = q2 < d.n2t;
-        uint4 lo2[kMaxK2], w3[2][3];
+        uint4 mid2[kMaxK2], lo2[kMaxK2], w3[2][3];
         float v2[16];
         uint32_t cnt2[8];
         f32x16_t acc3 = {};
 #pragma unroll
-        for (int c = 0; c < kMaxK2; ++c)
-            lo2[c] = a.P2[(size_t)(((c < d.k2 ? c : 0) * d.n2t + (has2 ? q2 : 0)) * 3 + 2) * 64 + lane];
+        for (int c = 0; c < kMaxK2; ++c) {
+            const uint4 *pw = a.P2 + (size_t)(((c < d.k2 ? c : 0) * d.n2t + (has2 ? q2 : 0)) * 3) * 64 + lane;
+            mid2[c] = pw[64];
+            lo2[c] = pw[128];
+        }
 #pragma unroll
-        for (int c = 0; c < kMaxK2; ++c)
-            if (!(has2 && c < d.k2)) lo2[c] = zero;
+        for (int c = 0; c < kMaxK2; ++c) {
+            if (!(has2 && c < d.k2)) {
+                mid2[c] = zero;
+                lo2[c] = zero;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int c3 = 2 * wr + j;
@@ -349,33 +376,19 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
         for (int i = 0; i <= a.T; ++i) {
             if (i > 0) {
                 const int t = i - 1;
-                const uint32_t *m1 = mask1 + (t & 1) * 32 * kM1;
-                if (REC && a.o.raster_h1) {
-                    for (int k = tid; k < 32 * h1w; k += 256) {
-                        const int row = k / h1w, wd = k - row * h1w;
-                        if (s0 + row < a.B)
-                            a.o.raster_h1[((size_t)t * a.B + s0 + row) * h1w + wd] = m1[row * kM1 + wd];
-                    }
-                }
+                const uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
                 if (has2) {
                     // h2: current from step t's h1 spikes.  Branch-free over
-                    // all 16 chunks: mask words past the h1 tiles read as 0,
-                    // so chunks past the layer add exact zeros (clamped
-                    // weight reads).
-                    uint32_t words[kMaxK2 / 2];
-#pragma unroll
-                    for (int j = 0; j < kMaxK2 / 2; ++j) {
-                        const uint32_t x = m1[col_in * kM1 + j];
-                        words[j] = j < d.n1t ? x : 0u;
-                    }
+                    // all 16 chunks: fragments of chunks past the h1 tiles
+                    // are zero, so they add exact zeros (clamped weight reads).
                     f32x16_t acc2 = {};
 #pragma unroll
                     for (int c = 0; c < kMaxK2; ++c) {
-                        const uint4 A = ones_bf16((words[c >> 1] >> (16 * (c & 1) + 8 * (lane >> 5))) & 0xFFu);
+                        const uint4 A = ab[c * 64 + lane];
                         const int cc = c < d.k2 ? c : 0;
-                        const uint4 *wb = w2s + (size_t)((cc * d.n2t + q2) * 2) * 64 + lane;
-                        acc2 = mfma<PREC_FP32>(A, wb[0], acc2);
-                        acc2 = mfma<PREC_FP32>(A, wb[64], acc2);
+                        const uint4 hi = w2s[(size_t)(cc * d.n2t + q2) * 64 + lane];
+                        acc2 = mfma<PREC_FP32>(A, hi, acc2);
+                        acc2 = mfma<PREC_FP32>(A, mid2[c], acc2);
                         acc2 = mfma<PREC_FP32>(A, lo2[c], acc2);
                     }
                     const int col2 = 32 * q2 + col_in;
