@@ -34,8 +34,10 @@ namespace {
 constexpr int kMaxH1 = 256, kMaxH2 = 128, kMaxOut = 32;
 constexpr int kMaxK2 = kMaxH1 / 16;  // 16-deep chunks of the h1 -> h2 contraction
 constexpr int kNetThreads = 512;     // 8 waves: h2 tile w (w < 4), h1 tiles w - 4, w (w >= 4)
-constexpr int kM1 = 9;               // LDS words per sample row of the h1 mask (8 + pad)
-constexpr int kM2 = 5;               // the same for h2 (4 + pad)
+// Spike words of a 32-neuron tile in LDS: the ballot of C row r holds the
+// words of samples 8 (r / 4) + r % 4 (low half) and that + 4 (high half) and
+// is stored whole at word 2r, so sample S's word is at ballot_slot(S).
+__device__ __forceinline__ int ballot_slot(int S) { return 8 * (S >> 3) + 2 * (S & 3) + ((S >> 2) & 1); }
 
 struct IfDims {
     int n_in, h1, h2, n_out;
@@ -92,55 +94,59 @@ struct IfInArgs {
 // First-layer current of one (32-sample, 32-neuron) tile.  The 16 waves
 // take every sixteenth 16-pixel chunk, four chunks' operands loaded before
 // their products; the partial sums are added in wave order.
-constexpr int kInWaves = 16;
+constexpr int kInWaves = 16;  // also the number of row blocks of a C tile
 
-// 8 pixels (bytes) of one sample as bfloat16 operand elements.
+// 8 pixels (bytes) of one sample, raw: one 8-byte load when rows are 8-byte
+// aligned (n_in % 8 == 0; k0 < n_in then implies the bytes are in the row).
 template <bool VEC8>
-__device__ __forceinline__ uint4 pixels_bf16(const uint8_t *im, int k0, int n_in)
+__device__ __forceinline__ uint2 pixels_raw(const uint8_t *im, int k0, int n_in)
 {
-    uint32_t px[8];
-    if constexpr (VEC8) {  // n_in % 8 == 0, k0 < n_in: the 8 bytes are in the row
-        const uint2 raw = *reinterpret_cast<const uint2 *>(im + k0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            px[e] = (raw.x >> (8 * e)) & 0xFFu;
-            px[4 + e] = (raw.y >> (8 * e)) & 0xFFu;
-        }
+    if constexpr (VEC8) {
+        return *reinterpret_cast<const uint2 *>(im + k0);
     } else {
+        uint32_t px[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) px[e] = k0 + e < n_in ? im[k0 + e] : 0u;
+        return make_uint2(px[0] | (px[1] << 8) | (px[2] << 16) | (px[3] << 24),
+                          px[4] | (px[5] << 8) | (px[6] << 16) | (px[7] << 24));
     }
+}
+
+// The 8 pixels as bfloat16 operand elements (integers up to 255 are exact).
+__device__ __forceinline__ uint4 pixels_bf16(uint2 raw)
+{
     uint4 A;
-    A.x = px_bf16(px[0]) | (px_bf16(px[1]) << 16);
-    A.y = px_bf16(px[2]) | (px_bf16(px[3]) << 16);
-    A.z = px_bf16(px[4]) | (px_bf16(px[5]) << 16);
-    A.w = px_bf16(px[6]) | (px_bf16(px[7]) << 16);
+    A.x = px_bf16(raw.x & 0xFFu) | (px_bf16((raw.x >> 8) & 0xFFu) << 16);
+    A.y = px_bf16((raw.x >> 16) & 0xFFu) | (px_bf16(raw.x >> 24) << 16);
+    A.z = px_bf16(raw.y & 0xFFu) | (px_bf16((raw.y >> 8) & 0xFFu) << 16);
+    A.w = px_bf16((raw.y >> 16) & 0xFFu) | (px_bf16(raw.y >> 24) << 16);
     return A;
 }
 
-// Loads are unconditional (addresses clamped into range) so that a wave's
-// four chunks are in flight together; the operand of a chunk past the end
-// or of a sample past the batch is zeroed instead.
+// Loads are unconditional (addresses clamped into range) and issued for all
+// four chunks before any product, so that they are in flight together; the
+// operand of a chunk past the end or of a sample past the batch is zeroed
+// instead.  The 16 partial sums are added in wave order, wave r adding row
+// block r of the tile.
 template <bool VEC8>
 __global__ __launch_bounds__(64 * kInWaves) void k_if_input(IfInArgs a)
 {
-    __shared__ float red[kInWaves - 1][16][64];
+    __shared__ float red[kInWaves][16][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int s0 = blockIdx.x * 32, q = blockIdx.y;
     const int srow = s0 + (lane & 31);
     const bool rv = srow < a.B;
     const uint8_t *im = a.img + (size_t)(rv ? srow : s0) * a.d.n_in;
     const int k1 = a.d.k1, n1t = a.d.n1t;
-    const uint4 zero = make_uint4(0, 0, 0, 0);
     f32x16_t acc = {};
     for (int base = w; base < k1; base += 4 * kInWaves) {
-        uint4 A[4], Bh[4], Bm[4], Bl[4];
+        uint2 raw[4];
+        uint4 Bh[4], Bm[4], Bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int c = base + j * kInWaves;
             const int cc = c < k1 ? c : base;
-            A[j] = pixels_bf16<VEC8>(im, 16 * cc + 8 * (lane >> 5), a.d.n_in);
-            if (!(rv && c < k1)) A[j] = zero;
+            raw[j] = pixels_raw<VEC8>(im, 16 * cc + 8 * (lane >> 5), a.d.n_in);
             const uint4 *pb = a.P1 + (size_t)((cc * n1t + q) * 3) * 64 + lane;
             Bh[j] = pb[0];
             Bm[j] = pb[64];
@@ -148,29 +154,24 @@ __global__ __launch_bounds__(64 * kInWaves) void k_if_input(IfInArgs a)
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            acc = mfma<PREC_FP32>(A[j], Bh[j], acc);
-            acc = mfma<PREC_FP32>(A[j], Bm[j], acc);
-            acc = mfma<PREC_FP32>(A[j], Bl[j], acc);
+            uint4 A = pixels_bf16(raw[j]);
+            if (!(rv && base + j * kInWaves < k1)) A = make_uint4(0, 0, 0, 0);
+            acc = mfma<PREC_FP32>(A, Bh[j], acc);
+            acc = mfma<PREC_FP32>(A, Bm[j], acc);
+            acc = mfma<PREC_FP32>(A, Bl[j], acc);
         }
     }
-    if (w > 0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[w - 1][r][lane] = acc[r];
-    }
+    for (int r = 0; r < 16; ++r) red[w][r][lane] = acc[r];
     __syncthreads();
-    if (w == 0) {
-        const int n1p = 32 * n1t;
-        const int col = 32 * q + (lane & 31);
-        const float bias = a.b1[col];
+    const int r = w;  // kInWaves == 16 row blocks
+    float sum = red[0][r][lane];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            float sum = acc[r];
-#pragma unroll
-            for (int v = 0; v < kInWaves - 1; ++v) sum += red[v][r][lane];
-            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (s0 + row < a.B) a.I1[(size_t)(s0 + row) * n1p + col] = sum * (1.f / 255.f) + bias;
-        }
-    }
+    for (int v = 1; v < kInWaves; ++v) sum += red[v][r][lane];
+    const int n1p = 32 * n1t;
+    const int col = 32 * q + (lane & 31);
+    const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (s0 + row < a.B) a.I1[(size_t)(s0 + row) * n1p + col] = sum * (1.f / 255.f) + a.b1[col];
 }
 
 struct IfNetArgs {
@@ -195,7 +196,7 @@ __host__ __device__ inline size_t net_w2_region(const IfDims &d)
 constexpr size_t kAbufBytes = 2 * kMaxK2 * 64 * sizeof(uint4);
 __host__ __device__ inline size_t net_lds_bytes(const IfDims &d)
 {
-    return net_w2_region(d) + kAbufBytes + (32 * kM1 + 32 * kM2) * sizeof(uint32_t);
+    return net_w2_region(d) + kAbufBytes + (8 + 4) * 32 * sizeof(uint32_t);
 }
 
 // One 32-sample tile for all T steps, as a two-stage pipeline of 8 waves
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     uint4 *w2s = lds_if;
     uint4 *abuf = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(lds_if) + w2_region);
     uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(abuf) + kAbufBytes);
-    uint32_t *mask2 = mask1 + 32 * kM1;
+    uint32_t *mask2 = mask1 + 8 * 32;  // 8 h1 tiles, then 4 h2 tiles, 32 words each
 
     // stage plane 0 of the h2 weights, 16 loads in flight per thread (loads
     // past the end re-read element i0 and store it to the spare slot w2s[w2n])
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     }
 
     const int col_in = lane & 31;
+    const int slot = ballot_slot(col_in);
     const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
     const uint4 zero = make_uint4(0, 0, 0, 0);
     float *red = reinterpret_cast<float *>(lds_if);  // readout partial sums (after the loop)
@@ -300,13 +302,10 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                             if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[qi][r];
                         }
                     }
+                    uint64_t *mq = reinterpret_cast<uint64_t *>(m1 + 32 * q1);
                     if (lane == 0) {
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row0 = 8 * (r >> 2) + (r & 3);
-                            m1[row0 * kM1 + q1] = (uint32_t)mb[r];
-                            m1[(row0 + 4) * kM1 + q1] = (uint32_t)(mb[r] >> 32);
-                        }
+                        for (int r = 0; r < 16; ++r) mq[r] = mb[r];
                     }
                     // read the tile's words back per sample (lane: sample
                     // l % 32, units 8 (l / 32)..+7 of each chunk) and publish
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const uint32_t word = m1[col_in * kM1 + q1];
+                    const uint32_t word = m1[32 * q1 + slot];
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         ab[(2 * q1 + j) * 64 + lane] = ones_bf16((word >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
@@ -405,26 +404,18 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                             if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
                         }
                     }
+                    uint64_t *mq = reinterpret_cast<uint64_t *>(mask2 + 32 * q2);
                     if (lane == 0) {
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row0 = 8 * (r >> 2) + (r & 3);
-                            mask2[row0 * kM2 + q2] = (uint32_t)mb[r];
-                            mask2[(row0 + 4) * kM2 + q2] = (uint32_t)(mb[r] >> 32);
-                            if (REC && a.o.raster_h2) {
-                                if (s0 + row0 < a.B)
-                                    a.o.raster_h2[((size_t)t * a.B + s0 + row0) * h2w + q2] = (uint32_t)mb[r];
-                                if (s0 + row0 + 4 < a.B)
-                                    a.o.raster_h2[((size_t)t * a.B + s0 + row0 + 4) * h2w + q2] =
-                                        (uint32_t)(mb[r] >> 32);
-                            }
-                        }
+                        for (int r = 0; r < 16; ++r) mq[r] = mb[r];
                     }
                     // output layer: the wave reads back its own h2 spikes
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const uint32_t word2 = mask2[col_in * kM2 + q2];
+                    const uint32_t word2 = mask2[32 * q2 + slot];
+                    if (REC && a.o.raster_h2 && lane < 32 && s0 + lane < a.B)
+                        a.o.raster_h2[((size_t)t * a.B + s0 + lane) * h2w + q2] = word2;
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
                         const uint4 A = ones_bf16((word2 >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
