@@ -404,6 +404,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-conversion", action="store_true", help="skip the converted IF network run")
+    ap.add_argument("--conversion-only", action="store_true",
+                    help="print only the converted IF network's measurement")
     ap.add_argument("--sweep", choices=["scale", "dc400"], default=None,
                     help="print a throughput sweep instead of the benchmark line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -416,6 +418,9 @@ def main():
 
     if args.sweep:
         print(json.dumps({"sweep": sweep(args.sweep, args.steps)}), flush=True)
+        return
+    if args.conversion_only:
+        print(json.dumps({"conversion": conversion_run(oracle=not args.no_cpu)}), flush=True)
         return
 
     import torch
