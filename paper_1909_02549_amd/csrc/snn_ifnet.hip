@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kMaxH1 = 256, kMaxH2 = 128, kMaxOut = 32;
 constexpr int kMaxK2 = kMaxH1 / 16;  // 16-deep chunks of the h1 -> h2 contraction
-constexpr int kNetThreads = 512;     // 8 waves: h2 tile w (w < 4), h1 tiles w - 4, w (w >= 4)
+constexpr int kNetThreads = 768;     // 12 waves: 4 chunk waves (h2), 8 h1 waves (one h1 tile each)
 // Spike words of a 32-neuron tile in LDS: the ballot of C row r holds the
 // words of samples 8 (r / 4) + r % 4 (low half) and that + 4 (high half) and
 // is stored whole at word 2r, so sample S's word is at ballot_slot(S).
@@ -178,35 +178,32 @@ struct IfNetArgs {
     const float *I1;  // B x n1t * 32
     const uint4 *P2, *P3;
     const float *b2, *b3;  // padded to 32-wide tiles
+    float *rpart;          // n2t x B x 32 partial readouts (one per h2 tile)
     float th1, th2;
     int B, T;
     IfDims d;
     snn_ifnet_outputs o;
 };
 
-// LDS of k_if_net: the staged h2 weights' plane 0 (+ one spare slot; the
-// region is reused for the readout's partial sums at the end), the h2
-// operand fragments of two steps' h1 spikes, then the h1 and h2 spike words.
-__host__ __device__ inline size_t net_w2_region(const IfDims &d)
-{
-    const size_t w2 = (size_t)(d.k2 * d.n2t * 64 + 1) * sizeof(uint4);
-    const size_t fin = (4 * 16 * 64 + 32 * 32) * sizeof(float);
-    return w2 > fin ? w2 : fin;
-}
+// LDS of k_if_net: the h2 operand fragments of two steps' h1 spikes, the h2
+// partial sums of two steps (4 chunk groups), the h1 spike words (8 tiles)
+// and the h2 spike words (one tile).
 constexpr size_t kAbufBytes = 2 * kMaxK2 * 64 * sizeof(uint4);
-__host__ __device__ inline size_t net_lds_bytes(const IfDims &d)
-{
-    return net_w2_region(d) + kAbufBytes + (8 + 4) * 32 * sizeof(uint32_t);
-}
+constexpr size_t kPartBytes = 2 * 4 * 16 * 64 * sizeof(float);
+constexpr size_t kNetLds = kAbufBytes + kPartBytes + (8 + 1) * 32 * sizeof(uint32_t);
 
-// One 32-sample tile for all T steps, as a two-stage pipeline of 8 waves
-// (two per SIMD, so one wave's vector work overlaps the other's matrix-core
-// work).  In iteration i:
-//   waves 4..7 ("h1 waves") integrate step i of h1 tiles (w - 4) and
-//     (w - 4) + 4 and publish their spikes as bit masks in buffer i % 2;
-//   waves 0..3 ("h2 waves") run step i - 1 of h2 tile w from buffer
-//     (i - 1) % 2, then the output chunks 2w and 2w + 1 (the h2 neurons of
-//     their own tile, read back within the wave);
+// One workgroup per (32-sample tile, h2 tile y) runs all T steps as a
+// three-stage pipeline of 12 waves; in iteration i:
+//   waves 4..11 ("h1 waves") integrate step i of h1 tile w - 4 (every h2
+//     tile's workgroup integrates all of h1) and publish the h2 operand
+//     fragments of its two chunks in buffer i % 2;
+//   waves 0..3 ("chunk waves") multiply step i - 1's fragments of chunks
+//     4p..4p + 3 (p = wave) by h2 tile y's weights (three planes, held in
+//     registers) and store the partial sums in buffer (i - 1) % 2;
+//   wave 0 first finishes step i - 2: adds the four partial sums in wave
+//     order plus the bias, integrates h2 tile y, publishes its spike word
+//     and multiplies it by the output weights of chunks 2y and 2y + 1,
+//     accumulating this tile's share of the readout over the run;
 // one workgroup barrier ends the iteration.  C layout of a tile: lane l
 // holds neuron 32q + l % 32 of samples 8 (r / 4) + 4 (l / 32) + r % 4,
 // r = 0..15.  REC: also record voltages and rasters (the parity outputs).
@@ -218,253 +215,237 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w & 3;
     const bool h1wave = w >= 4;
-    const int s0 = blockIdx.x * 32;
-    const int w2n = d.k2 * d.n2t * 64;  // uint4 of the staged h2 weights (plane 0)
-    const size_t w2_region = net_w2_region(d);
-    uint4 *w2s = lds_if;
-    uint4 *abuf = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(lds_if) + w2_region);
-    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(abuf) + kAbufBytes);
-    uint32_t *mask2 = mask1 + 8 * 32;  // 8 h1 tiles, then 4 h2 tiles, 32 words each
+    const int q1 = w - 4;  // h1 wave's tile
+    const int s0 = blockIdx.x * 32, y = blockIdx.y;
+    const bool lead = y == 0;  // the workgroup that records h1 outputs
+    uint4 *abuf = lds_if;
+    float *part = reinterpret_cast<float *>(reinterpret_cast<char *>(lds_if) + kAbufBytes);
+    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(part) + kPartBytes);
+    uint32_t *mask2 = mask1 + 8 * 32;
 
-    // stage plane 0 of the h2 weights, 16 loads in flight per thread (loads
-    // past the end re-read element i0 and store it to the spare slot w2s[w2n])
-    for (int i0 = tid; i0 < w2n; i0 += 16 * kNetThreads) {
-        uint4 buf[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int i = i0 + j * kNetThreads;
-            const int ii = i < w2n ? i : i0;
-            buf[j] = a.P2[(size_t)((ii >> 6) * 3) * 64 + (ii & 63)];
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int i = i0 + j * kNetThreads;
-            w2s[i < w2n ? i : w2n] = buf[j];
-        }
-    }
     // operand fragments of the chunks no h1 tile writes (c >= 2 n1t) stay zero
     const int nz = (kMaxK2 - 2 * d.n1t) * 64;
     for (int k = tid; k < 2 * nz; k += kNetThreads) {
         const int bf = k / nz, rest = k - bf * nz;
         abuf[bf * kMaxK2 * 64 + 2 * d.n1t * 64 + rest] = make_uint4(0, 0, 0, 0);
     }
-
     const int col_in = lane & 31;
     const int slot = ballot_slot(col_in);
     const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
     const uint4 zero = make_uint4(0, 0, 0, 0);
-    float *red = reinterpret_cast<float *>(lds_if);  // readout partial sums (after the loop)
 
-    // Each role runs its own loop with one barrier per iteration (T + 1 in
+    // Each role runs its own loop with one barrier per iteration (T + 2 in
     // both), so that only its own state is live in registers.
     if (h1wave) {
         const int n1p = 32 * d.n1t;
-        float I1[2][16], v1[2][16];
-        uint32_t cnt1[2][8];
-        bool has1[2];
+        const bool has1 = q1 < d.n1t;
+        const int col = 32 * q1 + col_in;
+        float I1[16], v1[16];
+        uint32_t cnt1[8];
 #pragma unroll
-        for (int qi = 0; qi < 2; ++qi) {
-            const int q1 = wr + 4 * qi;
-            has1[qi] = q1 < d.n1t;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const bool ok = has1[qi] && s < a.B;
-                const float x = a.I1[(size_t)(ok ? s : s0) * n1p + 32 * (has1[qi] ? q1 : 0) + col_in];
-                I1[qi][r] = ok ? x : 0.f;
-                v1[qi][r] = 0.f;
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) cnt1[qi][j] = 0;
+        for (int r = 0; r < 16; ++r) {
+            const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const bool ok = has1 && s < a.B;
+            const float x = a.I1[(size_t)(ok ? s : s0) * n1p + (has1 ? col : col_in)];
+            I1[r] = ok ? x : 0.f;
+            v1[r] = 0.f;
         }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cnt1[j] = 0;
         __syncthreads();
-        for (int i = 0; i <= a.T; ++i) {
-            if (i < a.T) {
+        for (int i = 0; i <= a.T + 1; ++i) {
+            if (i < a.T && has1) {
                 const int t = i;
-                uint32_t *m1 = mask1;
                 uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
+                // the ballot of row r holds samples row0 (low half) and
+                // row0 + 4 (high half), stored whole at word 2r
+                uint64_t mb[16];
 #pragma unroll
-                for (int qi = 0; qi < 2; ++qi) {
-                    if (!has1[qi]) continue;
-                    const int q1 = wr + 4 * qi, col = 32 * q1 + col_in;
-                    // the ballot of row r holds samples row0 (low half) and
-                    // row0 + 4 (high half); one lane stores the 32 words
-                    uint64_t mb[16];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const float u = v1[qi][r] + I1[qi][r];
-                        const bool s = u >= a.th1;
-                        v1[qi][r] = s ? u - a.th1 : u;
-                        cnt1[qi][r >> 1] += (uint32_t)s << (16 * (r & 1));
-                        mb[r] = __builtin_amdgcn_ballot_w64(s);
-                        if (REC && a.o.v_h1) {
-                            const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
-                            if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[qi][r];
-                        }
+                for (int r = 0; r < 16; ++r) {
+                    const float u = v1[r] + I1[r];
+                    const bool s = u >= a.th1;
+                    v1[r] = s ? u - a.th1 : u;
+                    cnt1[r >> 1] += (uint32_t)s << (16 * (r & 1));
+                    mb[r] = __builtin_amdgcn_ballot_w64(s);
+                    if (REC && lead && a.o.v_h1) {
+                        const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
+                        if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[r];
                     }
-                    uint64_t *mq = reinterpret_cast<uint64_t *>(m1 + 32 * q1);
-                    if (lane == 0) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) mq[r] = mb[r];
-                    }
-                    // read the tile's words back per sample (lane: sample
-                    // l % 32, units 8 (l / 32)..+7 of each chunk) and publish
-                    // the h2 operand fragments of chunks 2 q1 and 2 q1 + 1
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const uint32_t word = m1[32 * q1 + slot];
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        ab[(2 * q1 + j) * 64 + lane] = ones_bf16((word >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
-                    if (REC && a.o.raster_h1 && lane < 32 && s0 + lane < a.B)
-                        a.o.raster_h1[((size_t)t * a.B + s0 + lane) * h1w + q1] = word;
                 }
+                uint64_t *mq = reinterpret_cast<uint64_t *>(mask1 + 32 * q1);
+                if (lane == 0) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mq[r] = mb[r];
+                }
+                // read the tile's words back per sample (lane: sample l % 32,
+                // units 8 (l / 32)..+7 of each chunk) and publish the h2
+                // operand fragments of chunks 2 q1 and 2 q1 + 1
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint32_t word = mask1[32 * q1 + slot];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    ab[(2 * q1 + j) * 64 + lane] = ones_bf16((word >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
+                if (REC && lead && a.o.raster_h1 && lane < 32 && s0 + lane < a.B)
+                    a.o.raster_h1[((size_t)t * a.B + s0 + lane) * h1w + q1] = word;
             }
             __syncthreads();
         }
-        if (a.o.counts_h1) {
+        if (lead && a.o.counts_h1 && has1 && col < d.h1) {
 #pragma unroll
-            for (int qi = 0; qi < 2; ++qi) {
-                const int col = 32 * (wr + 4 * qi) + col_in;
-                if (!has1[qi] || col >= d.h1) continue;
+            for (int r = 0; r < 16; ++r) {
+                const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (s < a.B) a.o.counts_h1[(size_t)s * d.h1 + col] = (cnt1[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+            }
+        }
+    } else {
+        // chunk wave p = wr: h2 tile y's weights of chunks 4p..4p + 3
+        const int p = wr;
+        uint4 wp[4][3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * p + j;
+            const uint4 *pw = a.P2 + (size_t)(((c < d.k2 ? c : 0) * d.n2t + y) * 3) * 64 + lane;
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                const uint4 x = pw[64 * pl];
+                wp[j][pl] = c < d.k2 ? x : zero;
+            }
+        }
+        // wave 0 also finishes the steps: output weights of chunks 2y, 2y + 1
+        uint4 w3[2][3];
+        float v2[16], bias2 = 0.f;
+        uint32_t cnt2[8];
+        f32x16_t acc3 = {};
+        if (p == 0) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c3 = 2 * y + j;
+#pragma unroll
+                for (int pl = 0; pl < 3; ++pl) {
+                    const uint4 x = a.P3[(size_t)((c3 < d.k3 ? c3 : 0) * 3 + pl) * 64 + lane];
+                    w3[j][pl] = c3 < d.k3 ? x : zero;
+                }
+            }
+            bias2 = a.b2[32 * y + col_in];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v2[r] = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cnt2[j] = 0;
+        }
+        __syncthreads();
+        for (int i = 0; i <= a.T + 1; ++i) {
+            if (p == 0 && i >= 2) {
+                // finish step t = i - 2 of h2 tile y
+                const int t = i - 2;
+                const float *pt = part + (t & 1) * 4 * 16 * 64;
+                const int col2 = 32 * y + col_in;
+                uint64_t mb[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float sum = ((pt[r * 64 + lane] + pt[(16 + r) * 64 + lane]) + pt[(32 + r) * 64 + lane]) +
+                                      pt[(48 + r) * 64 + lane];
+                    const float u = v2[r] + (sum + bias2);
+                    const bool s = u >= a.th2;
+                    v2[r] = s ? u - a.th2 : u;
+                    cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
+                    mb[r] = __builtin_amdgcn_ballot_w64(s);
+                    if (REC && a.o.v_h2) {
+                        const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
+                        if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
+                    }
+                }
+                uint64_t *mq = reinterpret_cast<uint64_t *>(mask2);
+                if (lane == 0) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mq[r] = mb[r];
+                }
+                // output layer: the wave reads back its own h2 spikes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint32_t word2 = mask2[slot];
+                if (REC && a.o.raster_h2 && lane < 32 && s0 + lane < a.B)
+                    a.o.raster_h2[((size_t)t * a.B + s0 + lane) * h2w + y] = word2;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint4 A = ones_bf16((word2 >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
+                    acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
+                    acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
+                    acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
+                }
+            }
+            if (i >= 1 && i <= a.T) {
+                // partial h2 current of step t = i - 1 over chunks 4p..4p + 3
+                const int t = i - 1;
+                const uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
+                f32x16_t acc = {};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint4 A = ab[(4 * p + j) * 64 + lane];
+                    acc = mfma<PREC_FP32>(A, wp[j][0], acc);
+                    acc = mfma<PREC_FP32>(A, wp[j][1], acc);
+                    acc = mfma<PREC_FP32>(A, wp[j][2], acc);
+                }
+                float *pt = part + (t & 1) * 4 * 16 * 64 + p * 16 * 64;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) pt[r * 64 + lane] = acc[r];
+            }
+            __syncthreads();
+        }
+        if (p == 0) {
+            if (a.o.counts_h2 && 32 * y + col_in < d.h2) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     if (s < a.B)
-                        a.o.counts_h1[(size_t)s * d.h1 + col] = (cnt1[qi][r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+                        a.o.counts_h2[(size_t)s * d.h2 + 32 * y + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
                 }
             }
-        }
-    } else {
-        const int q2 = wr;
-        const bool has2 = q2 < d.n2t;
-        uint4 mid2[kMaxK2], lo2[kMaxK2], w3[2][3];
-        float v2[16];
-        uint32_t cnt2[8];
-        f32x16_t acc3 = {};
-#pragma unroll
-        for (int c = 0; c < kMaxK2; ++c) {
-            const uint4 *pw = a.P2 + (size_t)(((c < d.k2 ? c : 0) * d.n2t + (has2 ? q2 : 0)) * 3) * 64 + lane;
-            mid2[c] = pw[64];
-            lo2[c] = pw[128];
-        }
-#pragma unroll
-        for (int c = 0; c < kMaxK2; ++c) {
-            if (!(has2 && c < d.k2)) {
-                mid2[c] = zero;
-                lo2[c] = zero;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int c3 = 2 * wr + j;
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                const uint4 x = a.P3[(size_t)((c3 < d.k3 ? c3 : 0) * 3 + p) * 64 + lane];
-                w3[j][p] = c3 < d.k3 ? x : zero;
-            }
-        }
-        float bias2 = a.b2[32 * (has2 ? q2 : 0) + col_in];
-        if (!has2) bias2 = 0.f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v2[r] = 0.f;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) cnt2[j] = 0;
-        __syncthreads();
-        for (int i = 0; i <= a.T; ++i) {
-            if (i > 0) {
-                const int t = i - 1;
-                const uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
-                if (has2) {
-                    // h2: current from step t's h1 spikes.  Branch-free over
-                    // all 16 chunks: fragments of chunks past the h1 tiles
-                    // are zero, so they add exact zeros (clamped weight reads).
-                    f32x16_t acc2 = {};
-#pragma unroll
-                    for (int c = 0; c < kMaxK2; ++c) {
-                        const uint4 A = ab[c * 64 + lane];
-                        const int cc = c < d.k2 ? c : 0;
-                        const uint4 hi = w2s[(size_t)(cc * d.n2t + q2) * 64 + lane];
-                        acc2 = mfma<PREC_FP32>(A, hi, acc2);
-                        acc2 = mfma<PREC_FP32>(A, mid2[c], acc2);
-                        acc2 = mfma<PREC_FP32>(A, lo2[c], acc2);
-                    }
-                    const int col2 = 32 * q2 + col_in;
-                    uint64_t mb[16];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const float u = v2[r] + (acc2[r] + bias2);
-                        const bool s = u >= a.th2;
-                        v2[r] = s ? u - a.th2 : u;
-                        cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
-                        mb[r] = __builtin_amdgcn_ballot_w64(s);
-                        if (REC && a.o.v_h2) {
-                            const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
-                            if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
-                        }
-                    }
-                    uint64_t *mq = reinterpret_cast<uint64_t *>(mask2 + 32 * q2);
-                    if (lane == 0) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) mq[r] = mb[r];
-                    }
-                    // output layer: the wave reads back its own h2 spikes
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const uint32_t word2 = mask2[32 * q2 + slot];
-                    if (REC && a.o.raster_h2 && lane < 32 && s0 + lane < a.B)
-                        a.o.raster_h2[((size_t)t * a.B + s0 + lane) * h2w + q2] = word2;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const uint4 A = ones_bf16((word2 >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
-                        acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
-                        acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
-                        acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (has2 && a.o.counts_h2 && 32 * q2 + col_in < d.h2) {
+            // this tile's share of the readout
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (s < a.B)
-                    a.o.counts_h2[(size_t)s * d.h2 + 32 * q2 + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+                if (s < a.B) a.rpart[((size_t)y * a.B + s) * 32 + col_in] = acc3[r];
             }
         }
-        // the loop's last barrier has retired every use of the staged weights
-#pragma unroll
-        for (int r = 0; r < 16; ++r) red[(wr * 16 + r) * 64 + lane] = acc3[r];
     }
+}
 
-    // readout: the h2 waves' partial sums, added in wave order, plus T * b3
-    float *fin = red + 4 * 16 * 64;
-    __syncthreads();
-    for (int k = tid; k < 16 * 64; k += kNetThreads) {
-        const int r = k >> 6, ln = k & 63;
-        const float sum = ((red[r * 64 + ln] + red[(16 + r) * 64 + ln]) + red[(32 + r) * 64 + ln]) +
-                          red[(48 + r) * 64 + ln];
-        const int col = ln & 31, row = 8 * (r >> 2) + 4 * (ln >> 5) + (r & 3);
-        const float val = sum + (float)a.T * a.b3[col];
-        fin[row * 32 + col] = val;
-        if (a.o.out_sum && col < d.n_out && s0 + row < a.B) a.o.out_sum[(size_t)(s0 + row) * d.n_out + col] = val;
-    }
-    __syncthreads();
-    if (a.o.pred && tid < 32 && s0 + tid < a.B) {
-        int best = 0;
-        float bv = fin[tid * 32];
-        for (int o = 1; o < d.n_out; ++o) {
-            const float x = fin[tid * 32 + o];
-            if (x > bv) {
-                bv = x;
-                best = o;
-            }
+// Readout: the h2 tiles' shares added in tile order, plus T * b3, and the
+// argmax (first maximum on ties).  32 lanes per sample, lane o = output o.
+__global__ __launch_bounds__(256) void k_if_readout(const float *__restrict__ rpart, const float *__restrict__ b3,
+                                                     int B, int T, int n2t, int n_out, float *__restrict__ out_sum,
+                                                     int32_t *__restrict__ pred)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = g >> 5, o = g & 31;
+    const bool ok = s < B && o < n_out;
+    const int sc = s < B ? s : 0;
+    float part[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) part[y] = rpart[((size_t)(y < n2t ? y : 0) * B + sc) * 32 + o];
+    float sum = part[0];
+#pragma unroll
+    for (int y = 1; y < 4; ++y)
+        if (y < n2t) sum += part[y];
+    const float val = sum + (float)T * b3[o];
+    if (ok && out_sum) out_sum[(size_t)s * n_out + o] = val;
+    // argmax over the 32 lanes of the sample: larger value, or equal value
+    // and smaller index
+    float bv = ok ? val : -INFINITY;
+    int bi = o;
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) {
+        const float ov = __shfl_xor(bv, m, 32);
+        const int oi = __shfl_xor(bi, m, 32);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
         }
-        a.o.pred[s0 + tid] = best;
     }
+    if (pred && o == 0 && s < B) pred[s] = bi;
 }
 
 }  // namespace
@@ -477,6 +458,7 @@ struct snn_ifnet {
     uint4 *P[3] = {nullptr, nullptr, nullptr};
     float *b[3] = {nullptr, nullptr, nullptr};
     float *I1 = nullptr;
+    float *rpart = nullptr;  // n2t x max_batch x 32 partial readouts
     float *wtmp = nullptr;
     size_t wtmp_n = 0;
     bool set[3] = {false, false, false};
@@ -490,6 +472,7 @@ struct snn_ifnet {
             if (b[l]) (void)hipFree(b[l]);
         }
         if (I1) (void)hipFree(I1);
+        if (rpart) (void)hipFree(rpart);
         if (wtmp) (void)hipFree(wtmp);
     }
     // rows K, columns N, 16-deep chunks, 32-wide tiles of layer l (0-based)
@@ -536,7 +519,7 @@ extern "C" snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream
     d.k2 = (d.h1 + 15) / 16;
     d.n2t = (d.h2 + 31) / 32;
     d.k3 = (d.h2 + 15) / 16;
-    n->lds = net_lds_bytes(d);
+    n->lds = kNetLds;
     auto bail = [&](hipError_t e, const char *what) {
         delete n;
         return snn_net::error(e == hipErrorOutOfMemory ? SNN_ENOMEM : SNN_EDEVICE,
@@ -555,6 +538,8 @@ extern "C" snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream
     n->wtmp_n = wmax;
     if ((e = hipMalloc(&n->wtmp, wmax * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = hipMalloc(&n->I1, (size_t)cfg->max_batch * 32 * d.n1t * sizeof(float))) != hipSuccess)
+        return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&n->rpart, (size_t)cfg->max_batch * 32 * d.n2t * sizeof(float))) != hipSuccess)
         return bail(e, "hipMalloc");
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_if_net<false>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds)) != hipSuccess ||
@@ -610,12 +595,17 @@ extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, u
     else
         hipLaunchKernelGGL(k_if_input<false>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
     IF_TRY(hipGetLastError());
-    IfNetArgs na{net->I1, net->P[1], net->P[2], net->b[1], net->b[2], (float)net->cfg.theta_h1,
+    IfNetArgs na{net->I1, net->P[1], net->P[2], net->b[1], net->b[2], net->rpart, (float)net->cfg.theta_h1,
                  (float)net->cfg.theta_h2, (int)batch, (int)T, net->d, o};
+    const dim3 grid(tiles, net->d.n2t);
     if (o.raster_h1 || o.raster_h2 || o.v_h1 || o.v_h2)
-        hipLaunchKernelGGL(k_if_net<true>, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
+        hipLaunchKernelGGL(k_if_net<true>, grid, dim3(kNetThreads), net->lds, net->stream, na);
     else
-        hipLaunchKernelGGL(k_if_net<false>, dim3(tiles), dim3(kNetThreads), net->lds, net->stream, na);
+        hipLaunchKernelGGL(k_if_net<false>, grid, dim3(kNetThreads), net->lds, net->stream, na);
+    IF_TRY(hipGetLastError());
+    if (o.out_sum || o.pred)
+        hipLaunchKernelGGL(k_if_readout, dim3((batch + 7) / 8), dim3(256), 0, net->stream, net->rpart, net->b[2],
+                           (int)batch, (int)T, net->d.n2t, net->d.n_out, o.out_sum, o.pred);
     IF_TRY(hipGetLastError());
     return SNN_OK;
 }
