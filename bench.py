@@ -272,7 +272,7 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
             "peak_active": st["peak_active"]}
 
 
-MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+FP32_MATRIX_PEAK_TFLOPS = 157.3
 
 
 def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> dict:
@@ -320,8 +320,8 @@ def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> di
            "b1_us_per_image": ms1 * 1e3, "b1_value": T / (ms1 * 1e-3),
            "batch_speedup_b1024_vs_b1": (B / ms) / (1 / ms1),
            "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
-                        "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-                        "frac": flops / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"],
+                        "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": flops / (ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
                         "flops_per_run": flops,
                         "issued_bf16_frac": issued / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"]}}
     if oracle:
