@@ -20,6 +20,7 @@
  *     (Unsupervised Learning section);
  *   - online STDP from nearest-spike traces, reduced over the batch by sum,
  *     mean or per-synapse maximum (Reduction methods section; Fig. 3 text),
+ *     or by the signed maximum of the per-sample changes (a variant),
  *     clamp to [w_min, w_max] and per-column normalisation to a fixed sum
  *     (Unsupervised Learning section).
  * Readings of points the paper leaves open are listed in the design notes:
@@ -95,7 +96,7 @@ typedef struct {
 typedef struct {
     int32_t n_in, n_exc, n_inh;      /* n_inh = 0: no inhibitory layer      */
     int32_t uniform_rate, learn;     /* uniform_rate: every input max_rate  */
-    int32_t trace_additive, reduce;  /* reduce: 0 sum, 1 mean, 2 max         */
+    int32_t trace_additive, reduce;  /* reduce: 0 sum, 1 mean, 2 max, 3 signed max */
     int32_t precision;               /* operand rounding, see orc_quantize  */
     double dt_ms, max_rate_hz;
     orc_lif exc, inh;
@@ -319,11 +320,14 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
             /* 6-7. batch-reduced weight change, clamp.  P: potentiation on a
              * post spike from the pre trace; D: depression on a pre spike from
              * the post trace; each reduced over the batch on its own, visiting
-             * the samples in order b = 0 .. B-1. */
+             * the samples in order b = 0 .. B-1.  Signed max (mode 3) instead
+             * takes, per synapse, the largest of the B per-sample changes
+             * nu_post tp - nu_pre td (0 for a sample with neither spike). */
 #pragma omp parallel
             {
                 double *P = malloc(sizeof(double) * (size_t)n_exc);
                 double *D = malloc(sizeof(double) * (size_t)n_exc);
+                double *M = malloc(sizeof(double) * (size_t)n_exc);
 #pragma omp for schedule(static)
                 for (int i = 0; i < n_in; ++i) {
                     for (int b = 0; b < B; ++b) {
@@ -334,6 +338,10 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                         for (int j = 0; j < n_exc; ++j) {
                             double tp = se[j] ? orc_quantize(xp, prec) : 0.0;
                             double td = sp ? orc_quantize(xq[j], prec) : 0.0;
+                            if (c->reduce == 3) {
+                                double dw = c->nu_post * tp - c->nu_pre * td;
+                                if (b == 0 || dw > M[j]) M[j] = dw;
+                            }
                             if (b == 0) {
                                 P[j] = tp;
                                 D[j] = td;
@@ -349,7 +357,8 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                     for (int j = 0; j < n_exc; ++j) {
                         double Pj = c->reduce == 1 ? P[j] / (double)B : P[j];
                         double Dj = c->reduce == 1 ? D[j] / (double)B : D[j];
-                        double w = W[(size_t)i * n_exc + j] + c->nu_post * Pj - c->nu_pre * Dj;
+                        double w = c->reduce == 3 ? W[(size_t)i * n_exc + j] + M[j]
+                                                  : W[(size_t)i * n_exc + j] + c->nu_post * Pj - c->nu_pre * Dj;
                         if (w < c->w_min) w = c->w_min;
                         if (w > c->w_max) w = c->w_max;
                         W[(size_t)i * n_exc + j] = w;
@@ -357,6 +366,7 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                 }
                 free(P);
                 free(D);
+                free(M);
             }
 
             /* 7b. column normalisation: the weights into each post neuron
@@ -378,7 +388,7 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                 double *terms = malloc(sizeof(double) * (size_t)B);
                 for (int j = 0; j < n_exc; ++j) {
                     for (int b = 0; b < B; ++b) terms[b] = (double)s_exc[(size_t)b * n_exc + j];
-                    theta[j] += c->exc.theta_plus * reduce_terms(terms, B, c->reduce);
+                    theta[j] += c->exc.theta_plus * reduce_terms(terms, B, c->reduce == 3 ? 2 : c->reduce);
                 }
                 free(terms);
             }

@@ -239,10 +239,10 @@ def run_dc(oracle_mod, cfg, W, images, ids, T, **kw):
     return net, out
 
 
-@pytest.mark.parametrize("reduce", ["sum", "mean", "max"])
+@pytest.mark.parametrize("reduce", ["sum", "mean", "max", "max_signed"])
 def test_identical_samples_match_single_run(oracle_mod, reduce):
-    """B = 2 copies of one sample (same image, same id): mean and max equal
-    the single-sample run exactly; sum equals the single run with the learning
+    """B = 2 copies of one sample (same image, same id): mean, max and signed
+    max equal the single-sample run exactly; sum equals the single run with the learning
     rates and theta increment doubled (x + x = 2x exactly)."""
     T = 60
     img = stroke_images(1, 11, 0.25)
@@ -263,12 +263,16 @@ def test_single_sample_reductions_agree(oracle_mod):
     """With B = 1 every reduction is the identity."""
     img = stroke_images(1, 5, 0.2)
     Ws = []
-    for r in ("sum", "mean", "max"):
+    for r in ("sum", "mean", "max", "max_signed"):
         cfg, W = dc_small(reduce=r)
         net, _ = run_dc(oracle_mod, cfg, W, img, sample_ids(1), 50)
         Ws.append((net.W, net.theta))
-    for W_, th in Ws[1:]:
+    for W_, th in Ws[1:3]:
         assert np.array_equal(W_, Ws[0][0]) and np.array_equal(th, Ws[0][1])
+    # signed max adds the per-sample change as one term: W + (a - b) instead
+    # of (W + a) - b, equal up to the last bit
+    np.testing.assert_allclose(Ws[3][0], Ws[0][0], rtol=0, atol=1e-14)
+    assert np.array_equal(Ws[3][1], Ws[0][1]) and np.abs(Ws[3][0] - Ws[0][0]).max() < 1e-15
 
 
 def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post):
@@ -281,7 +285,7 @@ def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post):
     n_in, n_exc = 6, 4
     cfg = tiny_cfg(n_in, n_exc, learn=True, norm=0.0, w_min=-100.0, w_max=100.0,
                    nu_pre=nu_pre, nu_post=nu_post, exc=dict(adaptive=0))
-    cfg["reduce"] = {"sum": 0, "mean": 1, "max": 2}[reduce]
+    cfg["reduce"] = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3}[reduce]
     W0 = np.full((n_in, n_exc), 0.5)
     W0[0, :] = [20.0, 0.0, 20.0, 0.0]
     W0[1, :] = [0.0, 20.0, 20.0, 0.0]
@@ -314,6 +318,30 @@ def test_max_reduction_is_per_synapse_maximum(oracle_mod):
     W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "max", 1e-4, 0.0)
     assert np.array_equal(Wb, np.minimum(W1, W2))
     assert (Wb != W1).any() and (Wb != W2).any()
+
+
+def test_signed_max_is_largest_per_sample_change(oracle_mod):
+    """The signed max reduction keeps, per synapse, the largest of the
+    per-sample changes nu_post P_b - nu_pre D_b (0 for a sample without an
+    event), so after one learning step W = max of the single-sample results.
+    Where one sample potentiates a synapse and the other depresses it, this
+    differs from the per-term max (largest potentiation minus largest
+    depression)."""
+    W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "max_signed", 1e-4, 1e-2)
+    assert np.array_equal(Wb, np.maximum(W1, W2))
+    # nu_pre > nu_post: a pre and post spike in the same step depress, a
+    # trace from the earlier step potentiates, so some synapses see both
+    W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "max_signed", 1e-2, 1e-4)
+    assert np.array_equal(Wb, np.maximum(W1, W2))
+    _, Wt, _ = _two_samples_one_learning_step(oracle_mod, "max", 1e-2, 1e-4)
+    mixed = ((W1 > W0) & (W2 < W0)) | ((W1 < W0) & (W2 > W0))
+    assert mixed.any() and (Wb[mixed] > W0[mixed]).all() and (Wt[mixed] < W0[mixed]).all()
+    # depression only: the two samples' pre spikes of the learning step fall
+    # on different inputs, so each depressed synapse has a sample without an
+    # event on it, whose change 0 is the largest: no weight moves
+    W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "max_signed", 1e-4, 0.0)
+    assert np.array_equal(Wb, np.maximum(W1, W2))
+    assert (np.minimum(W1, W2) < W0).any() and np.array_equal(Wb, W0)
 
 
 def test_sum_and_mean_over_distinct_samples(oracle_mod):
