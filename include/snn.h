@@ -51,8 +51,18 @@ typedef enum {
 
 /* Batch reduction of per-sample parameter updates (Reduction methods
  * section: averaging by default, summation, per-synapse maximum per step as
- * in the unsupervised-learning experiment). */
-typedef enum { SNN_REDUCE_SUM = 0, SNN_REDUCE_MEAN = 1, SNN_REDUCE_MAX = 2 } snn_reduce;
+ * in the unsupervised-learning experiment).  MAX keeps the largest
+ * potentiation and, separately, the largest depression of each synapse;
+ * MAX_SIGNED (a variant) adds the largest per-sample change
+ * nu_post P_b - nu_pre D_b, which is 0 for a sample with no spike on the
+ * synapse.  Theta uses the maximum for both.  MAX_SIGNED runs on the PLAIN
+ * and MFMA paths (the FUSED and PERSISTENT paths fall back to PLAIN). */
+typedef enum {
+    SNN_REDUCE_SUM = 0,
+    SNN_REDUCE_MEAN = 1,
+    SNN_REDUCE_MAX = 2,
+    SNN_REDUCE_MAX_SIGNED = 3
+} snn_reduce;
 
 /* Operand form of the two contractions of a step (the synaptic current and
  * the STDP products).  Spikes are exact 0/1 operands; the weight (current)

@@ -65,6 +65,6 @@ struct Outs {
     float *v_inh;          // T x B x n_exc
 };
 
-enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2 };
+enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2, RED_MAX_SIGNED = 3 };
 
 }  // namespace snn

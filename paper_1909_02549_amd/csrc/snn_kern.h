@@ -78,7 +78,7 @@ __device__ __forceinline__ double theta_step(const Params &p, double theta, int 
 {
     double r = (double)count;
     if (p.reduce == RED_MEAN) r = (double)count / (double)p.B;
-    else if (p.reduce == RED_MAX) r = count > 0 ? 1.0 : 0.0;
+    else if (p.reduce >= RED_MAX) r = count > 0 ? 1.0 : 0.0;
     return theta * p.beta + p.theta_plus * r;
 }
 

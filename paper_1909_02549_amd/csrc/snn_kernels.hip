@@ -209,7 +209,9 @@ __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__
 //   W <- clamp(W + nu_post P - nu_pre D), column sums in FP64, W[:, j] *=
 //   norm / c_j; theta <- theta * beta + theta_plus * R_b s_exc[b, j].
 // R is sum, mean (sum / B) or max, applied to P and D separately; the traces
-// enter in the operand form of the precision (unrounded for FP32).
+// enter in the operand form of the precision (unrounded for FP32).  The
+// signed max instead adds max_b (nu_post P_b - nu_pre D_b), the largest
+// per-sample change, 0 for a sample with neither spike on the synapse.
 __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W, double *__restrict__ theta,
                                                  const uint16_t *__restrict__ rf,
                                                  const float *__restrict__ x_post,
@@ -241,7 +243,36 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
     const bool col_ok = r0 < R && j < p.n_exc;
     float *Wg = W + (size_t)g * p.n_in_pad * JB;
     double cs = 0.0;
-    if (col_ok) {
+    if (col_ok && p.reduce == RED_MAX_SIGNED) {
+        for (int i = r0; i < p.n_in; i += R) {
+            // walk the samples in which input i or post neuron j spiked
+            const uint32_t *bt = bitsT_t + (size_t)i * p.bwords;
+            const uint32_t *sp = spk + jj * p.bwords;
+            float best = -INFINITY;
+            int events = 0;
+            for (int bw = 0; bw < p.bwords; ++bw) {
+                const uint32_t mi = bt[bw], ms = sp[bw];
+                uint32_t m = mi | ms;
+                events += __builtin_popcount(m);
+                while (m) {
+                    const int bit = __builtin_ctz(m);
+                    const int b = 32 * bw + bit;
+                    m &= m - 1;
+                    const float pot = (ms >> bit) & 1u
+                                          ? p.nu_post * operand_value(p.prec, x_pre[(size_t)b * p.n_in_pad + i])
+                                          : 0.f;
+                    const float dep = (mi >> bit) & 1u
+                                          ? p.nu_pre * operand_value(p.prec, x_post[sbase + (size_t)b * p.jbp + jj])
+                                          : 0.f;
+                    best = fmaxf(best, pot - dep);
+                }
+            }
+            if (events < p.B) best = fmaxf(best, 0.f);
+            const float w = fminf(fmaxf(Wg[(size_t)i * JB + jj] + best, p.w_min), p.w_max);
+            Wg[(size_t)i * JB + jj] = w;
+            cs += (double)w;
+        }
+    } else if (col_ok) {
         for (int i = r0; i < p.n_in; i += R) {
             float D = 0.f, P = 0.f;
             const uint32_t *bt = bitsT_t + (size_t)i * p.bwords;

@@ -311,7 +311,7 @@ size_t mfma_plastic_lds(const Params &p, int prec) { return PlasticLds(p, prec).
 
 bool mfma_plastic_fits(const Params &p, int prec)
 {
-    return p.reduce != RED_MAX && p.jb <= 32 && p.n_in_pad <= 32 * kPlasticWaves * kPlasticTiles &&
+    return p.reduce < RED_MAX && p.jb <= 32 && p.n_in_pad <= 32 * kPlasticWaves * kPlasticTiles &&
            mfma_plastic_lds(p, prec) <= 160 * 1024;
 }
 

@@ -138,7 +138,8 @@ static snn_status validate(const snn_config *c)
     if (c->exc.refrac_steps < 0 || c->exc.refrac_steps > 127 || c->inh.refrac_steps < 0 ||
         c->inh.refrac_steps > 127)
         return fail(SNN_EINVAL, "refrac_steps must be in [0, 127]");
-    if (c->reduce < 0 || c->reduce > 2) return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean) or 2 (max)");
+    if (c->reduce < 0 || c->reduce > 3)
+        return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean), 2 (max) or 3 (signed max)");
     if (c->precision < 0 || c->precision > 2) return fail(SNN_EINVAL, "precision must be 0, 1 or 2");
     if (c->path < 0 || c->path > 4) return fail(SNN_EINVAL, "path must be 0..4");
     if (c->learn && (!(c->tau_pre_ms > 0) || !(c->tau_post_ms > 0)))
@@ -418,7 +419,7 @@ extern "C" snn_status snn_get_theta(snn_net *net, double *th, size_t n)
 extern "C" snn_status snn_stdp_reduce(snn_net *net, int32_t mode)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
-    if (mode < 0 || mode > 2) return fail(SNN_EINVAL, "mode must be 0 (sum), 1 (mean) or 2 (max)");
+    if (mode < 0 || mode > 3) return fail(SNN_EINVAL, "mode must be 0 (sum), 1 (mean), 2 (max) or 3 (signed max)");
     net->cfg.reduce = mode;
     net->p.reduce = mode;
     net->graphs_invalidate();
@@ -839,6 +840,10 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
+    // the signed max reduction is implemented by the gather plasticity kernel
+    // (plain and MFMA routes) only
+    if (p.learn && p.reduce == RED_MAX_SIGNED && (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
+        path = SNN_PATH_PLAIN;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
     if (path == SNN_PATH_MFMA && p.jb > 32) path = SNN_PATH_PLAIN;

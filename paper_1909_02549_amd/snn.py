@@ -20,7 +20,7 @@ SNN_ABI_VERSION = 1
 SNN_RUN_RESET = 1
 PATHS = {"plain": 0, "fused": 1, "persistent": 2, "auto": 3, "mfma": 4}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
-REDUCES = {"sum": 0, "mean": 1, "max": 2}
+REDUCES = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3}
 STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4: "SNN_EAGAIN",
           -5: "SNN_ENOTFOUND", -6: "SNN_ESTATE"}
 

@@ -135,6 +135,29 @@ def test_reductions_parity(torch_cuda, oracle_mod, reduce, path):
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_signed_max_reduction_parity(torch_cuda, oracle_mod, path):
+    """Signed max (the largest per-sample change) through the first burst of
+    excitatory spikes: the gather plasticity kernel of the plain and MFMA
+    routes; the fused and persistent paths fall back to the plain path.  The
+    learned weights follow the signed max, not the per-term max, wherever
+    the two differ."""
+    cfg = dc_config(100, reduce="max_signed")
+    imgs = stroke_images(16, 3, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 1)
+    T = 14
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(16, 10), T, path=path)
+    assert g["path"] == (path if path in ("plain", "mfma") else "plain")
+    assert ref["exc"].sum() > 100
+    t_div = check_parity(g, ref)
+    assert t_div == T, f"rasters diverged at step {t_div}: weights not compared"
+    orc = oracle_mod.OracleNet(dc_config(100, reduce="max"), W.astype(np.float64))
+    orc.run(imgs, sample_ids(16, 10), T, record=())
+    diff = np.abs(orc.W - ref["W"]) > 1e-5
+    assert diff.sum() > 100
+    assert (np.abs(g["W"] - ref["W"])[diff] < 0.5 * np.abs(orc.W - ref["W"])[diff]).all()
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_ragged_batch_and_inputs(torch_cuda, oracle_mod, path):
     """B = 70 (two 64-sample tiles, three 32-sample words), n_in = 50
     (ragged input word), n_exc = 37 (ragged column block)."""
