@@ -36,7 +36,7 @@ class _Config(C.Structure):
                 ("exc", _Lif), ("inh", _Lif), ("w_ei", C.c_double), ("w_ie", C.c_double),
                 ("nu_pre", C.c_double), ("nu_post", C.c_double), ("tau_pre_ms", C.c_double),
                 ("tau_post_ms", C.c_double), ("w_min", C.c_double), ("w_max", C.c_double),
-                ("norm", C.c_double), ("seed", C.c_uint64)]
+                ("norm", C.c_double), ("seed", C.c_uint64), ("norm_per_run", C.c_int32)]
 
 
 _lib = None
@@ -79,6 +79,7 @@ def make_config(cfg: dict, precision=0) -> _Config:
               "tau_post_ms", "w_min", "w_max", "norm"):
         setattr(c, k, float(cfg[k]))
     c.seed = int(cfg["seed"])
+    c.norm_per_run = int(cfg.get("norm_per_run", 0))
     for layer in ("exc", "inh"):
         L = getattr(c, layer)
         p = cfg[layer]

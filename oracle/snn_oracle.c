@@ -103,6 +103,7 @@ typedef struct {
     double w_ei, w_ie;
     double nu_pre, nu_post, tau_pre_ms, tau_post_ms, w_min, w_max, norm;
     uint64_t seed;
+    int32_t norm_per_run;            /* 1: normalise after a run's last step only */
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -370,8 +371,9 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
             }
 
             /* 7b. column normalisation: the weights into each post neuron
-             * sum to `norm` (skipped for an all-zero column) */
-            if (c->norm > 0.0) {
+             * sum to `norm` (skipped for an all-zero column); every learning
+             * step, or (the cheaper variant) after the run's last step only */
+            if (c->norm > 0.0 && (!c->norm_per_run || k == T - 1)) {
 #pragma omp parallel for schedule(static)
                 for (int j = 0; j < n_exc; ++j) {
                     double cs = 0.0;

@@ -367,6 +367,30 @@ def test_column_normalisation_invariant(oracle_mod):
     assert net.W.min() >= 0.0
 
 
+def test_per_run_normalisation(oracle_mod):
+    """The cheaper variant normalises once, after a run's last step.  Until
+    then the run is exactly the run without normalisation (same spikes and
+    thresholds), and its final weights are that run's weights with every
+    column scaled to sum to 78.4 (scale computed here by numpy).  A one-step
+    run equals the per-step variant bit for bit."""
+    T = 40
+    img = stroke_images(3, 17, 0.22)
+    ids = sample_ids(3, 40)
+    cfg, W = dc_small()
+    net_run, out_run = run_dc(oracle_mod, dict(cfg, norm_per_run=1), W, img, ids, T, record=("exc",))
+    net_off, out_off = run_dc(oracle_mod, dict(cfg, norm=0.0), W, img, ids, T, record=("exc",))
+    assert out_run["exc"].sum() >= 5
+    assert np.array_equal(out_run["exc"], out_off["exc"]) and np.array_equal(net_run.theta, net_off.theta)
+    cs = net_off.W.sum(axis=0)
+    assert (cs > 0).all()
+    np.testing.assert_allclose(net_run.W, net_off.W * (78.4 / cs)[None, :], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(net_run.W.sum(axis=0), 78.4, rtol=1e-12)
+    assert np.abs(net_off.W.sum(axis=0) - 78.4).max() > 1e-3
+    net1, _ = run_dc(oracle_mod, dict(cfg, norm_per_run=1), W, img, ids, 1)
+    net2, _ = run_dc(oracle_mod, cfg, W, img, ids, 1)
+    assert np.array_equal(net1.W, net2.W)
+
+
 def test_lateral_inhibition_hand_case(oracle_mod):
     """Exc neuron 0 fires at t; its inhibitory partner fires at t+1 (rest -60
     plus 22.5 crosses -40); at t+2 every other exc neuron is 120 mV lower than
