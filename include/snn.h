@@ -122,7 +122,11 @@ typedef struct {
     double norm;                   /* column sum target; <= 0 disables              */
     uint64_t seed;                 /* Philox key of the Poisson encoder             */
     uint32_t max_batch;            /* largest batch snn_run will accept             */
-    uint32_t reserved0;
+    uint32_t norm_per_run;         /* 1: normalise once, after the last step of
+                                      each snn_run / snn_run_spikes call (a
+                                      cheaper variant; PLAIN and MFMA paths,
+                                      FUSED and PERSISTENT fall back to PLAIN);
+                                      0: after every learning step            */
     uint64_t hbm_budget_bytes;     /* 0: no limit                                   */
 } snn_config;
 

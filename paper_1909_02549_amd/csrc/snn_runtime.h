@@ -46,6 +46,7 @@ struct snn_net {
     uint16_t *ord_s = nullptr;   // (chunk + 1) x B samples by decreasing cin
     uint16_t *ord_in = nullptr;  // (chunk + 1) x n_in_pad inputs by decreasing ct
     uint32_t chunk = kChunk;     // steps per encoder launch for the current batch
+    uint32_t run_T = 0;          // steps of the current snn_run call (per-run normalisation)
     uint32_t cap_chunk = kChunk; // steps the buffers hold at capacity
     uint8_t *flags_mask = nullptr;
 

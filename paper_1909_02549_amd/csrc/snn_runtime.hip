@@ -148,6 +148,7 @@ static snn_status validate(const snn_config *c)
         return fail(SNN_EINVAL, "tau_theta_ms must be > 0");
     if (c->w_min > c->w_max) return fail(SNN_EINVAL, "w_min > w_max");
     if (c->max_batch == 0) return fail(SNN_EINVAL, "max_batch must be > 0");
+    if (c->norm_per_run > 1) return fail(SNN_EINVAL, "norm_per_run must be 0 or 1");
     double prob = c->max_rate_hz * c->dt_ms / 1000.0;
     if (!(prob >= 0.0) || prob > 1.0) return fail(SNN_EINVAL, "max_rate_hz * dt must be a probability");
     return SNN_OK;
@@ -603,6 +604,10 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o, bool mfma)
                    (const float *)I, (const double *)theta, (const uint32_t *)Cprev, Ccur, Cnext, v_exc, v_inh, rf,
                    x_post, k, o);
     }
+    // per-run normalisation: the plasticity launches of all but the run's
+    // last step see norm = 0 (no normalisation)
+    Params pp = p;
+    if (cfg.norm_per_run && (uint32_t)k + 1 != run_T) pp.norm = 0.0;
     if (p.learn && mfma && mfma_plastic_fits(p, p.prec)) {
         const size_t lds = mfma_plastic_lds(p, p.prec);
         const void *fn = p.prec == PREC_FP32   ? (const void *)k_mfma_plastic<PREC_FP32>
@@ -614,18 +619,18 @@ snn_status snn_net::plain_step(int kk, int k, const Outs &o, bool mfma)
         }
         const dim3 grid((unsigned)p.nblk);
         if (p.prec == PREC_FP32)
-            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP32>, grid, dim3(512), lds, p, W, theta,
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP32>, grid, dim3(512), lds, pp, W, theta,
                        (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
         else if (p.prec == PREC_BF16)
-            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_BF16>, grid, dim3(512), lds, p, W, theta,
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_BF16>, grid, dim3(512), lds, pp, W, theta,
                        (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
         else
-            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP8>, grid, dim3(512), lds, p, W, theta,
+            SNN_LAUNCH("mfma_plastic", k_mfma_plastic<PREC_FP8>, grid, dim3(512), lds, pp, W, theta,
                        (const uint16_t *)rf, (const float *)x_post, (const float *)xcur, bitsT_t);
     } else if (p.learn) {
         const int R = 256 / p.jb;
         const size_t sm = align16((size_t)p.jb * p.bwords * 4) + (size_t)(R * p.jb + p.jb) * 8;
-        SNN_LAUNCH("plastic", k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, p, W, theta, (const uint16_t *)rf,
+        SNN_LAUNCH("plastic", k_plastic, dim3((unsigned)p.nblk), dim3(256), sm, pp, W, theta, (const uint16_t *)rf,
                    (const float *)x_post, (const float *)xcur, bitsT_t);
     }
     HIP_TRY(hipGetLastError());
@@ -840,10 +845,12 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
-    // the signed max reduction is implemented by the gather plasticity kernel
-    // (plain and MFMA routes) only
-    if (p.learn && p.reduce == RED_MAX_SIGNED && (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
+    // the signed max reduction and per-run normalisation are implemented by
+    // the plasticity kernels of the plain and MFMA routes only
+    if (p.learn && (p.reduce == RED_MAX_SIGNED || (cfg.norm_per_run && p.norm > 0.0)) &&
+        (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
         path = SNN_PATH_PLAIN;
+    run_T = T;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;
     if (path == SNN_PATH_MFMA && p.jb > 32) path = SNN_PATH_PLAIN;

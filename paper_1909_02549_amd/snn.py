@@ -54,7 +54,7 @@ class snn_config(C.Structure):
                 ("nu_pre", C.c_double), ("nu_post", C.c_double), ("tau_pre_ms", C.c_double),
                 ("tau_post_ms", C.c_double), ("w_min", C.c_double), ("w_max", C.c_double),
                 ("norm", C.c_double), ("seed", C.c_uint64), ("max_batch", C.c_uint32),
-                ("reserved0", C.c_uint32), ("hbm_budget_bytes", C.c_uint64)]
+                ("norm_per_run", C.c_uint32), ("hbm_budget_bytes", C.c_uint64)]
 
 
 class snn_outputs(C.Structure):
@@ -155,6 +155,7 @@ def make_config(cfg: dict, max_batch: int, path="plain", precision="fp32", hbm_b
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c.path = PATHS[path] if isinstance(path, str) else int(path)
     c.max_batch = int(max_batch)
+    c.norm_per_run = int(cfg.get("norm_per_run", 0))
     c.hbm_budget_bytes = int(hbm_budget)
     return c
 

@@ -158,6 +158,40 @@ def test_signed_max_reduction_parity(torch_cuda, oracle_mod, path):
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_per_run_normalisation_parity(torch_cuda, oracle_mod, path):
+    """Columns normalised once, after the run's last step (the cheaper
+    variant): the plasticity kernels of the plain and MFMA routes; the fused
+    and persistent paths fall back to the plain path.  Two runs in a row, the
+    second continuing the first, so that each call normalises at its own end."""
+    from paper_1909_02549_amd.snn import Net
+    cfg = dc_config(100, norm_per_run=1)
+    imgs = stroke_images(8, 4, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 5)
+    ids = sample_ids(8, 30)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, ids, 40, path=path)
+    assert g["path"] == (path if path in ("plain", "mfma") else "plain")
+    assert ref["exc"].sum() > 50
+    check_parity(g, ref)
+    np.testing.assert_allclose(g["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
+    # continuing: a second call of 10 steps on the same handle and oracle
+    torch = torch_cuda
+    net = Net(cfg, max_batch=8, path=path)
+    net.snn_set_weights(W)
+    d_imgs, d_ids = to_dev(torch, imgs), to_dev(torch, ids.astype(np.int64))
+    net.snn_run(d_imgs, d_ids, 40, record=())
+    net.snn_run(d_imgs, d_ids, 10, reset=False, record=())
+    torch.cuda.synchronize()
+    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
+    orc.run(imgs, ids, 40, record=())
+    orc.run(imgs, ids, 10, reset=False, record=())
+    gw = net.snn_get_weights()
+    net.close()
+    np.testing.assert_allclose(gw.astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
+    err = np.abs(gw - orc.W)
+    assert (err <= W_RTOL * np.abs(orc.W) + W_ATOL).mean() > 0.99
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_ragged_batch_and_inputs(torch_cuda, oracle_mod, path):
     """B = 70 (two 64-sample tiles, three 32-sample words), n_in = 50
     (ragged input word), n_exc = 37 (ragged column block)."""
