@@ -831,7 +831,7 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
 // weights), the rows of load_block without the thresholds.
 __device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S, const float *Wg, int tid, int nt)
 {
-    const int JB = p.jb, JBP = p.jbp, LS = p.ls;
+    const int JB = p.jb, LS = p.ls;
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     if (jj < JB) {
         int i = rg;
@@ -853,7 +853,7 @@ __device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S
 __device__ __forceinline__ void store_block(const Params &p, const StepLds &S, float *Wg, double *theta, int g,
                                             int tid, int nt)
 {
-    const int JB = p.jb, JBP = p.jbp, LS = p.ls;
+    const int JB = p.jb, LS = p.ls;
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     if (jj < JB) {
         const double sc = S.scale[jj];
