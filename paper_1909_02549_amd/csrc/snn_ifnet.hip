@@ -190,20 +190,24 @@ struct IfNetArgs {
 // and the h2 spike words (one tile).
 constexpr size_t kAbufBytes = 2 * kMaxK2 * 64 * sizeof(uint4);
 constexpr size_t kPartBytes = 2 * 4 * 16 * 64 * sizeof(float);
-constexpr size_t kNetLds = kAbufBytes + kPartBytes + (8 + 1) * 32 * sizeof(uint32_t);
+constexpr size_t kNetLds = kAbufBytes + kPartBytes + (8 + 2) * 32 * sizeof(uint32_t);
+constexpr int kOutWave = 3;  // the chunk wave that runs the output layer
 
 // One workgroup per (32-sample tile, h2 tile y) runs all T steps as a
-// three-stage pipeline of 12 waves; in iteration i:
+// four-stage pipeline of 12 waves; in iteration i:
 //   waves 4..11 ("h1 waves") integrate step i of h1 tile w - 4 (every h2
 //     tile's workgroup integrates all of h1) and publish the h2 operand
 //     fragments of its two chunks in buffer i % 2;
-//   waves 0..3 ("chunk waves") multiply step i - 1's fragments of chunks
-//     4p..4p + 3 (p = wave) by h2 tile y's weights (three planes, held in
-//     registers) and store the partial sums in buffer (i - 1) % 2;
-//   wave 0 first finishes step i - 2: adds the four partial sums in wave
-//     order plus the bias, integrates h2 tile y, publishes its spike word
-//     and multiplies it by the output weights of chunks 2y and 2y + 1,
-//     accumulating this tile's share of the readout over the run;
+//   waves 0..3 ("chunk waves"), wave p:
+//     multiplies step i - 1's fragments of chunks 4p..4p + 3 by h2 tile y's
+//       weights (three planes, held in registers) and stores the partial
+//       sum in buffer (i - 1) % 2;
+//     finishes step i - 2 for C rows 4p..4p + 3 of the tile: adds the four
+//       partial sums in wave order plus the bias, integrates, and stores the
+//       rows' ballot words of the tile in buffer (i - 2) % 2;
+//     (wave kOutWave only) multiplies step i - 3's spike words of the tile
+//       by the output weights of chunks 2y and 2y + 1, accumulating this
+//       tile's share of the readout over the run;
 // one workgroup barrier ends the iteration.  C layout of a tile: lane l
 // holds neuron 32q + l % 32 of samples 8 (r / 4) + 4 (l / 32) + r % 4,
 // r = 0..15.  REC: also record voltages and rasters (the parity outputs).
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     uint4 *abuf = lds_if;
     float *part = reinterpret_cast<float *>(reinterpret_cast<char *>(lds_if) + kAbufBytes);
     uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(part) + kPartBytes);
-    uint32_t *mask2 = mask1 + 8 * 32;
+    uint32_t *mask2 = mask1 + 8 * 32;  // two steps' words of the h2 tile
 
     // operand fragments of the chunks no h1 tile writes (c >= 2 n1t) stay zero
     const int nz = (kMaxK2 - 2 * d.n1t) * 64;
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     const int h1w = (d.h1 + 31) >> 5, h2w = (d.h2 + 31) >> 5;
     const uint4 zero = make_uint4(0, 0, 0, 0);
 
-    // Each role runs its own loop with one barrier per iteration (T + 2 in
+    // Each role runs its own loop with one barrier per iteration (T + 3 in
     // both), so that only its own state is live in registers.
     if (h1wave) {
         const int n1p = 32 * d.n1t;
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
 #pragma unroll
         for (int j = 0; j < 8; ++j) cnt1[j] = 0;
         __syncthreads();
-        for (int i = 0; i <= a.T + 1; ++i) {
+        for (int i = 0; i <= a.T + 2; ++i) {
             if (i < a.T && has1) {
                 const int t = i;
                 uint4 *ab = abuf + (t & 1) * kMaxK2 * 64;
@@ -313,59 +317,29 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                 wp[j][pl] = c < d.k2 ? x : zero;
             }
         }
-        // wave 0 also finishes the steps: output weights of chunks 2y, 2y + 1
+        // wave p also integrates C rows 4p..4p + 3 of the h2 tile; wave
+        // kOutWave runs the output chunks 2y and 2y + 1
         uint4 w3[2][3];
-        float v2[16], bias2 = 0.f;
-        uint32_t cnt2[8];
-        f32x16_t acc3 = {};
-        if (p == 0) {
+        const bool outw = p == kOutWave;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c3 = 2 * y + j;
+        for (int j = 0; j < 2; ++j) {
+            const int c3 = 2 * y + j;
 #pragma unroll
-                for (int pl = 0; pl < 3; ++pl) {
-                    const uint4 x = a.P3[(size_t)((c3 < d.k3 ? c3 : 0) * 3 + pl) * 64 + lane];
-                    w3[j][pl] = c3 < d.k3 ? x : zero;
-                }
+            for (int pl = 0; pl < 3; ++pl) {
+                const uint4 x = a.P3[(size_t)((c3 < d.k3 ? c3 : 0) * 3 + pl) * 64 + lane];
+                w3[j][pl] = (outw && c3 < d.k3) ? x : zero;
             }
-            bias2 = a.b2[32 * y + col_in];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) v2[r] = 0.f;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) cnt2[j] = 0;
         }
+        const float bias2 = a.b2[32 * y + col_in];
+        float v2[4] = {0.f, 0.f, 0.f, 0.f};
+        uint32_t cnt2[2] = {0u, 0u};
+        f32x16_t acc3 = {};
         __syncthreads();
-        for (int i = 0; i <= a.T + 1; ++i) {
-            if (p == 0 && i >= 2) {
-                // finish step t = i - 2 of h2 tile y
-                const int t = i - 2;
-                const float *pt = part + (t & 1) * 4 * 16 * 64;
-                const int col2 = 32 * y + col_in;
-                uint64_t mb[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float sum = ((pt[r * 64 + lane] + pt[(16 + r) * 64 + lane]) + pt[(32 + r) * 64 + lane]) +
-                                      pt[(48 + r) * 64 + lane];
-                    const float u = v2[r] + (sum + bias2);
-                    const bool s = u >= a.th2;
-                    v2[r] = s ? u - a.th2 : u;
-                    cnt2[r >> 1] += (uint32_t)s << (16 * (r & 1));
-                    mb[r] = __builtin_amdgcn_ballot_w64(s);
-                    if (REC && a.o.v_h2) {
-                        const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
-                        if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[r];
-                    }
-                }
-                uint64_t *mq = reinterpret_cast<uint64_t *>(mask2);
-                if (lane == 0) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) mq[r] = mb[r];
-                }
-                // output layer: the wave reads back its own h2 spikes
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const uint32_t word2 = mask2[slot];
+        for (int i = 0; i <= a.T + 2; ++i) {
+            if (outw && i >= 3) {
+                // output layer for step t = i - 3 from the tile's spike words
+                const int t = i - 3;
+                const uint32_t word2 = mask2[(t & 1) * 32 + slot];
                 if (REC && a.o.raster_h2 && lane < 32 && s0 + lane < a.B)
                     a.o.raster_h2[((size_t)t * a.B + s0 + lane) * h2w + y] = word2;
 #pragma unroll
@@ -374,6 +348,35 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                     acc3 = mfma<PREC_FP32>(A, w3[j][0], acc3);
                     acc3 = mfma<PREC_FP32>(A, w3[j][1], acc3);
                     acc3 = mfma<PREC_FP32>(A, w3[j][2], acc3);
+                }
+            }
+            if (i >= 2 && i <= a.T + 1) {
+                // finish step t = i - 2 for C rows 4p..4p + 3: add the four
+                // partial sums in wave order plus the bias, integrate, publish
+                // the rows' ballot words
+                const int t = i - 2;
+                const float *pt = part + (t & 1) * 4 * 16 * 64;
+                const int col2 = 32 * y + col_in;
+                uint64_t mb[4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int r = 4 * p + rr;
+                    const float sum = ((pt[r * 64 + lane] + pt[(16 + r) * 64 + lane]) + pt[(32 + r) * 64 + lane]) +
+                                      pt[(48 + r) * 64 + lane];
+                    const float u = v2[rr] + (sum + bias2);
+                    const bool s = u >= a.th2;
+                    v2[rr] = s ? u - a.th2 : u;
+                    cnt2[rr >> 1] += (uint32_t)s << (16 * (rr & 1));
+                    mb[rr] = __builtin_amdgcn_ballot_w64(s);
+                    if (REC && a.o.v_h2) {
+                        const int s_ = s0 + 8 * (r >> 2) + (r & 3) + 4 * (lane >> 5);
+                        if (s_ < a.B && col2 < d.h2) a.o.v_h2[((size_t)t * a.B + s_) * d.h2 + col2] = v2[rr];
+                    }
+                }
+                uint64_t *mq = reinterpret_cast<uint64_t *>(mask2 + (t & 1) * 32);
+                if (lane == 0) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) mq[4 * p + rr] = mb[rr];
                 }
             }
             if (i >= 1 && i <= a.T) {
@@ -394,15 +397,16 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
             }
             __syncthreads();
         }
-        if (p == 0) {
-            if (a.o.counts_h2 && 32 * y + col_in < d.h2) {
+        if (a.o.counts_h2 && 32 * y + col_in < d.h2) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (s < a.B)
-                        a.o.counts_h2[(size_t)s * d.h2 + 32 * y + col_in] = (cnt2[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-                }
+            for (int rr = 0; rr < 4; ++rr) {
+                const int r = 4 * p + rr;
+                const int s = s0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (s < a.B)
+                    a.o.counts_h2[(size_t)s * d.h2 + 32 * y + col_in] = (cnt2[rr >> 1] >> (16 * (rr & 1))) & 0xFFFFu;
             }
+        }
+        if (outw) {
             // this tile's share of the readout
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
