@@ -275,6 +275,22 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
 FP32_MATRIX_PEAK_TFLOPS = 157.3
 
 
+def conversion_flops(sizes, B: int, T: int) -> float:
+    """Algorithmic flops of one converted-network run: the analog input's
+    contraction once, the two spike contractions every step."""
+    n_in, h1, h2, n_out = sizes
+    return 2.0 * B * (n_in * h1 + T * (h1 * h2 + h2 * n_out))
+
+
+def conversion_issued_flops(sizes, B: int, T: int) -> float:
+    """bfloat16 matrix-core flops one run issues: three weight planes, tiles
+    padded to 32 samples x 32 neurons x 16-deep chunks, the output layer
+    padded to one 32-wide tile."""
+    n_in, h1, h2, n_out = sizes
+    pad = lambda n, m: m * ((n + m - 1) // m)  # noqa: E731
+    return 3 * 2.0 * pad(B, 32) * (pad(n_in, 16) * pad(h1, 32) + T * (pad(h1, 16) * pad(h2, 32) + pad(h2, 16) * 32))
+
+
 def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> dict:
     """The converted feed-forward IF network of the ANN to SNN conversion
     section: 784-256-128-10, analog input, T = 10, B = 1024 (and B = 1, the
@@ -310,9 +326,8 @@ def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> di
     ms, pred = timed(B)
     ms1, _ = timed(1)
     n_in, h1, h2, n_out = sizes
-    flops = 2.0 * B * (n_in * h1 + T * (h1 * h2 + h2 * n_out))
-    pad = lambda n, m: m * ((n + m - 1) // m)  # noqa: E731
-    issued = 3 * 2.0 * pad(B, 32) * (pad(n_in, 16) * pad(h1, 32) + T * (pad(h1, 16) * pad(h2, 32) + pad(h2, 16) * 32))
+    flops = conversion_flops(sizes, B, T)
+    issued = conversion_issued_flops(sizes, B, T)
     res = {"workload": f"converted IF net {n_in}-{h1}-{h2}-{n_out}, analog input, reset by subtraction, T={T}, "
                        f"B={B}, random weights with data-based normalisation, synthetic stroke images",
            "value": B * T / (ms * 1e-3), "unit": "sample·steps/s", "us_per_batch": ms * 1e3,

@@ -2,14 +2,15 @@
 // neurons with reset by subtraction (ANN to SNN conversion section): analog
 // input, two hidden IF layers, output-layer input summed over the run.
 //
-// Two launches per run:
-//  k_if_input  the analog input's current I1 = (p / 255) W1 + b1, the same at
-//              every step, computed once for the whole batch on a grid of
-//              (32-sample tile) x (32-neuron tile) workgroups;
-//  k_if_net    one workgroup (4 waves) per 32-sample tile runs all T steps:
-//              voltages in registers, the h1 -> h2 contraction and the h2 ->
-//              output contraction on the matrix cores, spikes exchanged
-//              through LDS bit masks; one workgroup barrier per step.
+// Three launches per run:
+//  k_if_input    the analog input's current I1 = (p / 255) W1 + b1, the same
+//                at every step, computed once for the whole batch on a grid
+//                of (32-sample tile) x (32-neuron tile) workgroups;
+//  k_if_net      one workgroup per (32-sample tile, 32-neuron h2 tile) runs
+//                all T steps: voltages in registers, the h1 -> h2 and h2 ->
+//                output contractions on the matrix cores, spikes exchanged
+//                through LDS, one workgroup barrier per step;
+//  k_if_readout  the h2 tiles' shares of the readout added, and the argmax.
 // All contractions are v_mfma_f32_32x32x16_bf16 with the FP32 weights split
 // into three bfloat16 planes that sum to them exactly; pixels (integers up to
 // 255) and spikes are exact bfloat16 operands, so every product is exact and
@@ -87,7 +88,6 @@ struct IfInArgs {
     const float *b1;     // n1t * 32, zero padded
     float *I1;           // B x n1t * 32
     int B;
-    int vec8;            // rows start on 8-byte boundaries: 8-pixel loads
     IfDims d;
 };
 
@@ -593,7 +593,7 @@ extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, u
     if (out) o = *out;
     const int tiles = (int)((batch + 31) / 32);
     const bool vec8 = net->d.n_in % 8 == 0 && (reinterpret_cast<uintptr_t>(images_dev) & 7) == 0;
-    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch, vec8 ? 1 : 0, net->d};
+    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch, net->d};
     if (vec8)
         hipLaunchKernelGGL(k_if_input<true>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
     else
