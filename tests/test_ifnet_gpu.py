@@ -6,8 +6,12 @@ Bars (FP32 path against FP64):
   neuron) entries, and at a sample's first differing step every differing
   entry of the first layer that differs is an oracle near-tie (voltage before
   the reset within 1e-3 of the threshold);
-- voltages agree within 1e-3 (threshold units) before a sample's first
-  differing step;
+- voltages agree within 1e-3 + 4e-6 |v| (threshold units) before a
+  sample's first differing step: a neuron driven above threshold keeps the
+  excess, so its voltage grows with the run (about 10^3 after 300 steps,
+  where FP32 spacing is 6e-5 and hundreds of rounded additions accumulate
+  past 1e-3); the relative term is the one of the learning network's
+  voltage bar;
 - samples that never differ: spike counts equal, summed output input within
   the FP32 summation bound gamma_m * sum |terms| (m = the number of terms
   added per output: 3 planes x 16-deep chunks x steps, plus the partial sums
@@ -24,6 +28,7 @@ pytestmark = pytest.mark.gpu
 
 RASTER_AGREE = 0.999
 V_TOL = 1e-3
+V_RTOL = 4e-6
 TIE_TOL = 1e-3
 U = 2.0 ** -24
 
@@ -79,8 +84,9 @@ def check(g, ref, layers, thresholds, T, min_clean=0.95, spikes=True):
         for b in range(B):
             t = t_div[b]
             if t:
-                dv = np.abs(g[key][b, :t] - ref[key][b, :t]).max()
-                assert dv <= V_TOL, f"sample {b}: {key} error {dv} before step {t}"
+                vr = ref[key][b, :t]
+                dv = np.abs(g[key][b, :t] - vr)
+                assert (dv <= V_TOL + V_RTOL * np.abs(vr)).all(), f"sample {b}: {key} error {dv.max()} before step {t}"
     clean = t_div == T
     assert clean.mean() >= min_clean, f"only {clean.mean():.3f} of the samples never differ"
     assert np.array_equal(g["c1"][clean], ref["c1"][clean])
@@ -206,3 +212,17 @@ def test_run_errors(torch_cuda, conv):
     net.close()
     assert net.lib.snn_ifnet_sync(None) == -1
     assert net.lib.snn_ifnet_set_layer(None, 1, None, 0, None, 0) == -1
+
+
+def test_long_run(torch_cuda, conv):
+    """T = 300 (long accumulations; 16-bit packed spike counters).  Over this
+    many steps an FP32 near-tie flip becomes likely in some samples, so the
+    bar is the raster agreement, the near-tie rule at each sample's first
+    differing step, and exact counts and readout where nothing differed."""
+    wl, layers = conv
+    imgs = inputs.stroke_images(40, 25, wl["density"])
+    T = 300
+    g = run_gpu(torch_cuda, layers, wl["thresholds"], imgs, T)
+    ref = oracle_run(layers, wl["thresholds"], imgs, T)
+    check(g, ref, layers, wl["thresholds"], T, min_clean=0.0)
+    assert g["c1"].max() > 255 or g["c2"].max() > 255 or ref["c1"].max() <= 255
