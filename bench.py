@@ -13,11 +13,15 @@ Also reported on the same JSON line:
   paths         the same workload on each execution path (plain per-step
                 launches, fused per-step kernel, persistent kernel);
   roofline      the dominant kernel's roofline from its average launch time
-                (HIP events on the library's stream over the timed region):
-                algorithmic HBM bytes per launch against the 8 TB/s HBM peak,
-                matrix-core flops against the MFMA peak (matrix kernels), and
-                algorithmic vector operations against the 157.3 TFLOP/s vector
-                peak (gather kernels); `bound` names the largest fraction;
+                (HIP events on the library's stream over the timed region).
+                For the step kernels it uses the per-step work of the whole
+                learning step (step_bytes, step_flops): the fused kernel,
+                which streams weights and state through HBM, against the
+                8 TB/s HBM peak; the persistent kernel, which keeps them on
+                chip, against the BF16 matrix-core peak of the step's
+                dense-equivalent flops.  The kernel's own models (its HBM
+                bytes, its sparse vector operations against the 157.3 TFLOP/s
+                vector peak) are kept under kernel_model / alu;
   serving       frozen 784 -> 1600 network, Poisson arrivals, T in
                 {100, 250, 500}: p50 / p99 latency and sample-steps/s;
   conversion    the converted 784-256-128-10 IF network (ANN to SNN
@@ -134,6 +138,23 @@ def alu_ops(kernel: str, d: dict, steps_per_launch: float = 1.0):
     return per_step * steps_per_launch
 
 
+def step_bytes(d: dict) -> float:
+    """HBM bytes of one learning step of the whole path for a design that
+    keeps weights and per-neuron state in HBM: the FP32 weights read and
+    written (2 x n_in_pad x N x 4), the per-neuron state read and written
+    (v_exc, v_inh, x_post 4 B each, refractory 2 B), the presynaptic traces
+    read and written.  88.5 MB for 784 -> 6400 at B = 256."""
+    B, n, N = d["B"], d["n_in_pad"], d["n_exc"]
+    return 2.0 * n * N * 4 + 2.0 * B * N * 14 + 2.0 * B * n * 4
+
+
+def step_flops(d: dict) -> float:
+    """Dense-equivalent flops of one learning step: the synaptic contraction
+    and the two STDP outer products over the batch, 3 x 2 x B x n_in_pad x N.
+    7.86 GFLOP for 784 -> 6400 at B = 256."""
+    return 6.0 * d["B"] * d["n_in_pad"] * d["n_exc"]
+
+
 def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms: float, spl: float):
     """Roofline entry of one kernel from its live HIP-event timing: HBM
     fraction from the algorithmic bytes, and for the matrix-core kernels the
@@ -164,6 +185,24 @@ def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms
                     "hbm_frac": r["frac"]}
         if afrac > r["frac"]:
             r.update(bound="alu", achieved=tf, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=afrac)
+    if kname in ("persistent", "fused_step") and d["learn"]:
+        # the per-step figures of the whole learning step: the fused kernel
+        # streams the weights and state through HBM every step and is graded
+        # against the HBM roofline; the persistent kernel keeps them on chip,
+        # so it is graded against the matrix-core roofline of the step's
+        # dense-equivalent flops (BF16 peak; FP8 peak for the FP8 form)
+        sb, sf = step_bytes(d) * spl, step_flops(d) * spl
+        hb, mf = sb / avg_s / 1e9, sf / avg_s / 1e12
+        dt = "fp8" if precision == "fp8" else "bf16"
+        model = {"bytes_per_launch": sb, "hbm_achieved": hb, "hbm_frac": hb / HBM_PEAK_GBS,
+                 "flops_per_launch": sf, "mfma_achieved": mf, "mfma_peak": MFMA_PEAK_TFLOPS[dt],
+                 "mfma_frac": mf / MFMA_PEAK_TFLOPS[dt]}
+        r["kernel_model"] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+        r["step_model"] = model
+        if kname == "persistent":
+            r.update(bound="mfma", achieved=mf, peak=MFMA_PEAK_TFLOPS[dt], unit="TFLOP/s", frac=mf / MFMA_PEAK_TFLOPS[dt])
+        else:
+            r.update(bound="hbm", achieved=hb, peak=HBM_PEAK_GBS, unit="GB/s", frac=hb / HBM_PEAK_GBS)
     return r
 
 

@@ -47,6 +47,17 @@ def test_persistent_bytes_hand_value(bench):
     assert bench.algorithmic_bytes("no_such_kernel", d) is None
 
 
+def test_step_model_hand_values(bench):
+    """One learning step of 784 (800) -> 6400 at B = 256:
+    bytes 2 * 800 * 6400 * 4 + 2 * 256 * 6400 * 14 + 2 * 256 * 800 * 4
+          = 40 960 000 + 45 875 200 + 1 638 400 = 88 473 600;
+    flops 6 * 256 * 800 * 6400 = 7 864 320 000."""
+    from paper_1909_02549_amd import inputs
+    d = bench.dims(inputs.dc_config(6400), 256)
+    assert bench.step_bytes(d) == 88_473_600
+    assert bench.step_flops(d) == 7_864_320_000
+
+
 def test_roofline_fractions_and_bound(bench):
     from paper_1909_02549_amd import inputs
     d = bench.dims(inputs.dc_config(6400), 256)
@@ -57,8 +68,15 @@ def test_roofline_fractions_and_bound(bench):
     assert r["alu"]["frac"] == pytest.approx(bench.alu_ops("fused_step", d) / 100e-6 / 1e12 / 157.3)
     hbm = per / 100e-6 / 1e9 / 8000.0
     assert r["alu"]["hbm_frac"] == pytest.approx(hbm)
-    assert r["frac"] == pytest.approx(max(hbm, r["alu"]["frac"]))
-    assert r["bound"] == ("alu" if r["alu"]["frac"] > hbm else "hbm")
+    # the kernel's own models, then the whole-step HBM figure as the bound
+    assert r["kernel_model"]["frac"] == pytest.approx(max(hbm, r["alu"]["frac"]))
+    assert r["bound"] == "hbm" and r["frac"] == pytest.approx(88_473_600 / 100e-6 / 1e9 / 8000.0)
+    # persistent: one launch of 350 steps in 10 ms, graded on the step's
+    # dense-equivalent flops against the BF16 matrix-core peak
+    q = bench.kernel_roofline("persistent", d, "fp32", 1, 10.0, 350.0)
+    assert q["bound"] == "mfma" and q["peak"] == 2500.0
+    assert q["frac"] == pytest.approx(350 * 7_864_320_000 / 10e-3 / 1e12 / 2500.0)
+    assert q["step_model"]["hbm_frac"] == pytest.approx(350 * 88_473_600 / 10e-3 / 1e9 / 8000.0)
     m = bench.kernel_roofline("mfma_front", d, "fp32", 1, 0.01, 1.0)
     tf = 2.0 * 256 * 784 * 6400 / 10e-6 / 1e12
     assert m["mfma"]["achieved"] == pytest.approx(tf)
