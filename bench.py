@@ -466,8 +466,8 @@ def main():
                     help="also run a device copy of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is in "
-              "DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the batch or the columns "
+              "would be sharded across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.sweep:
