@@ -7,7 +7,9 @@ style network with STDP on (Poisson encoding, contraction, inhibition, neuron
 updates, traces, batch-reduced weight change, clamp, column normalisation,
 threshold update), on the execution path the library's autotuner picks.
 Inputs (images, ids, weights) are resident in HBM before the timed region.
-value = B * T * steps / elapsed seconds (sample-steps/s).
+value = B * T * steps / elapsed seconds (sample-steps/s) over the timed trials
+(default: 3 warm-up trials, then 10 timed ones); `trials` adds the median and
+the mean +- std of the per-trial times (HIP events between the trials).
 
 Also reported on the same JSON line:
   paths         the same workload on each execution path (plain per-step
@@ -253,12 +255,18 @@ def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
     net.snn_sync()
     if profile:
         net.snn_profile_enable(True)
+    # one HIP event between consecutive trials on the handle's stream (torch's
+    # current stream when the handle was made) gives the per-trial times
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         net.snn_run(imgs_d, ids_d, T, reset=True, record=())
+        ev[k + 1].record()
     torch.cuda.synchronize()
     net.snn_sync()
     el = time.perf_counter() - t0
+    time_path.trial_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     prof = {}
     if profile:
         prof = net.snn_profile_get()
@@ -447,8 +455,8 @@ def sweep(name: str, trials: int) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed trials (one trial = T clock steps)")
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10, help="timed trials (one trial = T clock steps)")
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dc6400")
     ap.add_argument("--path", default="auto", choices=["plain", "fused", "persistent", "mfma", "auto"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
@@ -504,6 +512,10 @@ def main():
     net = Net(cfg, max_batch=B, path=args.path, precision=args.precision)
     net.snn_set_weights(W)
     el, prof = time_path(net, imgs_d, ids_d, T, args.steps, args.warmup, profile=True)
+    trial_ms = np.array(time_path.trial_ms)
+    trials = {"n": int(len(trial_ms)), "median_ms": float(np.median(trial_ms)), "mean_ms": float(trial_ms.mean()),
+              "std_ms": float(trial_ms.std(ddof=1)) if len(trial_ms) > 1 else 0.0,
+              "median_value": B * T / (float(np.median(trial_ms)) * 1e-3), "trial_ms": [float(x) for x in trial_ms]}
     used_path = net.snn_last_path()
     value = B * T * args.steps / el
 
@@ -561,7 +573,8 @@ def main():
                                f"{['sum', 'mean', 'max'][cfg['reduce']]}, synthetic stroke images",
                    "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},
-        "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving, "conversion": conversion,
+        "trials": trials, "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
+        "conversion": conversion,
         "vs_plain_path": (value / paths["plain"]["value"]) if "plain" in paths else None,
         "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1),
                         **({"roofline": kroofs[k]} if k in kroofs else {})} for k, v in prof.items()},
