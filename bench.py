@@ -220,14 +220,27 @@ def measured_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0, single_s: float = 6.0) -> dict:
     """Time the FP64 oracle (test infrastructure) on the first steps of one
-    trial of the same workload."""
+    trial of the same workload: with all host threads, then single-threaded
+    on fewer steps."""
     from oracle import build as obuild
     from oracle import oracle as omod
     if not os.path.exists(omod.LIB_PATH):
         obuild.build()
     cfg, B = wl["cfg"], wl["B"]
+    lib = omod.lib()
+    cores = int(lib.orc_threads())
     net = omod.OracleNet(cfg, W.astype(np.float64))
     t0 = time.perf_counter()
     net.run(imgs, ids, 2, record=())
@@ -237,9 +250,21 @@ def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0) -> dict:
     t0 = time.perf_counter()
     net.run(imgs, ids, steps, record=())
     el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": B * steps / el, "unit": "sample·steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {steps} of the {wl['T']} steps of one B={B} trial, FP64, {el:.1f} s"}
+    res = {"value": B * steps / el, "unit": "sample·steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {steps} of the {wl['T']} steps of one B={B} trial, FP64, {el:.1f} s",
+           "cpu": cpu_model()}
+    # single-threaded, on as many steps as fit single_s at the measured rate
+    s1 = int(max(1, min(steps, single_s / max(el / steps * cores, 1e-3))))
+    lib.orc_set_threads(1)
+    try:
+        net = omod.OracleNet(cfg, W.astype(np.float64))
+        t0 = time.perf_counter()
+        net.run(imgs, ids, s1, record=())
+        e1 = time.perf_counter() - t0
+    finally:
+        lib.orc_set_threads(cores)
+    res["single_thread"] = {"value": B * s1 / e1, "sample": f"first {s1} steps, {e1:.1f} s"}
+    return res
 
 
 def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):

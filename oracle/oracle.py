@@ -58,6 +58,10 @@ def lib():
         _lib.orc_run.restype = C.c_int
         _lib.orc_quantize.argtypes = [C.c_double, C.c_int]
         _lib.orc_quantize.restype = C.c_double
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_set_threads.restype = None
+        _lib.orc_threads.argtypes = []
+        _lib.orc_threads.restype = C.c_int
     return _lib
 
 

@@ -35,6 +35,7 @@
  * elements, so every sum keeps one fixed order.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -74,6 +75,11 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 /* The 32-bit uniform that decides input i of sample `id` at local step t:
  * counter (i / 8, t, id, 0), key (seed, 0); the four 64-bit outputs are read
  * as eight 32-bit words, low half first. */
+/* Host threads the parallel loops use (timing only; results do not depend
+ * on it: every parallel loop writes disjoint outputs). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_threads(void) { return omp_get_max_threads(); }
+
 uint32_t orc_uniform32(uint64_t seed, uint64_t id, uint64_t t, uint64_t i)
 {
     uint64_t ctr[4] = {i / 8, t, id, 0};
