@@ -427,7 +427,15 @@ def sweep(name: str, trials: int) -> dict:
            B = 1 .. 4096: per-step launches with and without graph replay,
            the matrix-core route, the fused and the persistent kernel;
     dc400  784 -> 400/400, T=250, STDP on, over B = 16 .. 1024, each batch
-           reduction and operand precision on the autotuned path."""
+           reduction and operand precision on the autotuned path;
+    serve  the serving workload at 2000, 5000, 10000 and 20000 requests/s
+           (`trials` x 1000 requests each)."""
+    if name == "serve":
+        rows = []
+        for rate in (2000.0, 5000.0, 10000.0, 20000.0):
+            rows.append(serving_run(1000 * trials, rate, max_slots=1024, chunk=25))
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        return {"name": name, "rows": rows}
     import torch
     from paper_1909_02549_amd import inputs
     from paper_1909_02549_amd.snn import Net, SnnError
@@ -493,7 +501,7 @@ def main():
     ap.add_argument("--no-conversion", action="store_true", help="skip the converted IF network run")
     ap.add_argument("--conversion-only", action="store_true",
                     help="print only the converted IF network's measurement")
-    ap.add_argument("--sweep", choices=["scale", "dc400"], default=None,
+    ap.add_argument("--sweep", choices=["scale", "dc400", "serve"], default=None,
                     help="print a throughput sweep instead of the benchmark line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (profiler calibration)")
