@@ -176,7 +176,8 @@ snn_status snn_set_theta(snn_net *net, const double *theta_host, size_t n);
 snn_status snn_get_theta(snn_net *net, double *theta_host, size_t n);
 
 /* Select the batch reduction of weight and threshold updates (Reduction
- * methods section).  Takes effect at the next step. */
+ * methods section), a snn_reduce value.  Takes effect at the next step.
+ * SNN_EINVAL for a NULL handle or a mode outside snn_reduce. */
 snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
 
 /* Select the execution path (snn_path) and the operand form of the
