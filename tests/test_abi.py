@@ -109,3 +109,31 @@ def test_ifnet_null_handle_calls(lib):
     assert lib.snn_ifnet_run(None, None, 1, 1, None) == -1
     assert lib.snn_ifnet_sync(None) == -1
     assert lib.snn_ifnet_set_layer(None, 1, None, 0, None, 0) == -1
+
+
+def test_product_package_never_uses_the_oracle():
+    """The HIP path has no CPU fallback: no module of the package imports the
+    oracle (test infrastructure), and the oracle does not import the package's
+    binding."""
+    pkg = os.path.join(ROOT, "paper_1909_02549_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            src = open(os.path.join(pkg, name)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), name
+    for name in ("oracle.py", "ifnet.py"):
+        src = open(os.path.join(ROOT, "oracle", name)).read()
+        assert "paper_1909_02549_amd.snn" not in src and "libsnn" not in src, name
+
+
+def test_handles_raise_without_gpu_or_library(monkeypatch):
+    torch = pytest.importorskip("torch")
+    from paper_1909_02549_amd import inputs, snn
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            snn.Net(inputs.dc_config(100), max_batch=4)
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            snn.IFNet((784, 256, 128, 10))
+    monkeypatch.setattr(snn, "_lib", None)
+    monkeypatch.setattr(snn, "LIB_PATH", os.path.join(ROOT, "no_such_libsnn.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        snn.load_library()
