@@ -35,9 +35,10 @@ namespace {
 constexpr int kMaxH1 = 256, kMaxH2 = 128, kMaxOut = 32;
 constexpr int kMaxK2 = kMaxH1 / 16;  // 16-deep chunks of the h1 -> h2 contraction
 constexpr int kNetThreads = 768;     // 12 waves: 4 chunk waves (h2), 8 h1 waves (one h1 tile each)
-// Spike words of a 32-neuron tile in LDS: the ballot of C row r holds the
-// words of samples 8 (r / 4) + r % 4 (low half) and that + 4 (high half) and
-// is stored whole at word 2r, so sample S's word is at ballot_slot(S).
+// Spike words of a 32-neuron tile: the ballot of C row r holds the words of
+// samples 8 (r / 4) + r % 4 (low half) and that + 4 (high half); stored whole
+// at word 2r, sample S's word is at ballot_slot(S) (and is half
+// ballot_slot(S) % 2 of the ballot of row ballot_slot(S) / 2).
 __device__ __forceinline__ int ballot_slot(int S) { return 8 * (S >> 3) + 2 * (S & 3) + ((S >> 2) & 1); }
 
 struct IfDims {
@@ -186,11 +187,11 @@ struct IfNetArgs {
 };
 
 // LDS of k_if_net: the h2 operand fragments of two steps' h1 spikes, the h2
-// partial sums of two steps (4 chunk groups), the h1 spike words (8 tiles)
-// and the h2 spike words (one tile).
+// partial sums of two steps (4 chunk groups) and two steps' h2 spike words
+// (one tile).
 constexpr size_t kAbufBytes = 2 * kMaxK2 * 64 * sizeof(uint4);
 constexpr size_t kPartBytes = 2 * 4 * 16 * 64 * sizeof(float);
-constexpr size_t kNetLds = kAbufBytes + kPartBytes + (8 + 2) * 32 * sizeof(uint32_t);
+constexpr size_t kNetLds = kAbufBytes + kPartBytes + 2 * 32 * sizeof(uint32_t);
 constexpr int kOutWave = 3;  // the chunk wave that runs the output layer
 
 // One workgroup per (32-sample tile, h2 tile y) runs all T steps as a
@@ -224,8 +225,7 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
     const bool lead = y == 0;  // the workgroup that records h1 outputs
     uint4 *abuf = lds_if;
     float *part = reinterpret_cast<float *>(reinterpret_cast<char *>(lds_if) + kAbufBytes);
-    uint32_t *mask1 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(part) + kPartBytes);
-    uint32_t *mask2 = mask1 + 8 * 32;  // two steps' words of the h2 tile
+    uint32_t *mask2 = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(part) + kPartBytes);  // two steps' h2 words
 
     // operand fragments of the chunks no h1 tile writes (c >= 2 n1t) stay zero
     const int nz = (kMaxK2 - 2 * d.n1t) * 64;
@@ -276,18 +276,15 @@ __global__ __launch_bounds__(kNetThreads) void k_if_net(IfNetArgs a)
                         if (s_ < a.B && col < d.h1) a.o.v_h1[((size_t)t * a.B + s_) * d.h1 + col] = v1[r];
                     }
                 }
-                uint64_t *mq = reinterpret_cast<uint64_t *>(mask1 + 32 * q1);
-                if (lane == 0) {
+                // the word of sample S = l % 32 is half h(S) of the ballot of
+                // row r(S) (slot(S) = 2 r(S) + h(S)): picked per lane from the
+                // wave-uniform ballots (lane: sample l % 32, units
+                // 8 (l / 32)..+7 of each chunk); then the h2 operand fragments
+                // of chunks 2 q1 and 2 q1 + 1 are published
+                uint64_t sel = 0;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) mq[r] = mb[r];
-                }
-                // read the tile's words back per sample (lane: sample l % 32,
-                // units 8 (l / 32)..+7 of each chunk) and publish the h2
-                // operand fragments of chunks 2 q1 and 2 q1 + 1
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const uint32_t word = mask1[32 * q1 + slot];
+                for (int r = 0; r < 16; ++r) sel = (slot >> 1) == r ? mb[r] : sel;
+                const uint32_t word = (slot & 1) ? (uint32_t)(sel >> 32) : (uint32_t)sel;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     ab[(2 * q1 + j) * 64 + lane] = ones_bf16((word >> (16 * j + 8 * (lane >> 5))) & 0xFFu);
