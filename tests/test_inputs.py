@@ -31,3 +31,18 @@ def test_weights_and_arrivals():
     assert abs(np.diff(t).mean() - 1 / 5000.0) < 1e-5
     T = inputs.request_durations(3000)
     assert set(np.unique(T)) == {100, 250, 500}
+
+
+def test_conversion_mlp_is_seeded_and_shaped():
+    """The converted network's weights depend only on the seed (and the
+    calibration images); shapes and dtypes follow the layer sizes."""
+    from paper_1909_02549_amd.inputs import conversion_mlp, stroke_images
+    calib = stroke_images(32, 5, 0.19)
+    a = conversion_mlp((784, 64, 32, 10), 3, calib_images=calib)
+    b = conversion_mlp((784, 64, 32, 10), 3, calib_images=calib)
+    c = conversion_mlp((784, 64, 32, 10), 4, calib_images=calib)
+    assert [w.shape for w, _ in a] == [(784, 64), (64, 32), (32, 10)]
+    assert [bb.shape for _, bb in a] == [(64,), (32,), (10,)]
+    assert all(w.dtype == np.float32 and bb.dtype == np.float32 for w, bb in a)
+    assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(a, b))
+    assert not np.array_equal(a[0][0], c[0][0])
