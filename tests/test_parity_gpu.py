@@ -243,3 +243,31 @@ def test_long_run_crosses_encoder_chunks(torch_cuda, oracle_mod, path):
     W = uniform_weights(784, 40, 0.0, 0.3, 4)
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(3, 77), 300, path=path)
     check_parity(g, ref)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_batch_equals_separate_runs_bit_exact(torch_cuda, path):
+    """Learning off: a batch of 8 gives each sample exactly the spikes and
+    voltages it gets when run alone (every sample's arithmetic is its own;
+    the encoder is keyed by sample id, not by batch slot)."""
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net
+    cfg = dc_config(100, learn=False)
+    imgs = stroke_images(8, 31, 0.19)
+    ids = sample_ids(8, 900)
+    W = inputs.column_scaled(uniform_weights(784, 100, 0.0, 0.3, 6), 78.4)
+    T = 60
+    net = Net(cfg, max_batch=8, path=path)
+    net.snn_set_weights(W)
+    full = net.snn_run(to_dev(torch, imgs), to_dev(torch, ids.astype(np.int64)), T, record=("exc", "v_exc"))
+    torch.cuda.synchronize()
+    fe, fv = full["exc"].cpu().numpy(), full["v_exc"].cpu().numpy()
+    assert net.snn_last_path() == path
+    assert fe.any()
+    for b in range(8):
+        one = net.snn_run(to_dev(torch, imgs[b:b + 1]), to_dev(torch, ids[b:b + 1].astype(np.int64)), T,
+                          record=("exc", "v_exc"))
+        torch.cuda.synchronize()
+        assert np.array_equal(one["exc"].cpu().numpy()[:, 0], fe[:, b]), f"sample {b}: spikes differ"
+        assert np.array_equal(one["v_exc"].cpu().numpy()[:, 0], fv[:, b]), f"sample {b}: voltages differ"
+    net.close()
