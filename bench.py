@@ -347,6 +347,48 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
 FP32_MATRIX_PEAK_TFLOPS = 157.3
 
 
+def measured_peaks() -> dict:
+    """What this GPU reaches on plain library work, as context for the
+    published peaks the rooflines use: a 1 GiB device-to-device copy (read +
+    write bytes) and a 8192^3 bfloat16 matrix product (torch / the vendor
+    BLAS), each timed with HIP events over 10 repetitions after 3 warm-ups."""
+    import torch
+    dev = torch.device("cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    n = 256 * 2 ** 20
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * n * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    m = 8192
+    x = torch.randn(m, m, dtype=torch.bfloat16, device=dev)
+    y = torch.randn(m, m, dtype=torch.bfloat16, device=dev)
+    for _ in range(3):
+        z = torch.matmul(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(10):
+        z = torch.matmul(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    gemm_tf = 2.0 * m ** 3 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y, z
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbs": copy_gbs, "hbm_copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+            "bf16_gemm_tflops": gemm_tf, "bf16_gemm_frac_of_peak": gemm_tf / MFMA_PEAK_TFLOPS["bf16"]}
+
+
 def conversion_flops(sizes, B: int, T: int) -> float:
     """Algorithmic flops of one converted-network run: the analog input's
     contraction once, the two spike contractions every step."""
@@ -505,6 +547,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-conversion", action="store_true", help="skip the converted IF network run")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and GEMM peak measurements")
     ap.add_argument("--conversion-only", action="store_true",
                     help="print only the converted IF network's measurement")
     ap.add_argument("--sweep", choices=["scale", "dc400", "serve"], default=None,
@@ -599,6 +642,7 @@ def main():
         serving = serving_run(args.serve_requests, args.serve_rate, max_slots=1024, chunk=25)
 
     conversion = None if args.no_conversion else conversion_run(oracle=not args.no_cpu)
+    peaks = None if args.no_peaks else measured_peaks()
 
     cpu = None if args.no_cpu else cpu_baseline(wl, imgs, ids, W)
 
@@ -613,7 +657,7 @@ def main():
                    "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},
         "trials": trials, "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
-        "conversion": conversion,
+        "conversion": conversion, "measured_peaks": peaks,
         "vs_plain_path": (value / paths["plain"]["value"]) if "plain" in paths else None,
         "kernels": {k: {"launches": v[0], "avg_us": v[1] * 1e3 / max(v[0], 1),
                         **({"roofline": kroofs[k]} if k in kroofs else {})} for k, v in prof.items()},
