@@ -124,8 +124,7 @@ typedef struct {
     uint32_t max_batch;            /* largest batch snn_run will accept             */
     uint32_t norm_per_run;         /* 1: normalise once, after the last step of
                                       each snn_run / snn_run_spikes call (a
-                                      cheaper variant; PLAIN and MFMA paths,
-                                      FUSED and PERSISTENT fall back to PLAIN);
+                                      cheaper variant, on every path);
                                       0: after every learning step            */
     uint64_t hbm_budget_bytes;     /* 0: no limit                                   */
 } snn_config;

@@ -77,6 +77,7 @@ struct ChunkPtrs {
     int has_next;          // inputs of step `steps` are encoded (x_pre ahead)
     int mod0;              // s % 3 of the first step
     int k0;                // output index of the first step
+    int norm_from;         // first step (within the chunk) that normalises
 };
 
 // Cross-workgroup state of one persistent launch.
@@ -753,8 +754,10 @@ __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, i
 }
 
 // Phase C3: FP64 column sums of the updated block, the pending
-// normalisation scale, the threshold update.  Two workgroup barriers.
-__device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, int tid, int nt)
+// normalisation scale (norm / column sum; 1 when norm is 0, as on the steps
+// before the last of a run under per-run normalisation), the threshold
+// update.  Two workgroup barriers.
+__device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, double norm, int tid, int nt)
 {
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     double cs = 0.0;
@@ -765,7 +768,7 @@ __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S,
     if (tid < 32) {
         double c = 0.0;
         for (int r = 0; r < nrg; ++r) c += S.part[r * 32 + tid];
-        S.scale[tid] = (p.norm > 0.0 && c > 0.0 && tid < p.jb) ? p.norm / c : 1.0;
+        S.scale[tid] = (norm > 0.0 && c > 0.0 && tid < p.jb) ? norm / c : 1.0;
         S.scalef[tid] = (float)S.scale[tid];
         if (p.adaptive && tid < p.jb) {
             int cnt = 0;

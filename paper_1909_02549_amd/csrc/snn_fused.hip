@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     plasticity_all<false, 16, true, kListHead, PREC == PREC_FP32>(p, S, s.lt, s.ct, s.ord_in, s.xpre, tid, nt,
                                                                  PREC, 0);
     __syncthreads();
-    colsums_theta(p, S, tid, nt);
+    colsums_theta(p, S, p.norm, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);
     store_block(p, S, Wg, a.theta, g, tid, nt);
 }

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
                                               ch.ct + (size_t)k * p.n_in_pad, ch.ord_in + (size_t)k * p.n_in_pad,
                                               xpre, tid, nt, PREC, PREC);
             __syncthreads();
-            colsums_theta(p, S, tid, nt);
+            colsums_theta(p, S, k >= ch.norm_from ? p.norm : 0.0, tid, nt);
             if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);
         }
         if (k + 1 < ch.steps) {

@@ -733,6 +733,9 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     s.Cprev = C + (size_t)((gstep + 2) % 3) * p.Bs;
     s.Cnext = C + (size_t)((gstep + 1) % 3) * p.Bs;
     s.k = k;
+    // per-run normalisation: only the run's last step normalises
+    Params pp = p;
+    if (cfg.norm_per_run && (uint32_t)k + 1 != run_T) pp.norm = 0.0;
     FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
     const size_t lds = fused_lds_bytes(p);
     const void *fn = p.prec == PREC_FP32   ? (const void *)k_fused_step<PREC_FP32>
@@ -744,11 +747,11 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     }
     const dim3 grid((unsigned)p.nblk);
     if (p.prec == PREC_FP32)
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP32>, grid, dim3(kFusedThreads), lds, p, a, s);
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP32>, grid, dim3(kFusedThreads), lds, pp, a, s);
     else if (p.prec == PREC_BF16)
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_BF16>, grid, dim3(kFusedThreads), lds, p, a, s);
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_BF16>, grid, dim3(kFusedThreads), lds, pp, a, s);
     else
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP8>, grid, dim3(kFusedThreads), lds, p, a, s);
+        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP8>, grid, dim3(kFusedThreads), lds, pp, a, s);
     HIP_TRY(hipGetLastError());
     ++gstep;
     return SNN_OK;
@@ -787,6 +790,9 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     c.has_next = has_next ? 1 : 0;
     c.mod0 = (int)(gstep % 3);
     c.k0 = k0;
+    // every step normalises, or under per-run normalisation only the last
+    // step of the run (none if the run continues in a later chunk)
+    c.norm_from = !cfg.norm_per_run ? 0 : (uint32_t)(k0 + steps) == run_T ? steps - 1 : steps;
     h->sy = PersistSync{bar, err};
     HIP_TRY(hipMemcpyAsync(d, h, sizeof(PersistArgs), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(pargs_ev[slot], stream));
@@ -845,10 +851,9 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
-    // the signed max reduction and per-run normalisation are implemented by
-    // the plasticity kernels of the plain and MFMA routes only
-    if (p.learn && (p.reduce == RED_MAX_SIGNED || (cfg.norm_per_run && p.norm > 0.0)) &&
-        (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
+    // the signed max reduction is implemented by the plasticity kernels of
+    // the plain and MFMA routes only
+    if (p.learn && p.reduce == RED_MAX_SIGNED && (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
         path = SNN_PATH_PLAIN;
     run_T = T;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;

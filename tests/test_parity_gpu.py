@@ -160,16 +160,15 @@ def test_signed_max_reduction_parity(torch_cuda, oracle_mod, path):
 @pytest.mark.parametrize("path", PATHS + ["auto"])
 def test_per_run_normalisation_parity(torch_cuda, oracle_mod, path):
     """Columns normalised once, after the run's last step (the cheaper
-    variant): the plasticity kernels of the plain and MFMA routes; the fused
-    and persistent paths fall back to the plain path.  Two runs in a row, the
-    second continuing the first, so that each call normalises at its own end."""
+    variant), on every path.  Two runs in a row, the second continuing the
+    first, so that each call normalises at its own end."""
     from paper_1909_02549_amd.snn import Net
     cfg = dc_config(100, norm_per_run=1)
     imgs = stroke_images(8, 4, 0.19)
     W = uniform_weights(784, 100, 0.0, 0.3, 5)
     ids = sample_ids(8, 30)
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, ids, 40, path=path)
-    assert g["path"] == (path if path in ("plain", "mfma") else "plain") or (path == "auto" and g["path"] == "mfma")
+    assert path == "auto" or g["path"] == path
     assert ref["exc"].sum() > 50
     check_parity(g, ref)
     np.testing.assert_allclose(g["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
@@ -189,6 +188,23 @@ def test_per_run_normalisation_parity(torch_cuda, oracle_mod, path):
     np.testing.assert_allclose(gw.astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
     err = np.abs(gw - orc.W)
     assert (err <= W_RTOL * np.abs(orc.W) + W_ATOL).mean() > 0.99
+
+
+@pytest.mark.parametrize("path", ["fused", "persistent"])
+def test_per_run_normalisation_across_chunks(torch_cuda, oracle_mod, path):
+    """A run longer than one encoder chunk (512 steps, two persistent
+    launches): the columns are normalised after the run's last step only, not
+    at the end of the first chunk."""
+    cfg = dc_config(100, norm_per_run=1)
+    imgs = stroke_images(4, 6, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 8)
+    T = 520
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(4, 40), T, path=path)
+    assert g["path"] == path
+    assert ref["exc"].sum() > 50
+    t_div = check_parity(g, ref)
+    assert t_div > 512, f"rasters diverged at step {t_div}, before the chunk boundary"
+    np.testing.assert_allclose(g["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
 
 
 @pytest.mark.parametrize("path", PATHS)
