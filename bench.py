@@ -541,6 +541,8 @@ def main():
     ap.add_argument("--workload", default="dc6400")
     ap.add_argument("--path", default="auto", choices=["plain", "fused", "persistent", "mfma", "auto"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--norm-per-run", action="store_true",
+                    help="normalise the columns once per trial instead of after every step")
     ap.add_argument("--no-paths", action="store_true", help="skip the per-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -573,6 +575,8 @@ def main():
 
     wl = inputs.workload(args.workload)
     cfg, B, T = wl["cfg"], wl["B"], wl["T"]
+    if args.norm_per_run:
+        cfg = dict(cfg, norm_per_run=1)
     imgs = inputs.stroke_images(B, 1234, wl["density"]) if wl["density"] is not None else None
     ids = inputs.sample_ids(B)
     if "wlo" in wl:
@@ -644,7 +648,7 @@ def main():
     conversion = None if args.no_conversion else conversion_run(oracle=not args.no_cpu)
     peaks = None if args.no_peaks else measured_peaks()
 
-    cpu = None if args.no_cpu else cpu_baseline(wl, imgs, ids, W)
+    cpu = None if args.no_cpu else cpu_baseline(dict(wl, cfg=cfg), imgs, ids, W)
 
     line = {
         "metric": METRIC, "value": value, "unit": "sample·steps/s", "n_gpus": 1,
@@ -653,7 +657,8 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['n_in']}->{cfg['n_exc']}/{cfg['n_inh']} Diehl&Cook, "
                                f"B={B}, T={T}, STDP {'on' if cfg['learn'] else 'off'}, reduce="
-                               f"{['sum', 'mean', 'max'][cfg['reduce']]}, synthetic stroke images",
+                               f"{['sum', 'mean', 'max', 'max_signed'][cfg['reduce']]}"
+                               f"{', normalisation per trial' if cfg.get('norm_per_run') else ''}, synthetic stroke images",
                    "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},
         "trials": trials, "roofline": roof, "cpu_baseline": cpu, "paths": paths, "serving": serving,
