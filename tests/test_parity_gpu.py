@@ -37,14 +37,17 @@ def to_dev(torch, a, dtype=None):
 
 
 def run_both(torch, oracle_mod, cfg, W, imgs, ids, T, path="plain", record=("in", "exc", "inh", "v_exc", "counts"),
-             reduce=None, forced=None, precision="fp32", oracle_precision=None):
+             reduce=None, forced=None, precision="fp32", oracle_precision=None, before=None):
     """Run the HIP path and the oracle on the same inputs.  The oracle takes
     the same operand form as the GPU unless ``oracle_precision`` says
-    otherwise.  Returns (gpu, oracle, path the GPU ran)."""
+    otherwise; ``before(net)``, if given, is called on the handle before the
+    run.  Returns (gpu, oracle, path the GPU ran)."""
     from paper_1909_02549_amd.snn import Net, pack_bits, unpack_bits
     B = len(ids)
     net = Net(cfg, max_batch=B, path=path, precision=precision)
     net.snn_set_weights(W)
+    if before is not None:
+        before(net)
     if forced is not None:
         bits = pack_bits(forced.transpose(1, 0, 2))  # T, B, words
         out = net.snn_run_spikes(to_dev(torch, bits.view(np.int32)), T, record=record)
@@ -205,6 +208,53 @@ def test_per_run_normalisation_across_chunks(torch_cuda, oracle_mod, path):
     t_div = check_parity(g, ref)
     assert t_div > 512, f"rasters diverged at step {t_div}, before the chunk boundary"
     np.testing.assert_allclose(g["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_run_errors_leave_the_handle_usable(torch_cuda, oracle_mod, path):
+    """Invalid calls return an error without touching the state: a run on the
+    same handle afterwards still matches the oracle from the initial state."""
+    from paper_1909_02549_amd.snn import SnnError
+    torch = torch_cuda
+    cfg = dc_config(100)
+    imgs = stroke_images(4, 2, 0.19)
+    ids = sample_ids(4, 50)
+    W = uniform_weights(784, 100, 0.0, 0.3, 2)
+    d_imgs, d_ids = to_dev(torch, imgs), to_dev(torch, ids.astype(np.int64))
+
+    def invalid_calls(net):
+        with pytest.raises(SnnError, match="EINVAL"):
+            net.snn_run(d_imgs, d_ids, 0)
+        with pytest.raises(SnnError, match="ENOMEM"):  # more samples than max_batch
+            net.snn_run(to_dev(torch, stroke_images(5, 2, 0.19)), to_dev(torch, sample_ids(5).astype(np.int64)), 10)
+        assert net.lib.snn_run(net.h, d_imgs.data_ptr(), None, 4, 10, 1, None) == -1  # no sample ids
+        assert net.lib.snn_run(net.h, None, d_ids.data_ptr(), 4, 10, 1, None) == -1  # no images, no uniform rate
+        assert net.lib.snn_run(net.h, d_imgs.data_ptr(), d_ids.data_ptr(), 0, 10, 1, None) == -1
+        assert net.lib.snn_run_spikes(net.h, None, 4, 10, 1, None) == -1
+
+    g, ref = run_both(torch, oracle_mod, cfg, W, imgs, ids, 40, path=path, before=invalid_calls)
+    assert ref["exc"].sum() > 20
+    assert check_parity(g, ref) == 40
+    assert np.array_equal(g["counts"], ref["counts"].astype(np.int64))
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("level", [0, 255])
+def test_blank_and_saturated_images(torch_cuda, oracle_mod, path, level):
+    """Degenerate inputs with learning on: blank images give no input or
+    output spike, so the weights change only by the per-step normalisation;
+    saturated images drive every input at the highest rate (B = 3, ragged
+    batch word)."""
+    cfg = dc_config(100)
+    imgs = np.full((3, 784), level, np.uint8)
+    W = uniform_weights(784, 100, 0.0, 0.3, 3)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(3, 60), 30, path=path)
+    if level == 0:
+        assert ref["in"].sum() == 0 and ref["exc"].sum() == 0
+    else:
+        assert ref["in"].mean() > 0.03
+    assert check_parity(g, ref) == 30
+    assert np.array_equal(g["counts"], ref["counts"].astype(np.int64))
 
 
 @pytest.mark.parametrize("path", PATHS)
