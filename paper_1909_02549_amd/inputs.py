@@ -208,6 +208,9 @@ def workload(name: str) -> dict:
     scale   1000 uniform-20Hz inputs -> 1000 LIF, no learning, T=1000
     dc400   784->400/400, T=250, learning, reduction sum/mean/max
     dc6400  784->6400/6400, B=256, T=350, learning, 10-30 % nonzero images
+    shard8  784->800/800, otherwise as dc6400: the per-GPU column share of
+            dc6400 split over 8 GPUs (its own inhibition only: the count
+            exchange between shards is not part of it)
     serve   frozen 784->1600/1600 inference, T in {100,250,500}
     conv    converted IF network 784-256-128-10, B=1024, T=10, 10000 images
     """
@@ -219,6 +222,8 @@ def workload(name: str) -> dict:
         return dict(cfg=dc_config(400), B=64, T=250, density=0.19, wlo=0.0, whi=0.3)
     if name == "dc6400":
         return dict(cfg=dc_config(6400), B=256, T=350, density=(0.10, 0.30), wlo=0.0, whi=0.3)
+    if name == "shard8":
+        return dict(cfg=dc_config(800), B=256, T=350, density=(0.10, 0.30), wlo=0.0, whi=0.3)
     if name == "serve":
         return dict(cfg=dc_config(1600, learn=False), B=4096, T=None, density=0.19, wlo=0.0, whi=0.3)
     if name == "conv":
