@@ -756,18 +756,40 @@ __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, i
 // Phase C3: FP64 column sums of the updated block, the pending
 // normalisation scale (norm / column sum; 1 when norm is 0, as on the steps
 // before the last of a run under per-run normalisation), the threshold
-// update.  Two workgroup barriers.
+// update.  Two workgroup barriers.  Both sums issue four LDS loads before
+// their additions (a loop of one load and one dependent add per row would
+// pay the LDS latency on every row); the order of the additions is the
+// row order either way.
 __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, double norm, int tid, int nt)
 {
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
     double cs = 0.0;
-    if (jj < p.jb)
-        for (int i = rg; i < p.n_in; i += nrg) cs += (double)S.W[i * p.ls + jj];
+    if (jj < p.jb) {
+        int i = rg;
+        for (; i + 3 * nrg < p.n_in; i += 4 * nrg) {
+            const float w0 = S.W[i * p.ls + jj], w1 = S.W[(i + nrg) * p.ls + jj];
+            const float w2 = S.W[(i + 2 * nrg) * p.ls + jj], w3 = S.W[(i + 3 * nrg) * p.ls + jj];
+            cs += (double)w0;
+            cs += (double)w1;
+            cs += (double)w2;
+            cs += (double)w3;
+        }
+        for (; i < p.n_in; i += nrg) cs += (double)S.W[i * p.ls + jj];
+    }
     S.part[rg * 32 + jj] = cs;
     __syncthreads();
     if (tid < 32) {
         double c = 0.0;
-        for (int r = 0; r < nrg; ++r) c += S.part[r * 32 + tid];
+        int r = 0;
+        for (; r + 3 < nrg; r += 4) {
+            const double q0 = S.part[r * 32 + tid], q1 = S.part[(r + 1) * 32 + tid];
+            const double q2 = S.part[(r + 2) * 32 + tid], q3 = S.part[(r + 3) * 32 + tid];
+            c += q0;
+            c += q1;
+            c += q2;
+            c += q3;
+        }
+        for (; r < nrg; ++r) c += S.part[r * 32 + tid];
         S.scale[tid] = (norm > 0.0 && c > 0.0 && tid < p.jb) ? norm / c : 1.0;
         S.scalef[tid] = (float)S.scale[tid];
         if (p.adaptive && tid < p.jb) {
