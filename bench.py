@@ -5,25 +5,28 @@ One bench step is one episodic trial of the whole hot path: ``snn_run`` of
 B = 256 samples for T = 350 clock steps of the 784 -> 6400/6400 Diehl & Cook
 style network with STDP on (Poisson encoding, contraction, inhibition, neuron
 updates, traces, batch-reduced weight change, clamp, column normalisation,
-threshold update), on the execution path the library's autotuner picks.
-Inputs (images, ids, weights) are resident in HBM before the timed region.
-value = B * T * steps / elapsed seconds (sample-steps/s) over the timed trials
-(default: 3 warm-up trials, then 10 timed ones); `trials` adds the median and
-the mean +- std of the per-trial times (HIP events between the trials).
+threshold update, spike-count readout), on the execution path the library's
+autotuner picks.  Inputs (images, ids, weights) and the readout buffer are
+resident in HBM before the timed region.  value = B * T * steps / elapsed
+seconds (sample-steps/s) over the timed trials (default: 3 warm-up trials,
+then 10 timed ones); `ms_per_step` is the time of one bench step (a trial),
+also given as `ms_per_trial`, and `us_per_clock_step` divides it by T;
+`trials` adds the median and the mean +- std of the per-trial times (HIP
+events between the trials).
 
 Also reported on the same JSON line:
   paths         the same workload on each execution path (plain per-step
                 launches, fused per-step kernel, persistent kernel);
   roofline      the dominant kernel's roofline from its average launch time
                 (HIP events on the library's stream over the timed region).
-                For the step kernels it uses the per-step work of the whole
-                learning step (step_bytes, step_flops): the fused kernel,
-                which streams weights and state through HBM, against the
-                8 TB/s HBM peak; the persistent kernel, which keeps them on
-                chip, against the BF16 matrix-core peak of the step's
-                dense-equivalent flops.  The kernel's own models (its HBM
-                bytes, its sparse vector operations against the 157.3 TFLOP/s
-                vector peak) are kept under kernel_model / alu;
+                For the step kernels it uses the per-step bytes of the whole
+                learning step (step_bytes: weights, per-neuron state and
+                presynaptic traces read and written, 88.5 MB) times the steps
+                one launch runs, against the 8 TB/s HBM peak.  The step's
+                dense-equivalent flops against the BF16 matrix-core peak
+                (step_model) and the kernel's own models (its HBM bytes, its
+                sparse vector operations against the 157.3 TFLOP/s vector
+                peak) are kept beside it as context;
   serving       frozen 784 -> 1600 network, Poisson arrivals, T in
                 {100, 250, 500}: p50 / p99 latency and sample-steps/s;
   conversion    the converted 784-256-128-10 IF network (ANN to SNN
@@ -188,23 +191,22 @@ def kernel_roofline(kname: str, d: dict, precision: str, launches: int, total_ms
         if afrac > r["frac"]:
             r.update(bound="alu", achieved=tf, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=afrac)
     if kname in ("persistent", "fused_step") and d["learn"]:
-        # the per-step figures of the whole learning step: the fused kernel
-        # streams the weights and state through HBM every step and is graded
-        # against the HBM roofline; the persistent kernel keeps them on chip,
-        # so it is graded against the matrix-core roofline of the step's
-        # dense-equivalent flops (BF16 peak; FP8 peak for the FP8 form)
+        # the per-step figure of the whole learning step (88.5 MB at 784 ->
+        # 6400, B = 256: weights, per-neuron state and presynaptic traces read
+        # and written) times the steps one launch runs, against the 8 TB/s HBM
+        # peak, for both step kernels; the dense-equivalent flops of the step
+        # (contraction and both STDP outer products) against the BF16
+        # matrix-core peak are kept as context under step_model
         sb, sf = step_bytes(d) * spl, step_flops(d) * spl
         hb, mf = sb / avg_s / 1e9, sf / avg_s / 1e12
         dt = "fp8" if precision == "fp8" else "bf16"
-        model = {"bytes_per_launch": sb, "hbm_achieved": hb, "hbm_frac": hb / HBM_PEAK_GBS,
-                 "flops_per_launch": sf, "mfma_achieved": mf, "mfma_peak": MFMA_PEAK_TFLOPS[dt],
-                 "mfma_frac": mf / MFMA_PEAK_TFLOPS[dt]}
+        model = {"bytes_per_step": step_bytes(d), "bytes_per_launch": sb, "hbm_achieved": hb,
+                 "hbm_frac": hb / HBM_PEAK_GBS, "flops_per_launch": sf, "mfma_achieved": mf,
+                 "mfma_peak": MFMA_PEAK_TFLOPS[dt], "mfma_frac": mf / MFMA_PEAK_TFLOPS[dt]}
         r["kernel_model"] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
         r["step_model"] = model
-        if kname == "persistent":
-            r.update(bound="mfma", achieved=mf, peak=MFMA_PEAK_TFLOPS[dt], unit="TFLOP/s", frac=mf / MFMA_PEAK_TFLOPS[dt])
-        else:
-            r.update(bound="hbm", achieved=hb, peak=HBM_PEAK_GBS, unit="GB/s", frac=hb / HBM_PEAK_GBS)
+        r.update(bound="hbm", achieved=hb, peak=HBM_PEAK_GBS, unit="GB/s", frac=hb / HBM_PEAK_GBS,
+                 algorithmic_bytes_per_launch=sb)
     return r
 
 
@@ -268,14 +270,16 @@ def cpu_baseline(wl, imgs, ids, W, target_s: float = 15.0, single_s: float = 6.0
 
 
 def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
-    """Wall time of `steps` episodic trials after `warmup` untimed ones.  With
-    `profile`, the library brackets each run of consecutive launches of one
-    kernel in the timed trials with a pair of HIP events on its stream (a few
-    events per trial, none between the launches of a run), which gives the
-    per-kernel times of the timed region itself."""
+    """Wall time of `steps` episodic trials after `warmup` untimed ones; every
+    trial records the readout (per-sample excitatory spike counts, into one
+    preallocated buffer).  With `profile`, the library brackets each run of
+    consecutive launches of one kernel in the timed trials with a pair of HIP
+    events on its stream (a few events per trial, none between the launches
+    of a run), which gives the per-kernel times of the timed region itself."""
     import torch
+    out = net.outputs(int(ids_d.shape[0]), T, ("counts",))
     for _ in range(warmup):
-        net.snn_run(imgs_d, ids_d, T, reset=True, record=())
+        net.snn_run(imgs_d, ids_d, T, reset=True, out=out)
     torch.cuda.synchronize()
     net.snn_sync()
     if profile:
@@ -286,7 +290,7 @@ def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
     t0 = time.perf_counter()
     ev[0].record()
     for k in range(steps):
-        net.snn_run(imgs_d, ids_d, T, reset=True, record=())
+        net.snn_run(imgs_d, ids_d, T, reset=True, out=out)
         ev[k + 1].record()
     torch.cuda.synchronize()
     net.snn_sync()
@@ -296,6 +300,7 @@ def time_path(net, imgs_d, ids_d, T, steps, warmup, profile=False):
     if profile:
         prof = net.snn_profile_get()
         net.snn_profile_enable(False)
+    time_path.spikes = int(out["counts"].sum().item())
     return el, prof
 
 
@@ -306,7 +311,7 @@ def serving_run(n_req: int, rate_hz: float, max_slots: int, chunk: int) -> dict:
     from paper_1909_02549_amd.snn import Net, Server
     wl = inputs.workload("serve")
     cfg = wl["cfg"]
-    W = inputs.column_scaled(inputs.uniform_weights(cfg["n_in"], cfg["n_exc"], wl["wlo"], wl["whi"], 0), 78.4)
+    W = inputs.frozen_weights(cfg["n_in"], cfg["n_exc"], 78.4, 0)
     net = Net(cfg, max_batch=1, path="auto")
     net.snn_set_weights(W)
     arrivals = inputs.poisson_arrivals(n_req, rate_hz, seed=1)
@@ -512,7 +517,7 @@ def sweep(name: str, trials: int) -> dict:
             net.snn_set_graphs(True)
         el, _ = time_path(net, imgs_d, ids_d, T, trials, 1)
         r = {"B": B, "path": path, "graphs": graphs, "used": net.snn_last_path(), "precision": precision,
-             "value": B * T * trials / el, "ms_per_step": el * 1e3 / (T * trials)}
+             "value": B * T * trials / el, "ms_per_clock_step": el * 1e3 / (T * trials)}
         if reduce is not None:
             r["reduce"] = reduce
         net.close()
@@ -626,7 +631,7 @@ def main():
             pnet.snn_set_weights(W)
             n = 1 if pth == "plain" else 2
             pel, pprof = time_path(pnet, imgs_d, ids_d, T, n, 1, profile=True)
-            entry = {"value": B * T * n / pel, "ms_per_step": pel * 1e3 / n, "used": pnet.snn_last_path()}
+            entry = {"value": B * T * n / pel, "ms_per_trial": pel * 1e3 / n, "used": pnet.snn_last_path()}
             entry["kernels"] = {}
             for kn, (ln, ms) in pprof.items():
                 kr = kernel_roofline(kn, d, args.precision, ln, ms, T * n / max(ln, 1))
@@ -653,6 +658,9 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "sample·steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "bench_step": f"one episodic trial: T={T} clock steps of all B={B} samples, spike-count readout recorded",
+        "ms_per_trial": el * 1e3 / args.steps, "us_per_clock_step": el * 1e6 / (args.steps * T),
+        "readout_spikes_last_trial": time_path.spikes,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['n_in']}->{cfg['n_exc']}/{cfg['n_inh']} Diehl&Cook, "

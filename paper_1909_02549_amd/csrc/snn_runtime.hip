@@ -435,6 +435,8 @@ extern "C" snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision
     net->path = path;
     net->precision = precision;
     net->p.prec = precision;
+    net->cfg.path = path;
+    net->cfg.precision = precision;
     net->graphs_invalidate();
     return SNN_OK;
 }
@@ -460,6 +462,9 @@ extern "C" snn_status snn_last_path(snn_net *net, int32_t *path)
 extern "C" snn_status snn_sync(snn_net *net)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
+    // with profiling on, the open span ends with the work queued so far (not
+    // with whatever the stream runs before the next launch or read-out)
+    if (net->prof) net->prof_close();
     HIP_TRY(hipStreamSynchronize(net->stream));
     return net->check_device_error();
 }

@@ -234,7 +234,12 @@ extern "C" snn_status snn_serve_create(snn_net *frozen, uint32_t max_slots, uint
         delete sv;
         return st;
     }
+    // the frozen handle's current execution path and operand form (either may
+    // have been changed with snn_set_path after it was created)
     sv->net->path = frozen->path;
+    sv->net->precision = frozen->precision;
+    sv->net->p.prec = frozen->p.prec;
+    sv->net->cfg.precision = frozen->precision;
     const snn::Params &fp = frozen->p;
     hipError_t e = hipSuccess;
     if (sv->net->p.jb != fp.jb) {

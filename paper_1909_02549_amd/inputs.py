@@ -93,12 +93,15 @@ def normal_weights(n_in: int, n_out: int, mean: float, std: float, seed: int) ->
     return rng.normal(mean, std, size=(n_in, n_out)).astype(np.float32)
 
 
-def column_scaled(w: np.ndarray, col_sum: float) -> np.ndarray:
-    """Input preparation for frozen serving weights: every column of ``w``
-    rescaled so that it sums to ``col_sum`` (float64 arithmetic, float32 out)."""
-    w64 = w.astype(np.float64)
-    c = w64.sum(axis=0)
-    return (w64 * (col_sum / c)[None, :]).astype(np.float32)
+def frozen_weights(n_in: int, n_out: int, col_sum: float, seed: int, alpha: float = 3.0) -> np.ndarray:
+    """Row-major (n_in, n_out) float32 weights of a frozen (inference) network
+    whose columns sum to ``col_sum``: each column is ``col_sum`` times a draw
+    from a symmetric Dirichlet distribution of concentration ``alpha``.  Its
+    entries have mean col_sum / n_in and coefficient of variation about
+    1 / sqrt(alpha) (0.58 at alpha = 3, that of U(0, 0.3) weights)."""
+    rng = np.random.default_rng([int(seed), 0x465A])
+    cols = rng.dirichlet(np.full(n_in, float(alpha)), size=n_out)
+    return (col_sum * cols.T).astype(np.float32)
 
 
 def conversion_mlp(sizes=(784, 256, 128, 10), seed: int = 0, calib_images: np.ndarray | None = None,

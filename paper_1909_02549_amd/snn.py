@@ -276,14 +276,24 @@ class Net:
                         _ptr(out.get("inh")), _ptr(out.get("v_exc")), _ptr(out.get("v_inh")))
         return out, o
 
-    def snn_run(self, images, ids, T: int, reset: bool = True, record=("counts",)):
+    def outputs(self, B: int, T: int, record=("counts",)) -> dict:
+        """Device output tensors for a run of B samples and T steps, to be
+        passed to snn_run(..., out=) (allocated once, reused by many runs)."""
+        return self._outputs(B, T, record)[0]
+
+    def snn_run(self, images, ids, T: int, reset: bool = True, record=("counts",), out=None):
         """images: cuda uint8 (B, n_in) or None (uniform rate); ids: cuda
-        int64 (B,).  Returns the requested device outputs (asynchronous)."""
+        int64 (B,).  Returns the requested device outputs (asynchronous);
+        with ``out`` (from ``outputs``) the run writes into those tensors."""
         B = int(ids.shape[0])
         assert ids.is_cuda and ids.dtype.itemsize == 8 and ids.is_contiguous()
         if images is not None:
             assert images.is_cuda and images.shape == (B, self.n_in) and images.is_contiguous()
-        out, o = self._outputs(B, T, record)
+        if out is None:
+            out, o = self._outputs(B, T, record)
+        else:
+            o = snn_outputs(_ptr(out.get("counts")), _ptr(out.get("in")), _ptr(out.get("exc")),
+                            _ptr(out.get("inh")), _ptr(out.get("v_exc")), _ptr(out.get("v_inh")))
         _check(self.lib.snn_run(self.h, _ptr(images), _ptr(ids), B, int(T),
                                 SNN_RUN_RESET if reset else 0, C.byref(o)))
         return out

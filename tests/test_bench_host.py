@@ -72,11 +72,13 @@ def test_roofline_fractions_and_bound(bench):
     assert r["kernel_model"]["frac"] == pytest.approx(max(hbm, r["alu"]["frac"]))
     assert r["bound"] == "hbm" and r["frac"] == pytest.approx(88_473_600 / 100e-6 / 1e9 / 8000.0)
     # persistent: one launch of 350 steps in 10 ms, graded on the step's
-    # dense-equivalent flops against the BF16 matrix-core peak
+    # 88.5 MB times 350 against the HBM peak; the dense-equivalent flops
+    # against the BF16 matrix-core peak are context
     q = bench.kernel_roofline("persistent", d, "fp32", 1, 10.0, 350.0)
-    assert q["bound"] == "mfma" and q["peak"] == 2500.0
-    assert q["frac"] == pytest.approx(350 * 7_864_320_000 / 10e-3 / 1e12 / 2500.0)
-    assert q["step_model"]["hbm_frac"] == pytest.approx(350 * 88_473_600 / 10e-3 / 1e9 / 8000.0)
+    assert q["bound"] == "hbm" and q["peak"] == 8000.0 and q["unit"] == "GB/s"
+    assert q["algorithmic_bytes_per_launch"] == 350 * 88_473_600
+    assert q["frac"] == pytest.approx(350 * 88_473_600 / 10e-3 / 1e9 / 8000.0)
+    assert q["step_model"]["mfma_frac"] == pytest.approx(350 * 7_864_320_000 / 10e-3 / 1e12 / 2500.0)
     m = bench.kernel_roofline("mfma_front", d, "fp32", 1, 0.01, 1.0)
     tf = 2.0 * 256 * 784 * 6400 / 10e-6 / 1e12
     assert m["mfma"]["achieved"] == pytest.approx(tf)

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from paper_1909_02549_amd import inputs
-from test_parity_gpu import RASTER_AGREE, V_RTOL, V_TOL, W_ATOL, W_RTOL, first_divergence, torch_cuda  # noqa: F401
+from test_parity_gpu import RASTER_AGREE, W_ATOL, W_RTOL, check_voltages, first_divergence, torch_cuda  # noqa: F401
 from test_serve_gpu import wait_all
 
 pytestmark = pytest.mark.gpu
@@ -80,9 +80,7 @@ def test_scaling_voltages(torch_cuda, oracle_mod, scaling_oracle, path):
         d = np.nonzero((gexc[r] != ref["exc"][r]).any(axis=1))[0]
         t_div = int(d[0]) if len(d) else T
         assert t_div > 20
-        vr = ref["v_exc"][r, :t_div]
-        dv = np.abs(gv[r, :t_div] - vr)
-        assert not (dv > V_TOL + V_RTOL * np.abs(vr)).any(), f"sample {sel[r]}: voltage error {dv.max()} mV"
+        check_voltages(gv[r, :t_div], ref["v_exc"][r, :t_div], f"sample {sel[r]}: ")
 
 
 DC400_T = 30
@@ -133,9 +131,7 @@ def test_dc400_b1024_learning(torch_cuda, oracle_mod, dc400_inputs, reduce, path
         assert agree >= RASTER_AGREE, f"{k} raster agreement {agree}"
     t_div = first_divergence(g, ref)
     if t_div > 0:
-        vr = ref["v_exc"][:, :t_div]
-        dv = np.abs(g["v_exc"][:, :t_div] - vr)
-        assert not (dv > V_TOL + V_RTOL * np.abs(vr)).any(), f"voltage error {dv.max()} mV before step {t_div}"
+        check_voltages(g["v_exc"][:, :t_div], ref["v_exc"][:, :t_div], f"before step {t_div}: ")
     same = (g["exc"] == ref["exc"]).all(axis=(0, 1))
     assert same.mean() >= 0.9, f"only {same.mean():.3f} of the columns agree in every entry"
     err = np.abs(g["W"][:, same] - ref["W"][:, same])
@@ -148,7 +144,7 @@ def test_serving_dc1600_requests_against_oracle(torch_cuda, oracle_mod):
     from paper_1909_02549_amd.snn import Net, Server
     wl = inputs.workload("serve")
     cfg = wl["cfg"]
-    W = inputs.column_scaled(inputs.uniform_weights(cfg["n_in"], cfg["n_exc"], wl["wlo"], wl["whi"], 0), 78.4)
+    W = inputs.frozen_weights(cfg["n_in"], cfg["n_exc"], 78.4, 0)
     net = Net(cfg, max_batch=1, path="auto")
     net.snn_set_weights(W)
     n = 24

@@ -25,8 +25,10 @@ def test_image_depends_only_on_seed_and_index():
 def test_weights_and_arrivals():
     w = inputs.uniform_weights(784, 10, 0.0, 0.3, 0)
     assert w.dtype == np.float32 and 0 <= w.min() and w.max() < 0.3
-    s = inputs.column_scaled(w, 78.4)
-    assert np.allclose(s.astype(np.float64).sum(0), 78.4, rtol=1e-5)
+    f = inputs.frozen_weights(784, 50, 78.4, 0)
+    assert f.dtype == np.float32 and f.min() > 0 and np.array_equal(f, inputs.frozen_weights(784, 50, 78.4, 0))
+    assert np.allclose(f.astype(np.float64).sum(0), 78.4, rtol=1e-5)
+    assert abs(f.mean() - 0.1) < 2e-3 and abs(f.std() / f.mean() - 1 / np.sqrt(3.0)) < 0.02
     t = inputs.poisson_arrivals(20000, 5000.0)
     assert abs(np.diff(t).mean() - 1 / 5000.0) < 1e-5
     T = inputs.request_durations(3000)

@@ -224,6 +224,80 @@ def test_stdp_pair_closed_form(oracle_mod, delta):
 
 
 # ---------------------------------------------------------------------------
+# additive traces (the trace form the paper leaves open; a flag here)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("additive", [0, 1])
+def test_trace_closed_forms(oracle_mod, additive):
+    """Traces after a forced spike train t_1 < t_2 < ... (a trace decays by
+    lam every step and takes the spike in the same step):
+      additive      x(t) = sum over t_k <= t of lam^(t - t_k)
+      nearest spike x(t) = lam^(t - t_last)
+    for the pre trace of input 0 and the post trace of the driven neuron.
+    Weights are held still (nu = 0, no normalisation)."""
+    T = 60
+    cfg = tiny_cfg(2, 1, learn=True, norm=0.0, nu_pre=0.0, nu_post=0.0, w_max=100.0,
+                   trace_additive=additive, exc=dict(adaptive=0))
+    lam = math.exp(-1.0 / 20.0)
+    pre = [3, 4, 9, 30, 31, 32, 50]
+    post = [5, 12, 20, 40, 46]            # at least 6 steps apart (5 refractory steps)
+    forced = np.zeros((1, T, 2), np.uint8)
+    forced[0, pre, 0] = 1
+    forced[0, post, 1] = 1                 # input 1 (w = 20) drives the neuron over threshold
+    for t_end in (33, 47, T):
+        net = oracle_mod.OracleNet(cfg, np.array([[0.5], [20.0]]))
+        out = net.run(None, sample_ids(1), t_end, forced_in=forced[:, :t_end], record=("exc",))
+        assert spike_times(out["exc"][0, :, 0]) == [t for t in post if t < t_end]
+        t = t_end - 1
+
+        def expect(times):
+            past = [tk for tk in times if tk <= t]
+            if additive:
+                return sum(lam ** (t - tk) for tk in past)
+            return lam ** (t - max(past))
+        assert abs(net.x_pre[0, 0] - expect(pre)) < 1e-14
+        assert abs(net.x_post[0, 0] - expect(post)) < 1e-14
+
+
+@pytest.mark.parametrize("additive", [0, 1])
+def test_additive_stdp_closed_forms(oracle_mod, additive):
+    """STDP from several spikes per synapse (normalisation off, clamps far
+    away).  Each post spike at t potentiates by nu_post x_pre(t) and each pre
+    spike at t depresses by nu_pre x_post(t), with traces of the closed forms
+    above.  Cases: two pre spikes then a post spike; two post spikes then a
+    pre spike; a pre spike, then pre and post in the same step."""
+    lam = math.exp(-1.0 / 20.0)
+    nu_pre, nu_post = 1e-4, 1e-2
+    cases = [
+        ([4, 9], [15]),          # pre, pre, post
+        ([22], [4, 13]),         # post, post, pre
+        ([6, 11], [11]),         # pre, then pre and post together
+    ]
+    for pre, post in cases:
+        T = 30
+        cfg = tiny_cfg(2, 1, learn=True, norm=0.0, w_max=100.0, trace_additive=additive,
+                       exc=dict(adaptive=0))
+        net = oracle_mod.OracleNet(cfg, np.array([[0.5], [20.0]]))
+        forced = np.zeros((1, T, 2), np.uint8)
+        forced[0, pre, 0] = 1
+        forced[0, post, 1] = 1
+        out = net.run(None, sample_ids(1), T, forced_in=forced, record=("exc",))
+        assert spike_times(out["exc"][0, :, 0]) == post
+
+        def trace(times, t):
+            past = [tk for tk in times if tk <= t]
+            if not past:
+                return 0.0
+            if additive:
+                return sum(lam ** (t - tk) for tk in past)
+            return lam ** (t - max(past))
+        dw = sum(nu_post * trace(pre, t) for t in post) - sum(nu_pre * trace(post, t) for t in pre)
+        assert abs((net.W[0, 0] - 0.5) - dw) < 1e-15, (pre, post)
+    # the two forms differ on the first two cases
+    assert additive == 0 or abs(trace([4, 9], 15) - lam ** 6) > 0.5
+
+
+# ---------------------------------------------------------------------------
 # batch reductions
 # ---------------------------------------------------------------------------
 

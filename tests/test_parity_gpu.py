@@ -2,10 +2,16 @@
 
 Bars (FP32 path): input spikes bit-exact; exc/inh rasters agree on at least
 99.9 % of (sample, step, neuron) entries; voltages within 1e-3 mV up to the
-first raster divergence, widened by 4e-6 |v| where one FP32 ulp of v already
-exceeds 1e-3 mV (summed inhibition drives v to -1e4 mV, ulp 1e-3 mV);
+first raster divergence, or 4e-6 |v| where that is larger (|v| above 250
+mV: summed inhibition adds terms of thousands of mV in one step, and FP32
+resolves such sums to a few 1e-4 mV; at -1e4 mV one ulp of v is 1e-3 mV);
 weights within 1e-4 relative (1e-6 absolute near zero) and theta within 1e-6
-relative when no spike diverged.
+relative on every column whose excitatory raster agrees with the oracle in
+every sample and step, which must be at least 90 % of the columns.  A
+column's weights and threshold depend only on its own spikes, its post
+traces and the (bit-exact) input spikes, so agreeing columns are held to the
+bar even after another column's spikes diverged.  Samples whose excitatory
+rasters agree everywhere have equal spike counts.
 """
 import numpy as np
 import pytest
@@ -17,8 +23,23 @@ pytestmark = pytest.mark.gpu
 
 RASTER_AGREE = 0.999
 V_TOL = 1e-3
-V_RTOL = 4e-6
+V_REL = 4e-6
 W_RTOL, W_ATOL = 1e-4, 1e-6
+COL_AGREE = 0.9
+
+
+def v_bar(vr):
+    """Voltage bar at oracle voltage vr: 1e-3 mV, or 4e-6 |v| (about 34 FP32
+    ulps of v) where that is larger, i.e. for |v| above 250 mV."""
+    return np.maximum(V_TOL, V_REL * np.abs(np.asarray(vr, np.float64)))
+
+
+def check_voltages(gv, vr, what=""):
+    dv = np.abs(gv - vr)
+    bad = dv > v_bar(vr)
+    if bad.any():
+        q = np.argmax(np.where(bad, dv, -1.0))
+        raise AssertionError(f"{what}voltage error {dv.flat[q]} mV at v={vr.flat[q]} mV")
 
 
 @pytest.fixture(scope="module")
@@ -89,7 +110,8 @@ def first_divergence(g, ref):
     return int(idx[0]) if len(idx) else T
 
 
-def check_parity(g, ref, learn=True):
+def check_parity(g, ref, learn=True, min_cols=COL_AGREE):
+    """Every bar of the module docstring; returns the first divergence step."""
     assert np.array_equal(g["in"], ref["in"]), "input spikes not bit-exact"
     agree_e = (g["exc"] == ref["exc"]).mean()
     assert agree_e >= RASTER_AGREE, f"exc raster agreement {agree_e}"
@@ -98,15 +120,17 @@ def check_parity(g, ref, learn=True):
         assert agree_i >= RASTER_AGREE, f"inh raster agreement {agree_i}"
     t_div = first_divergence(g, ref)
     if "v_exc" in g and t_div > 0:
-        vr = ref["v_exc"][:, :t_div]
-        dv = np.abs(g["v_exc"][:, :t_div] - vr)
-        bad = dv > V_TOL + V_RTOL * np.abs(vr)
-        assert not bad.any(), f"voltage error {dv.max()} mV (v={vr.flat[dv.argmax()]}) before step {t_div}"
-    if learn and t_div == ref["exc"].shape[1]:
-        err = np.abs(g["W"] - ref["W"])
-        bad = err > W_RTOL * np.abs(ref["W"]) + W_ATOL
-        assert not bad.any(), f"weights: max err {err.max()}"
-        np.testing.assert_allclose(g["theta"], ref["theta"], rtol=1e-6, atol=1e-12)
+        check_voltages(g["v_exc"][:, :t_div], ref["v_exc"][:, :t_div], f"before step {t_div}: ")
+    if "counts" in g and "counts" in ref:
+        rows = (g["exc"] == ref["exc"]).all(axis=(1, 2))
+        assert np.array_equal(g["counts"][rows], ref["counts"][rows].astype(np.int64)), "spike counts differ"
+    if learn:
+        same = (g["exc"] == ref["exc"]).all(axis=(0, 1))
+        assert same.mean() >= min_cols, f"only {same.mean():.3f} of the columns agree in every entry"
+        err = np.abs(g["W"][:, same] - ref["W"][:, same])
+        bad = err > W_RTOL * np.abs(ref["W"][:, same]) + W_ATOL
+        assert not bad.any(), f"weights of agreeing columns: max err {err.max()}"
+        np.testing.assert_allclose(g["theta"][same], ref["theta"][same], rtol=1e-6, atol=1e-12)
     return t_div
 
 
@@ -122,8 +146,7 @@ def test_dc100_learning_parity(torch_cuda, oracle_mod, path):
     W = uniform_weights(784, 100, 0.0, 0.3, 0)
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(4), 100, path=path)
     assert ref["exc"].sum() > 50
-    t_div = check_parity(g, ref)
-    assert np.array_equal(g["counts"], ref["counts"].astype(np.int64)) or t_div < 100
+    check_parity(g, ref)
     assert g["path"] == path
 
 
@@ -175,22 +198,60 @@ def test_per_run_normalisation_parity(torch_cuda, oracle_mod, path):
     assert ref["exc"].sum() > 50
     check_parity(g, ref)
     np.testing.assert_allclose(g["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
-    # continuing: a second call of 10 steps on the same handle and oracle
-    torch = torch_cuda
-    net = Net(cfg, max_batch=8, path=path)
+    # continuing: a second call of 10 steps on the same handle and oracle,
+    # which normalises at its own end
+    gc, rc = continuing_pair(torch_cuda, oracle_mod, cfg, W, imgs, ids, path, 40, 10)
+    for g_, r_ in zip(gc, rc):
+        check_parity(g_, r_)
+    np.testing.assert_allclose(gc[1]["W"].astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
+
+
+def continuing_pair(torch, oracle_mod, cfg, W, imgs, ids, path, T1, T2, precision="fp32"):
+    """An episodic call of T1 steps, then a continuing call (no reset) of T2
+    steps on the same handle, and the same two calls on one oracle; returns
+    ([gpu1, gpu2], [ref1, ref2]) with each call's records and the weights and
+    thresholds after it."""
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    B = len(ids)
+    net = Net(cfg, max_batch=B, path=path, precision=precision)
     net.snn_set_weights(W)
     d_imgs, d_ids = to_dev(torch, imgs), to_dev(torch, ids.astype(np.int64))
-    net.snn_run(d_imgs, d_ids, 40, record=())
-    net.snn_run(d_imgs, d_ids, 10, reset=False, record=())
-    torch.cuda.synchronize()
-    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64))
-    orc.run(imgs, ids, 40, record=())
-    orc.run(imgs, ids, 10, reset=False, record=())
-    gw = net.snn_get_weights()
+    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64), precision=precision)
+    rec = ("in", "exc", "inh", "v_exc", "counts")
+    gs, rs = [], []
+    for T, reset in ((T1, True), (T2, False)):
+        out = net.snn_run(d_imgs, d_ids, T, reset=reset, record=rec)
+        torch.cuda.synchronize()
+        g = {"in": unpack_bits(out["in"].cpu().numpy(), cfg["n_in"]).transpose(1, 0, 2),
+             "exc": unpack_bits(out["exc"].cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2),
+             "inh": unpack_bits(out["inh"].cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2),
+             "v_exc": out["v_exc"].cpu().numpy().transpose(1, 0, 2),
+             "counts": out["counts"].cpu().numpy().astype(np.int64),
+             "W": net.snn_get_weights(), "theta": net.snn_get_theta(), "path": net.snn_last_path()}
+        r = orc.run(imgs, ids, T, reset=reset, record=rec)
+        r["W"], r["theta"] = orc.W.copy(), orc.theta.copy()
+        gs.append(g)
+        rs.append(r)
     net.close()
-    np.testing.assert_allclose(gw.astype(np.float64).sum(axis=0), 78.4, rtol=1e-5)
-    err = np.abs(gw - orc.W)
-    assert (err <= W_RTOL * np.abs(orc.W) + W_ATOL).mean() > 0.99
+    return gs, rs
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_continuing_run_parity(torch_cuda, oracle_mod, path):
+    """Continuing simulation (Episodic vs. continuing simulation section): a
+    40-step episode, then 10 more steps without a reset, every-step
+    normalisation.  The second call starts from the first call's voltages,
+    refractory counts, traces and previous spikes, and its encoder continues
+    at local step 40; both calls meet every parity bar."""
+    cfg = dc_config(100)
+    imgs = stroke_images(8, 14, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 15)
+    gs, rs = continuing_pair(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 130), path, 40, 10)
+    assert gs[1]["path"] == path
+    assert rs[1]["exc"].sum() > 5
+    for g, r in zip(gs, rs):
+        check_parity(g, r)
+    assert first_divergence(gs[0], rs[0]) == 40, "first call diverged: continuation not tested"
 
 
 @pytest.mark.parametrize("path", ["fused", "persistent"])
@@ -321,7 +382,7 @@ def test_batch_equals_separate_runs_bit_exact(torch_cuda, path):
     cfg = dc_config(100, learn=False)
     imgs = stroke_images(8, 31, 0.19)
     ids = sample_ids(8, 900)
-    W = inputs.column_scaled(uniform_weights(784, 100, 0.0, 0.3, 6), 78.4)
+    W = inputs.frozen_weights(784, 100, 78.4, 6)
     T = 60
     net = Net(cfg, max_batch=8, path=path)
     net.snn_set_weights(W)
@@ -337,3 +398,43 @@ def test_batch_equals_separate_runs_bit_exact(torch_cuda, path):
         assert np.array_equal(one["exc"].cpu().numpy()[:, 0], fe[:, b]), f"sample {b}: spikes differ"
         assert np.array_equal(one["v_exc"].cpu().numpy()[:, 0], fv[:, b]), f"sample {b}: voltages differ"
     net.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_additive_traces_parity(torch_cuda, oracle_mod, path):
+    """Additive traces (x <- lam x + 1 on a spike, the flag of the trace
+    form): a learning run of the 784 -> 100/100 network, B = 8, on every
+    path.  Pre traces exceed 1 where inputs fire in consecutive steps."""
+    cfg = dc_config(100, trace_additive=1)
+    imgs = stroke_images(8, 17, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 16)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 160), 80, path=path)
+    assert g["path"] == path
+    assert ref["exc"].sum() > 50
+    # the additive form changes the result: the nearest-spike run differs
+    orc = oracle_mod.OracleNet(dc_config(100), W.astype(np.float64))
+    orc.run(imgs, sample_ids(8, 160), 80, record=())
+    assert np.abs(orc.W - ref["W"]).max() > 1e-4
+    check_parity(g, ref)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_additive_forced_spike_trains(torch_cuda, oracle_mod, path):
+    """Additive traces from forced trains of several pre and post spikes per
+    sample (the closed forms the oracle is pinned to), through
+    snn_run_spikes: input 0 is the plastic synapse, input 1 (weight 20)
+    drives the neuron."""
+    cfg = dc_config(1, n_in=2, reduce="sum", norm=0.0, w_max=100.0, exc=dict(adaptive=0), trace_additive=1)
+    cfg["n_inh"] = 0
+    T = 40
+    trains = [([4, 9], [15]), ([22], [4, 13]), ([6, 11], [11]), ([3, 4, 5, 6], [7, 20, 30]),
+              ([10, 20, 30], [12, 25]), ([1], [1])]
+    forced = np.zeros((len(trains), T, 2), np.uint8)
+    for b, (pre, post) in enumerate(trains):
+        forced[b, pre, 0] = 1
+        forced[b, post, 1] = 1
+    W = np.array([[0.5], [20.0]], np.float32)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(len(trains)), T, path=path,
+                      forced=forced, record=("in", "exc", "v_exc"))
+    assert ref["exc"].sum() == sum(len(p) for _, p in trains)
+    check_parity(g, ref)

@@ -42,14 +42,17 @@ def test_max_reduction_in_reduced_form(torch_cuda, oracle_mod, path):
     check_parity(g, ref)
 
 
-def test_bf16_against_unrounded_oracle(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", ["plain", "mfma", "fused", "persistent", "auto"])
+def test_bf16_against_unrounded_oracle(torch_cuda, oracle_mod, path):
     """The BF16 bar of the method: at least 99 % raster agreement with the
-    FP64 oracle that rounds nothing."""
+    FP64 oracle that rounds nothing, on every path (the autotuner's choice
+    included)."""
     cfg = dc_config(100)
     imgs = stroke_images(8, 60, 0.19)
     W = uniform_weights(784, 100, 0.0, 0.3, 13)
-    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 500), 100, path="mfma",
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 500), 100, path=path,
                       precision="bf16", oracle_precision="fp32")
+    assert path == "auto" or g["path"] == path
     assert np.array_equal(g["in"], ref["in"])
     for k in ("exc", "inh"):
         agree = (g[k] == ref[k]).mean()

@@ -26,7 +26,7 @@ def torch_cuda():
 def frozen_net(n_exc=64, path="auto"):
     from paper_1909_02549_amd.snn import Net
     cfg = inputs.dc_config(n_exc, learn=False)
-    W = inputs.column_scaled(inputs.uniform_weights(784, n_exc, 0.0, 0.3, 7), 78.4)
+    W = inputs.frozen_weights(784, n_exc, 78.4, 7)
     net = Net(cfg, max_batch=1, path=path)
     net.snn_set_weights(W)
     return cfg, W, net
@@ -114,3 +114,36 @@ def test_error_paths(torch_cuda):
     with pytest.raises(SnnError) as e:
         Server(learn_net, max_slots=2)
     assert e.value.status == -1
+
+
+def test_server_takes_the_frozen_handles_precision(torch_cuda, oracle_mod):
+    """A server built from a handle switched to BF16 with snn_set_path serves
+    in BF16: each request equals the BF16 run of its sample on the handle
+    itself, bit for bit, and the BF16-rounding oracle's counts.  Request 3 is
+    one whose BF16 and FP32 counts differ (oracle), so an FP32 server fails."""
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net, Server
+    cfg = inputs.dc_config(64, learn=False)
+    W = inputs.frozen_weights(784, 64, 78.4, 9)
+    net = Net(cfg, max_batch=1, path="fused", precision="fp32")
+    net.snn_set_weights(W)
+    net.snn_set_path("fused", "bf16")
+    imgs = inputs.stroke_images(4, 44, 0.19)
+    T = 60
+    srv = Server(net, max_slots=4, chunk_steps=20)
+    rids = [srv.snn_serve_submit(imgs[k], 40 + k, T) for k in range(4)]
+    res = wait_all(srv, rids)
+    srv.snn_serve_destroy()
+    for k, r in enumerate(rids):
+        out = net.snn_run(torch.from_numpy(imgs[k:k + 1]).cuda(), torch.tensor([40 + k], dtype=torch.int64).cuda(),
+                          T, record=("counts",))
+        torch.cuda.synchronize()
+        alone = out["counts"].cpu().numpy()[0].astype(np.uint32)
+        assert np.array_equal(res[r][0], alone), f"request {k}: served counts differ from the BF16 run"
+        ref = oracle_mod.OracleNet(cfg, W.astype(np.float64), precision="bf16").run(
+            imgs[k:k + 1], np.array([40 + k], np.uint64), T, record=("counts",))
+        assert np.array_equal(ref["counts"][0], alone), f"request {k}: counts differ from the BF16 oracle"
+    ref32 = oracle_mod.OracleNet(cfg, W.astype(np.float64), precision="fp32").run(
+        imgs[3:4], np.array([43], np.uint64), T, record=("counts",))
+    assert not np.array_equal(ref32["counts"][0], res[rids[3]][0])
+    net.close()
