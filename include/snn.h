@@ -22,7 +22,8 @@
  *  - Handles are not thread-safe, except that snn_serve_submit and
  *    snn_serve_poll may be called from any thread.
  *  - No call allocates device memory except snn_create, snn_run when the batch
- *    size grows beyond what was allocated, and snn_serve_create.
+ *    size grows beyond what was allocated, snn_serve_create and
+ *    snn_ifnet_create.
  */
 #ifndef SNN_H
 #define SNN_H
@@ -336,6 +337,25 @@ snn_status snn_ifnet_set_layer(snn_ifnet *net, uint32_t layer, const float *w_ho
  *         SNN_EDEVICE. */
 snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
                          const snn_ifnet_outputs *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * run as snn_ifnet_run, with the same outputs, but its scratch (the
+ * first-layer current and the partial readouts, (32 ceil(n_h1/32) +
+ * 32 ceil(n_h2/32)) * 4 bytes per sample) lives in a fixed 6 MiB array of
+ * device memory inside the library instead of the handle's buffers.  Each GPU
+ * holds one copy of that array from its first snn_ifnet_create until the
+ * process ends.  The call allocates nothing and reads nothing the previous
+ * call left in the array (every scratch entry is written before it is read).
+ * All calls on one GPU share its array: calls whose work overlaps on the
+ * device (different streams, or different handles without ordering between
+ * them) race and give undefined results; calls ordered on one stream are
+ * safe.  batch is not limited by max_batch, only by the array.
+ * Errors: as snn_ifnet_run, and SNN_ENOMEM when batch needs more than 6 MiB
+ *         of scratch (batch > 4096 for 256 h1 and 128 h2 neurons; nothing
+ *         runs). */
+snn_status snn_ifnet_run_noalloc(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                                 const snn_ifnet_outputs *out);
 
 /* Block until the handle's stream has finished its queued work. */
 snn_status snn_ifnet_sync(snn_ifnet *net);

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -449,6 +450,34 @@ __global__ __launch_bounds__(256) void k_if_readout(const float *__restrict__ rp
     if (pred && o == 0 && s < B) pred[s] = bi;
 }
 
+// Scratch of snn_ifnet_run_noalloc: the first-layer current I1 (B x n1t *
+// 32 floats) followed by the partial readouts (n2t x B x 32 floats), for
+// callers that cannot allocate.  Each GPU holds one copy until the process
+// ends; every call on a GPU uses that GPU's copy.
+constexpr size_t kNoallocScratchBytes = size_t(6) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// Device addresses of `scratch`, one per GPU, looked up with that GPU current
+// when the first handle on it is created (the host-side name of the array is
+// not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = q;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct snn_ifnet {
@@ -460,6 +489,7 @@ struct snn_ifnet {
     float *b[3] = {nullptr, nullptr, nullptr};
     float *I1 = nullptr;
     float *rpart = nullptr;  // n2t x max_batch x 32 partial readouts
+    void *scratch = nullptr; // this device's copy of `scratch` (snn_ifnet_run_noalloc)
     float *wtmp = nullptr;
     size_t wtmp_n = 0;
     bool set[3] = {false, false, false};
@@ -528,6 +558,7 @@ extern "C" snn_status snn_ifnet_create(const snn_ifnet_config *cfg, void *stream
     };
     hipError_t e = hipGetDevice(&n->device);
     if (e != hipSuccess) return bail(e, "hipGetDevice");
+    if ((e = scratch_address(n->device, &n->scratch)) != hipSuccess) return bail(e, "hipGetSymbolAddress(scratch)");
     size_t wmax = 0;
     for (int l = 0; l < 3; ++l) {
         int K, N, Kc, Nt;
@@ -577,26 +608,33 @@ extern "C" snn_status snn_ifnet_set_layer(snn_ifnet *net, uint32_t layer, const 
     return SNN_OK;
 }
 
-extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
-                                    const snn_ifnet_outputs *out)
+// Argument checks shared by snn_ifnet_run and snn_ifnet_run_noalloc.
+static snn_status ifnet_check(const snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T)
 {
     if (!net) return snn_net::error(SNN_EINVAL, "net is NULL");
     if (!images_dev) return snn_net::error(SNN_EINVAL, "images_dev is NULL");
     if (batch == 0) return snn_net::error(SNN_EINVAL, "batch must be > 0");
     if (T == 0 || T > 65535) return snn_net::error(SNN_EINVAL, "T must be in [1, 65535]");
     if (!net->set[0] || !net->set[1] || !net->set[2]) return snn_net::error(SNN_EINVAL, "every layer must be set first");
-    if (batch > net->cfg.max_batch) return snn_net::error(SNN_ENOMEM, "batch exceeds max_batch");
+    return SNN_OK;
+}
+
+// The three launches of a run, with the first-layer current in I1 (batch x
+// n1t * 32 floats) and the partial readouts in rpart (n2t x batch x 32).
+static snn_status ifnet_launch(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                               const snn_ifnet_outputs *out, float *I1, float *rpart)
+{
     snn_ifnet_outputs o{};
     if (out) o = *out;
     const int tiles = (int)((batch + 31) / 32);
     const bool vec8 = net->d.n_in % 8 == 0 && (reinterpret_cast<uintptr_t>(images_dev) & 7) == 0;
-    IfInArgs ia{images_dev, net->P[0], net->b[0], net->I1, (int)batch, net->d};
+    IfInArgs ia{images_dev, net->P[0], net->b[0], I1, (int)batch, net->d};
     if (vec8)
         hipLaunchKernelGGL(k_if_input<true>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
     else
         hipLaunchKernelGGL(k_if_input<false>, dim3(tiles, net->d.n1t), dim3(64 * kInWaves), 0, net->stream, ia);
     IF_TRY(hipGetLastError());
-    IfNetArgs na{net->I1, net->P[1], net->P[2], net->b[1], net->b[2], net->rpart, (float)net->cfg.theta_h1,
+    IfNetArgs na{I1, net->P[1], net->P[2], net->b[1], net->b[2], rpart, (float)net->cfg.theta_h1,
                  (float)net->cfg.theta_h2, (int)batch, (int)T, net->d, o};
     const dim3 grid(tiles, net->d.n2t);
     if (o.raster_h1 || o.raster_h2 || o.v_h1 || o.v_h2)
@@ -605,10 +643,34 @@ extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, u
         hipLaunchKernelGGL(k_if_net<false>, grid, dim3(kNetThreads), net->lds, net->stream, na);
     IF_TRY(hipGetLastError());
     if (o.out_sum || o.pred)
-        hipLaunchKernelGGL(k_if_readout, dim3((batch + 7) / 8), dim3(256), 0, net->stream, net->rpart, net->b[2],
+        hipLaunchKernelGGL(k_if_readout, dim3((batch + 7) / 8), dim3(256), 0, net->stream, rpart, net->b[2],
                            (int)batch, (int)T, net->d.n2t, net->d.n_out, o.out_sum, o.pred);
     IF_TRY(hipGetLastError());
     return SNN_OK;
+}
+
+extern "C" snn_status snn_ifnet_run(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                                    const snn_ifnet_outputs *out)
+{
+    const snn_status st = ifnet_check(net, images_dev, batch, T);
+    if (st != SNN_OK) return st;
+    if (batch > net->cfg.max_batch) return snn_net::error(SNN_ENOMEM, "batch exceeds max_batch");
+    return ifnet_launch(net, images_dev, batch, T, out, net->I1, net->rpart);
+}
+
+extern "C" snn_status snn_ifnet_run_noalloc(snn_ifnet *net, const uint8_t *images_dev, uint32_t batch, uint32_t T,
+                                            const snn_ifnet_outputs *out)
+{
+    const snn_status st = ifnet_check(net, images_dev, batch, T);
+    if (st != SNN_OK) return st;
+    const size_t i1_floats = (size_t)batch * 32 * net->d.n1t;
+    const size_t need = (i1_floats + (size_t)batch * 32 * net->d.n2t) * sizeof(float);
+    if (need > kNoallocScratchBytes)
+        return snn_net::error(SNN_ENOMEM, ("batch needs " + std::to_string(need) + " scratch bytes, more than the " +
+                                           std::to_string(kNoallocScratchBytes) + " of snn_ifnet_run_noalloc")
+                                              .c_str());
+    float *base = static_cast<float *>(net->scratch);
+    return ifnet_launch(net, images_dev, batch, T, out, base, base + i1_floats);
 }
 
 extern "C" snn_status snn_ifnet_sync(snn_ifnet *net)

@@ -30,7 +30,7 @@ EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "s
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
             "snn_serve_destroy", "snn_ifnet_create", "snn_ifnet_destroy", "snn_ifnet_set_layer", "snn_ifnet_run",
-            "snn_ifnet_sync"]
+            "snn_ifnet_run_noalloc", "snn_ifnet_sync"]
 
 
 class SnnError(RuntimeError):
@@ -116,6 +116,7 @@ def load_library():
         "snn_ifnet_destroy": ([VP], None),
         "snn_ifnet_set_layer": ([VP, U32, VP, SZ, VP, SZ], I32),
         "snn_ifnet_run": ([VP, VP, U32, U32, P(snn_ifnet_outputs)], I32),
+        "snn_ifnet_run_noalloc": ([VP, VP, U32, U32, P(snn_ifnet_outputs)], I32),
         "snn_ifnet_sync": ([VP], I32),
     }
     for name, (args, res) in sig.items():
@@ -398,9 +399,11 @@ class IFNet:
         for l, (W, b) in enumerate(layers, start=1):
             self.snn_ifnet_set_layer(l, W, b)
 
-    def snn_ifnet_run(self, images, T: int, record=("out_sum", "pred")):
+    def snn_ifnet_run(self, images, T: int, record=("out_sum", "pred"), noalloc: bool = False):
         """images: cuda uint8 (B, n_in).  Returns the requested device outputs
-        (asynchronous): out_sum, pred, counts_h1/h2, raster_h1/h2, v_h1/h2."""
+        (asynchronous): out_sum, pred, counts_h1/h2, raster_h1/h2, v_h1/h2.
+        ``noalloc`` calls snn_ifnet_run_noalloc (scratch in the library's
+        fixed device array instead of the handle's buffers)."""
         import torch
         B = int(images.shape[0])
         assert images.is_cuda and images.dtype == torch.uint8 and images.is_contiguous()
@@ -415,7 +418,8 @@ class IFNet:
         out = {k: torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev) for k in record}
         o = snn_ifnet_outputs(*(_ptr(out.get(k)) for k in ("out_sum", "pred", "counts_h1", "counts_h2",
                                                            "raster_h1", "raster_h2", "v_h1", "v_h2")))
-        _check(self.lib.snn_ifnet_run(self.h, _ptr(images), B, int(T), C.byref(o)))
+        fn = self.lib.snn_ifnet_run_noalloc if noalloc else self.lib.snn_ifnet_run
+        _check(fn(self.h, _ptr(images), B, int(T), C.byref(o)))
         return out
 
     def snn_ifnet_sync(self):
