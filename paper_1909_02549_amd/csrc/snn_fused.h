@@ -86,8 +86,11 @@ struct PersistSync {
     uint32_t *err;  // set to 1 if a barrier wait timed out
 };
 
-// Arguments of a persistent launch, read from device memory (kept out of
-// scalar registers: the kernel is register-bound).
+// Arguments of a persistent launch, passed by value (the kernel argument
+// segment), so that the compiler knows every pointer in them addresses global
+// memory and uses global rather than flat memory instructions: a flat access
+// also counts against the LDS wait counter, so any wait for an LDS read would
+// drain the outstanding global loads too.
 struct PersistArgs {
     Params p;
     FusedArgs a;
@@ -100,7 +103,7 @@ size_t persist_lds_bytes(const Params &p);
 template <int PREC>
 __global__ void k_fused_step(Params p, FusedArgs a, StepPtrs s);
 template <int PREC>
-__global__ void k_persist(const PersistArgs *args);
+__global__ void k_persist(const PersistArgs args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
 constexpr int kOrderThreads = 1024;
@@ -252,6 +255,23 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
     }
 }
 
+// The entries k0 .. cnt of a list (k0 a multiple of 4), 4 * NW at a time:
+// the NW 8-byte list words of a batch are loaded together, then gathered in
+// list order (the additions are those of a one-word-at-a-time walk).
+template <int NW = 4>
+__device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0, int cnt, const float *rows, int jbp,
+                                            int c0, int zero_row, int mode, float *acc, int prec)
+{
+    for (; k0 < cnt; k0 += 4 * NW) {
+        uint2 e[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) e[q] = k0 + 4 * q < cnt ? l4[(k0 >> 2) + q] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+            if (k0 + 4 * q < cnt) gather4rows(e[q], k0 + 4 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    }
+}
+
 // acc[0..8) = R over the first `cnt` entries of `list` (u16 row indices, in
 // list order) of q(rows[idx * jbp + c0 .. + 8)), four rows in flight at a
 // time, q the operand rounding of the precision `prec` (none for FP32);
@@ -267,7 +287,7 @@ __device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int c
     const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
     gather4rows(head0, 0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
     if (cnt > 4) gather4rows(nhead == 8 ? head1 : l4[1], 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
-    for (int k0 = 8; k0 < cnt; k0 += 4) gather4rows(l4[k0 >> 2], k0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    gather_tail(l4, 8, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
 }
 
 // The same with the first 8 * NH entries of the list in h[0 .. NH) (16-byte
@@ -285,8 +305,7 @@ __device__ __forceinline__ void gather_pre(const uint16_t *__restrict__ list, in
         if (8 * q + 4 < cnt)
             gather4rows(make_uint2(h[q].z, h[q].w), 8 * q + 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
     }
-    const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
-    for (int k0 = 8 * NH; k0 < cnt; k0 += 4) gather4rows(l4[k0 >> 2], k0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    gather_tail<2>(reinterpret_cast<const uint2 *>(list), 8 * NH, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
 }
 
 // Load the first 8 * NH entries of a list (NH 16-byte words, all in flight).
@@ -298,13 +317,14 @@ __device__ __forceinline__ void load_heads(const uint16_t *list, uint4 *h)
     for (int q = 0; q < NH; ++q) h[q] = l[q];
 }
 
-// Step phase A: C(t-1) and per-step scratch in LDS, threshold offsets.
-// theta64 holds the workgroup's thresholds (FP64).
+// Step phase A: C(t-1) (unless Cprev is null: the caller keeps it in
+// registers) and per-step scratch in LDS, threshold offsets.  theta64 holds
+// the workgroup's thresholds (FP64).
 template <bool Coherent>
 __device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, const uint32_t *Cprev, int tid, int nt)
 {
     for (int q = tid; q < p.B; q += nt) {
-        S.cprev[q] = p.has_inh ? ld_u<Coherent>(Cprev + q) : 0u;
+        if (Cprev) S.cprev[q] = p.has_inh ? ld_u<Coherent>(Cprev + q) : 0u;
         S.cinh[q] = 0u;
         S.colmask[q] = 0u;
     }
@@ -314,11 +334,14 @@ __device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, co
 
 // Step phase B for one task: 8 neurons j0+c of sample b (c < nv real).
 // acc: column sums of the sample's input spikes over the LDS block (raw,
-// before the pending scale).  Updates the register state, the post traces in
-// LDS, the spike masks and the inhibitory count; writes requested outputs.
+// before the pending scale); cp: the sample's inhibitory spike count of step
+// t - 1.  Updates the register state, the post traces in LDS, the spike
+// masks and the inhibitory count; writes requested outputs.  Returns the
+// excitatory spikes as bits 0..7.
 template <class PP>
-__device__ __forceinline__ void neuron_task(const PP &p, const StepLds &S, const Outs &o, int k, int b, int c0,
-                                            int j0, int nv, const float *acc, float *ve, float *vi, uint32_t *rw)
+__device__ __forceinline__ uint32_t neuron_task(const PP &p, const StepLds &S, const Outs &o, int k, int b, int c0,
+                                                int j0, int nv, const float *acc, uint32_t cp, float *ve, float *vi,
+                                                uint32_t *rw)
 {
     float xp[8];
     if (p.learn) {
@@ -332,7 +355,6 @@ __device__ __forceinline__ void neuron_task(const PP &p, const StepLds &S, const
     }
     // padding columns (c >= nv) keep their state and never spike; per-lane
     // conditions are selects, not branches
-    const uint32_t cp = S.cprev[b];
     uint32_t se_m = 0u, si_m = 0u;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -361,6 +383,7 @@ __device__ __forceinline__ void neuron_task(const PP &p, const StepLds &S, const
     }
     if (si_m) atomicAdd(&S.cinh[b], (uint32_t)__builtin_popcount(si_m));
     write_outputs8(p, o, k, b, j0, nv, se_m, si_m, ve, vi);
+    return se_m;
 }
 
 // After phase B: publish the inhibitory counts, clear the next step's slot
@@ -517,12 +540,21 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
                 if (g < ng) gather4rows(e, 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
         }
     }
+    // list entries past the head, 8 at a time (two list words loaded
+    // together), in list order
     const uint2 *l4 = reinterpret_cast<const uint2 *>(ltrow);
-    for (int k0 = 8 * NH; k0 < cnt; k0 += 4) {
-        const uint2 e = l4[k0 >> 2];
+    for (int k0 = 8 * NH; k0 < cnt; k0 += 8) {
+        uint2 e[2];
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-            if (g < ng) gather4rows(e, k0, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
+        for (int q = 0; q < 2; ++q) e[q] = k0 + 4 * q < cnt ? l4[(k0 >> 2) + q] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (k0 + 4 * q >= cnt) break;
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+                if (g < ng)
+                    gather4rows(e[q], k0 + 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
+        }
     }
     if (ucnt > 0) {
         accumulate();
@@ -561,9 +593,12 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 // samples times the row items, which keeps blocks whose neurons fire in many
 // samples of a step from holding up the others.
 // One 32-row tile rt of the potentiation product (one wave; lane = lane index).
-template <bool Coherent>
+// With Pre, x0 holds this lane's x_pre operands of the first 32 listed
+// samples, loaded ahead of time (tile_loads); later chunks are loaded here.
+template <bool Coherent, bool Pre = false>
 __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds &S, const float *xpre, int ucnt,
-                                                  uint32_t colany, int prec, int rt, int lane)
+                                                  uint32_t colany, int prec, int rt, int lane,
+                                                  const float (*x0)[8] = nullptr)
 {
     const int col = lane & 31, kh = lane >> 5;
     const bool fired_col = ((colany >> col) & 1u) != 0u && col < p.jb;
@@ -581,7 +616,10 @@ __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds
             for (int e = 0; e < 8; ++e) {
                 const int u = k0 + 16 * h + 8 * kh + e;
                 const uint32_t b = u < ucnt ? S.ulist[u] : 0u;
-                x[h][e] = (u < ucnt && row < p.n_in) ? ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + row) : 0.f;
+                if (Pre && k0 == 0)
+                    x[h][e] = x0[h][e];
+                else
+                    x[h][e] = (u < ucnt && row < p.n_in) ? ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + row) : 0.f;
                 bits[h] |= (u < ucnt ? (S.colmask[b] >> col) & 1u : 0u) << e;
             }
 #pragma unroll
@@ -627,6 +665,156 @@ __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds
     }
 }
 
+// One 16-sample K chunk pair of the potentiation product on the matrix cores:
+// x[h][e] are this lane's operands (sample 16 h + 8 (lane / 32) + e of the
+// chunk pair, at the lane's row), bits[h] the spike bits of those samples
+// at the lane's column; hn of the two halves hold listed samples.
+__device__ __forceinline__ f32x16_t potentiation_chunk(const float (&x)[2][8], const uint32_t (&bits)[2], int hn,
+                                                       int prec, f32x16_t acc)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= hn) break;
+        const uint4 bop = ones_bf16(bits[h]);
+        uint32_t c0[8], c1[8], c2[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (prec == PREC_FP32) {
+                uint32_t c[3];
+                split<PREC_FP32>(x[h][e], c);
+                c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
+            } else {
+                c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
+                c1[e] = c2[e] = 0u;
+            }
+        }
+        const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
+                                    c0[6] | (c0[7] << 16));
+        acc = mfma<PREC_BF16>(a0, bop, acc);
+        if (prec == PREC_FP32) {
+            const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16), c1[4] | (c1[5] << 16),
+                                        c1[6] | (c1[7] << 16));
+            const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16), c2[4] | (c2[5] << 16),
+                                        c2[6] | (c2[7] << 16));
+            acc = mfma<PREC_BF16>(a1, bop, acc);
+            acc = mfma<PREC_BF16>(a2, bop, acc);
+        }
+    }
+    return acc;
+}
+
+// w <- w * scale + nu_post * P for the fired column of this lane in tile rt
+// (accumulator r: row 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile).
+__device__ __forceinline__ void potentiation_write(const Params &p, const StepLds &S, const f32x16_t &acc, int rt,
+                                                   int lane, bool fired_col)
+{
+    const int col = lane & 31, kh = lane >> 5;
+    if (!fired_col) return;
+    const float sc = S.scalef[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (i < p.n_in) {
+            float *w = S.W + i * p.ls + col;
+            *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
+        }
+    }
+}
+
+// The potentiation pass of all tiles (sum and mean), software-pipelined per
+// wave, on the FP32 matrix instruction (v_mfma_f32_32x32x2_f32: operand A
+// lane l = row l % 32 of the tile, K element l / 32; B lane l = column
+// l % 32, K element l / 32; the accumulator layout of the other 32 x 32
+// forms).  The x_pre operands enter as FP32 values (rounded first in the
+// BF16 / FP8 forms), the spikes as exact 0 / 1, so every product is exact and
+// the sums accumulate in FP32.  Work items are (tile, chunk of 16 listed
+// samples) in order; the x_pre operands of the next item are loaded before
+// the current item's matrix products, so a tile's global-memory latency
+// overlaps the previous one's work.  Lane l takes the listed samples of
+// parity l / 32 of a chunk (8 per chunk); the samples of the first chunk
+// and their spike bits at the lane's column are read from LDS once.
+template <bool Coherent>
+__device__ __forceinline__ void potentiation_pipe(const Params &p, const StepLds &S, const float *xpre, int ucnt,
+                                                  uint32_t colany, int prec, int tid, int nt)
+{
+    const int lane = tid & 63, col = lane & 31, kh = lane >> 5;
+    const int nrt = (p.n_in + 31) >> 5, nw = nt >> 6;
+    int rt = tid >> 6;
+    if (rt >= nrt || ucnt <= 0) return;
+    const bool fired_col = ((colany >> col) & 1u) != 0u && col < p.jb;
+    const int nch = (ucnt + 15) >> 4;
+    // listed sample u = 16 c + 2 j + kh of chunk c, j < 8: its x_pre row
+    // offset (0xFFFFFFFF past the list) and, in bit j, its spike at `col`
+    auto samples = [&](int c, uint32_t (&off)[8], uint32_t &bits) {
+        bits = 0u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int u = 16 * c + 2 * j + kh;
+            const uint32_t b = u < ucnt ? S.ulist[u] : 0u;
+            off[j] = u < ucnt ? b * (uint32_t)p.n_in_pad : 0xFFFFFFFFu;
+            bits |= (u < ucnt ? (S.colmask[b] >> col) & 1u : 0u) << j;
+        }
+    };
+    // eight loads at valid addresses whatever the lanes' samples, so that
+    // the loop body issues a fixed number of loads and the next item's stay
+    // in flight during this one's products.  No select follows them: a
+    // sample past the list has spike bit 0 (its x_pre, a finite trace value
+    // of some sample, times 0 adds nothing), and rows past n_in are never
+    // written back.
+    auto load = [&](int t, const uint32_t (&off)[8], float (&x)[8]) {
+        const int row = t * 32 + col;
+        const bool rok = row < p.n_in;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = ld_x<Coherent>(xpre + (off[j] != 0xFFFFFFFFu && rok ? off[j] + row : 0u));
+    };
+    uint32_t off0[8], bits0;
+    samples(0, off0, bits0);
+    float xa[8], xb[8];
+    load(rt, off0, xa);
+    uint32_t bits = bits0;
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    int c = 0;
+    // one item: the next item's loads into nxt, then the products of cur;
+    // returns false after the last item (the loop alternates the two
+    // buffers, so no copy waits for loads in flight)
+    auto item = [&](const float (&cur)[8], float (&nxt)[8]) {
+        int rn = rt, cn = c + 1;
+        if (cn == nch) {
+            cn = 0;
+            rn = rt + nw;
+        }
+        const bool more = rn < nrt;
+        // the next item's samples (chunk 0's are kept) and x_pre operands;
+        // after the last item the current tile is loaded again, unused
+        uint32_t offn[8], bitsn = bits0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) offn[j] = off0[j];
+        if (cn > 0) samples(cn, offn, bitsn);
+        load(more ? rn : rt, offn, nxt);
+        // K pairs (2 j, 2 j + 1) holding listed samples of this chunk
+        const int npair = min(8, (ucnt - 16 * c + 1) >> 1);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j >= npair) break;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(operand_value(prec, cur[j]), (bits >> j) & 1u ? 1.f : 0.f,
+                                                       acc, 0, 0, 0);
+        }
+        if (cn == 0 || !more) {
+            potentiation_write(p, S, acc, rt, lane, fired_col);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        }
+        bits = bitsn;
+        rt = rn;
+        c = cn;
+        return more;
+    };
+    while (item(xa, xb) && item(xb, xa)) {
+    }
+}
+
 template <bool Coherent>
 __device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds &S, const float *xpre, int ucnt,
                                                   uint32_t colany, int prec, int tid, int nt)
@@ -635,12 +823,77 @@ __device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds
     for (int rt = tid >> 6; rt < nrt; rt += nt >> 6) potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, tid & 63);
 }
 
+// The loads one 32-row tile's depression items start from (lane l: row
+// rt * 32 + l % 32): the row's sample list length and first 8 * NH entries.
+// plasticity_tiles issues them one tile ahead.
+template <int NH>
+struct TileLoads {
+    uint32_t cnt;
+    uint4 h[NH];
+};
+
+template <int NH>
+__device__ __forceinline__ void tile_loads(const Params &p, const uint16_t *lt, const uint32_t *ct, int rt, int lane,
+                                           bool item, TileLoads<NH> &T)
+{
+    const int row = rt * 32 + (lane & 31);
+    T.cnt = 0u;
+#pragma unroll
+    for (int q = 0; q < NH; ++q) T.h[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (item) {
+        T.cnt = ct[row];
+        load_heads<NH>(lt + (size_t)row * p.lt_stride, T.h);
+    }
+}
+
+// Phase C for sum and mean, blocks of two or more column groups: per 32-row
+// tile one wave takes the potentiation tile product and then the depression
+// items of the same rows (lane l: row l % 32, column groups 2 (l / 32) and
+// 2 (l / 32) + 1), so the two need no workgroup barrier between them.  The
+// next tile's list loads (tile_loads) are issued before the current tile's
+// work (Pipe; otherwise after it), so their latency overlaps the current
+// tile's potentiation (whose own x_pre loads go out at its start) and
+// depression.
+template <bool Coherent, int NH, bool Pipe>
+__device__ __forceinline__ void plasticity_tiles(const Params &p, const StepLds &S, const uint16_t *lt,
+                                                 const uint32_t *ct, const float *xpre, int ucnt, uint32_t colany,
+                                                 int tid, int nt, int prec, int prec_d)
+{
+    const int ncg = p.jbp >> 3;
+    const int lane = tid & 63, nrt = (p.n_in + 31) >> 5, nw = nt >> 6;
+    const int hf = lane >> 5, cg0 = 2 * hf, ng = min(2, ncg - cg0);
+    int rt = tid >> 6;
+    if (rt >= nrt) return;
+    TileLoads<NH> cur, nxt;
+    tile_loads<NH>(p, lt, ct, rt, lane, rt * 32 + (lane & 31) < p.n_in && ng > 0, cur);
+    for (; rt < nrt; rt += nw) {
+        const int i = rt * 32 + (lane & 31);
+        const bool item = i < p.n_in && ng > 0;
+        const int rn = rt + nw;
+        if (Pipe && rn < nrt) tile_loads<NH>(p, lt, ct, rn, lane, rn * 32 + (lane & 31) < p.n_in && ng > 0, nxt);
+        if (ucnt > 0) {
+            potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, lane);
+            // the tile's weights, written by other lanes of this wave
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (item)
+            plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cur.cnt, cur.h, lt + (size_t)i * p.lt_stride,
+                                              xpre, 0, colany, prec, prec_d);
+        if (Pipe)
+            cur = nxt;
+        else if (rn < nrt)
+            tile_loads<NH>(p, lt, ct, rn, lane, rn * 32 + (lane & 31) < p.n_in && ng > 0, cur);
+    }
+}
+
 // Phase C over all input rows of the block: split rows (Halves, blocks of
 // two or more column groups) or whole rows per thread; a thread loads its
 // next row's list head before working on the current row.  Rows are taken in
 // the order `ord` (inputs by decreasing sample-list length), so the lanes of
 // a wave walk lists of similar length.
-template <bool Coherent, int XR, bool Halves, int NH = kListHead, bool Interleave = true>
+template <bool Coherent, int XR, bool Halves, int NH = kListHead, bool Interleave = true, bool Pipe = false>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const uint16_t *ord, const float *xpre, int tid,
                                                int nt, int prec, int prec_d)
@@ -648,35 +901,10 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
     const int ucnt = (int)S.ulist[p.B];
     const int ncg = p.jbp >> 3;
     if (Interleave && Halves && ncg >= 2 && p.reduce != RED_MAX) {
-        // sum / mean: per 32-row tile, one wave takes the potentiation tile
-        // product and then the depression items of the same rows (lane l:
-        // row l % 32, column groups 2 (l / 32) and 2 (l / 32) + 1), so the
-        // two need no workgroup barrier between them
         uint32_t colany = 0u;
         for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
         colany = __builtin_amdgcn_readfirstlane(colany);
-        const int lane = tid & 63, nrt = (p.n_in + 31) >> 5;
-        const int hf = lane >> 5, cg0 = 2 * hf, ng = min(2, ncg - cg0);
-        for (int rt = tid >> 6; rt < nrt; rt += nt >> 6) {
-            const int i = rt * 32 + (lane & 31);
-            const bool item = i < p.n_in && ng > 0;
-            if (ucnt > 0) {
-                potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, lane);
-                // the tile's weights, written by other lanes of this wave
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            uint32_t cnt = 0u;
-            uint4 h[NH];
-            if (item) {
-                cnt = ct[i];
-                load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
-            }
-            if (item)
-                plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
-                                                  0, colany, prec, prec_d);
-        }
+        plasticity_tiles<Coherent, NH, Pipe>(p, S, lt, ct, xpre, ucnt, colany, tid, nt, prec, prec_d);
         return;
     }
     if (Halves && ncg >= 2) {
@@ -688,7 +916,10 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             uint32_t colany = 0u;
             for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
             colany = __builtin_amdgcn_readfirstlane(colany);
-            potentiation_mfma<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
+            if (Pipe)
+                potentiation_pipe<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
+            else
+                potentiation_mfma<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
             __syncthreads();
             pdone = colany;
             ucnt_items = 0;
@@ -697,6 +928,40 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
         // 2 hf + 1 with hf = (q / 64) % 2, the same in every lane of a wave
         // (nt is a multiple of 128)
         const int nrow = (p.n_in + 63) & ~63;
+        if (Pipe && ucnt_items == 0) {
+            // the next item's row, list length and list head are loaded
+            // before the current item's walk
+            auto fetch = [&](int q, int &i, TileLoads<NH> &T) {
+                const int hf = (q >> 6) & 1;
+                const int r = ((q >> 7) << 6) | (q & 63);
+                const bool ok = q < 2 * nrow && r < p.n_in && min(2, ncg - 2 * hf) > 0;
+                i = ok ? (int)ord[r] : -1;
+                T.cnt = 0u;
+#pragma unroll
+                for (int w = 0; w < NH; ++w) T.h[w] = make_uint4(0u, 0u, 0u, 0u);
+                if (ok) {
+                    T.cnt = ct[i];
+                    load_heads<NH>(lt + (size_t)i * p.lt_stride, T.h);
+                }
+            };
+            TileLoads<NH> cur, nxt;
+            int i_cur, i_nxt;
+            fetch(tid, i_cur, cur);
+            for (int q = tid; q < 2 * nrow; q += nt) {
+                const bool more = q + nt < 2 * nrow;
+                if (more) fetch(q + nt, i_nxt, nxt);
+                if (i_cur >= 0) {
+                    const int cg0 = 2 * ((q >> 6) & 1);
+                    plasticity_row_half<Coherent, NH>(p, S, i_cur, cg0, min(2, ncg - cg0), (int)cur.cnt, cur.h,
+                                                      lt + (size_t)i_cur * p.lt_stride, xpre, 0, pdone, prec,
+                                                      prec_d);
+                }
+                if (!more) break;
+                cur = nxt;
+                i_cur = i_nxt;
+            }
+            return;
+        }
         for (int q = tid; q < 2 * nrow; q += nt) {
             const int hf = (q >> 6) & 1;
             const int r = ((q >> 7) << 6) | (q & 63);
@@ -813,6 +1078,66 @@ __device__ __forceinline__ void xpre_next(const Params &p, const uint32_t *bits_
         for (int i = tid; i < p.n_in_pad; i += nt)
             st_x<Coherent>(xn + i, trace_step(ld_x<Coherent>(xc + i), p.lam_pre, (sb[i >> 5] >> (i & 31)) & 1u,
                                               p.trace_add));
+    }
+}
+
+// The workgroup's share of x_pre: samples g, g + ng, ... (the samples whose
+// next-step traces xpre_next writes), as one flat range f of
+// own_samples * n_in_pad entries (sample g + (f / n_in_pad) * ng, input
+// f % n_in_pad).  Entry f = tid + j * nt (j < XC) of that range is kept in
+// register xc[j] across the steps of a persistent launch.
+__device__ __forceinline__ int own_entries(const Params &p, int g, int ng)
+{
+    return g < p.B ? ((p.B - 1 - g) / ng + 1) * p.n_in_pad : 0;
+}
+
+__device__ __forceinline__ size_t own_offset(const Params &p, int f, int g, int ng, int &i)
+{
+    const int sq = f / p.n_in_pad;
+    i = f - sq * p.n_in_pad;
+    return (size_t)(g + sq * ng) * p.n_in_pad + i;
+}
+
+// Fill the register copy from x_pre(t) (buffer xpre).
+template <int XC>
+__device__ __forceinline__ void xpre_own_load(const Params &p, const float *xpre, float *xc, int g, int ng, int tid,
+                                              int nt)
+{
+    const int total = own_entries(p, g, ng);
+#pragma unroll
+    for (int j = 0; j < XC; ++j) {
+        const int f = tid + j * nt;
+        int i;
+        xc[j] = f < total ? ld_x<true>(xpre + own_offset(p, f, g, ng, i)) : 0.f;
+    }
+}
+
+// Phase E of the persistent kernel: x_pre(t+1) of the workgroup's share from
+// the register copy of x_pre(t) (entries past XC * nt from xpre), written to
+// xn_all for the other workgroups; the register copy becomes x_pre(t+1).
+template <int XC>
+__device__ __forceinline__ void xpre_next_own(const Params &p, const uint32_t *bits_next, const float *xpre,
+                                              float *xn_all, float *xc, int g, int ng, int tid, int nt)
+{
+    const int total = own_entries(p, g, ng);
+#pragma unroll
+    for (int j = 0; j < XC; ++j) {
+        const int f = tid + j * nt;
+        if (f < total) {
+            int i;
+            const size_t o = own_offset(p, f, g, ng, i);
+            const size_t b = o / (size_t)p.n_in_pad;
+            const uint32_t bit = (bits_next[b * p.in_words + (i >> 5)] >> (i & 31)) & 1u;
+            xc[j] = trace_step(xc[j], p.lam_pre, bit, p.trace_add);
+            st_x<true>(xn_all + o, xc[j]);
+        }
+    }
+    for (int f = tid + XC * nt; f < total; f += nt) {
+        int i;
+        const size_t o = own_offset(p, f, g, ng, i);
+        const size_t b = o / (size_t)p.n_in_pad;
+        const uint32_t bit = (bits_next[b * p.in_words + (i >> 5)] >> (i & 31)) & 1u;
+        st_x<true>(xn_all + o, trace_step(ld_x<true>(xpre + o), p.lam_pre, bit, p.trace_add));
     }
 }
 

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
         load_heads<kListHead>(row, h);
         load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         gather_pre<kListHead>(row, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, 0);
-        neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, ve, vi, rw);
+        neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, S.cprev[b], ve, vi, rw);
         store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         if (PREC != PREC_FP32 && p.learn) {
             float *xr = S.xpost + b * p.ls + c0;

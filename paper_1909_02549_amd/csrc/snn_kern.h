@@ -188,10 +188,12 @@ __device__ __forceinline__ void write_outputs8(const PP &p, const Outs &o, int k
     const int words = (p.n_exc + 31) >> 5;
     const size_t row = (size_t)k * p.B + b;
     if (o.counts && se_m) {
+        // one owner per entry: a device atomic with its result unused, so the
+        // step does not wait for a load of the old count
         uint32_t *cnt = o.counts + (size_t)b * p.n_exc + j0;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-            if ((se_m >> c) & 1u) cnt[c] += 1u;
+            if ((se_m >> c) & 1u) (void)__hip_atomic_fetch_add(cnt + c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     const int w0 = j0 >> 5, sh = j0 & 31;
     if (o.raster_exc && se_m) {

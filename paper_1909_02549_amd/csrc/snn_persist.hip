@@ -62,14 +62,14 @@ __device__ __forceinline__ bool grid_wait(const PersistSync &sy, uint32_t target
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *__restrict__ args)
+__global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs args)
 {
     // PREC: the operand form (rounding in the gathers for BF16 / FP8)
 
-    const Params &p = args->p;
-    const FusedArgs &a = args->a;
-    const ChunkPtrs &ch = args->ch;
-    const PersistSync &sy = args->sy;
+    const Params &p = args.p;
+    const FusedArgs &a = args.a;
+    const ChunkPtrs &ch = args.ch;
+    const PersistSync &sy = args.sy;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int abort_lds;
     const FusedLds L(p, blockDim.x);
@@ -114,6 +114,10 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             }
         }
     }
+    // x_pre(t) of this workgroup's own samples in registers (xpre_next_own)
+    constexpr int XC = 2;
+    float xc[XC];
+    if (p.learn) xpre_own_load<XC>(p, ch.xpre + (size_t)ch.mod0 * p.Bs * p.n_in_pad, xc, g, gridDim.x, tid, nt);
     __syncthreads();
 
     // neuron parameters and output pointers in registers for the step loop
@@ -126,7 +130,12 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
 
         // counts of step t - 1 and x_pre(t) from every workgroup
         if (k > 0 && !grid_wait(sy, (uint32_t)k * gridDim.x, &abort_lds)) return;
-        step_begin<true>(p, S, ch.C + (size_t)((mod + 2) % 3) * p.Bs, tid, nt);
+        step_begin<true>(p, S, nullptr, tid, nt);
+        // C(t - 1) of this thread's samples, in flight during the first gather
+        const uint32_t *Cprev = ch.C + (size_t)((mod + 2) % 3) * p.Bs;
+        uint32_t cp[kPersistTasks];
+#pragma unroll
+        for (int u = 0; u < kPersistTasks; ++u) cp[u] = (has_task[u] && p.has_inh) ? ld_u<true>(Cprev + tb[u]) : 0u;
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kPersistTasks; ++u) {
@@ -134,15 +143,16 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
             float acc[8];
             const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
             gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
-            neuron_task(nk, S, outs, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, ve[u], vi[u], rw[u]);
+            neuron_task(nk, S, outs, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, cp[u], ve[u], vi[u],
+                        rw[u]);
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
         if (p.learn && (k + 1 < ch.steps || ch.has_next))
-            xpre_next<true>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, g, gridDim.x, tid, nt);
+            xpre_next_own<XC>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, xc, g, gridDim.x, tid, nt);
         grid_arrive(sy);
         if (p.learn) {
-            plasticity_all<true, 16, true, 2, PREC == PREC_FP32>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
+            plasticity_all<true, 16, true, 2, false, true>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
                                               ch.ct + (size_t)k * p.n_in_pad, ch.ord_in + (size_t)k * p.n_in_pad,
                                               xpre, tid, nt, PREC, PREC);
             __syncthreads();
@@ -168,8 +178,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs *
     if (p.learn) store_block(p, S, Wg, a.theta, g, tid, nt);
 }
 
-template __global__ void k_persist<PREC_FP32>(const PersistArgs *);
-template __global__ void k_persist<PREC_BF16>(const PersistArgs *);
-template __global__ void k_persist<PREC_FP8>(const PersistArgs *);
+template __global__ void k_persist<PREC_FP32>(const PersistArgs);
+template __global__ void k_persist<PREC_BF16>(const PersistArgs);
+template __global__ void k_persist<PREC_FP8>(const PersistArgs);
 
 }  // namespace snn

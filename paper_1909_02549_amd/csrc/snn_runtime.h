@@ -109,13 +109,8 @@ struct snn_net {
     size_t fused_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};  // per operand form
     snn_status fused_step(int kk, int k, bool has_next, const snn::Outs &o);
 
-    // persistent path: grid barrier counter / error flag, argument ring
-    static constexpr int kArgSlots = 16;
+    // persistent path: grid barrier counter / error flag
     uint32_t *bar = nullptr, *err = nullptr;
-    void *pargs_dev = nullptr;           // kArgSlots x PersistArgs (device)
-    void *pargs_host = nullptr;          // kArgSlots x PersistArgs (pinned)
-    hipEvent_t pargs_ev[kArgSlots] = {};
-    int pargs_next = 0;
     size_t persist_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};
     int coop_ok = -1;
     bool persist_ok();

@@ -268,12 +268,8 @@ snn_net::~snn_net()
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    for (auto &e : pargs_ev)
-        if (e) (void)hipEventDestroy(e);
     (void)hipFree(bar);
     (void)hipFree(err);
-    (void)hipFree(pargs_dev);
-    if (pargs_host) (void)hipHostFree(pargs_host);
     free_state();
     (void)hipFree(W);
     (void)hipFree(theta);
@@ -326,9 +322,6 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **
     if (e == hipSuccess) e = hipMalloc(&n->thr_lut, 256 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&n->bar, 64);
     if (e == hipSuccess) e = hipMalloc(&n->err, 64);
-    if (e == hipSuccess) e = hipMalloc(&n->pargs_dev, snn_net::kArgSlots * sizeof(PersistArgs));
-    if (e == hipSuccess) e = hipHostMalloc(&n->pargs_host, snn_net::kArgSlots * sizeof(PersistArgs), hipHostMallocDefault);
-    for (int q = 0; q < snn_net::kArgSlots && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&n->pargs_ev[q], hipEventDisableTiming);
     if (e != hipSuccess) {
         delete n;
         return fail(SNN_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -774,15 +767,10 @@ bool snn_net::persist_ok()
 
 snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &o)
 {
-    const int slot = pargs_next;
-    pargs_next = (pargs_next + 1) % kArgSlots;
-    if (prof) prof_close();
-    HIP_TRY(hipEventSynchronize(pargs_ev[slot]));
-    PersistArgs *h = reinterpret_cast<PersistArgs *>(pargs_host) + slot;
-    PersistArgs *d = reinterpret_cast<PersistArgs *>(pargs_dev) + slot;
-    h->p = p;
-    h->a = FusedArgs{W, theta, v_exc, v_inh, x_post, rf, o};
-    ChunkPtrs &c = h->ch;
+    PersistArgs h;
+    h.p = p;
+    h.a = FusedArgs{W, theta, v_exc, v_inh, x_post, rf, o};
+    ChunkPtrs &c = h.ch;
     c.bits = bits;
     c.lin = lin;
     c.cin = cin;
@@ -798,9 +786,7 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     // every step normalises, or under per-run normalisation only the last
     // step of the run (none if the run continues in a later chunk)
     c.norm_from = !cfg.norm_per_run ? 0 : (uint32_t)(k0 + steps) == run_T ? steps - 1 : steps;
-    h->sy = PersistSync{bar, err};
-    HIP_TRY(hipMemcpyAsync(d, h, sizeof(PersistArgs), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(pargs_ev[slot], stream));
+    h.sy = PersistSync{bar, err};
     SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
     const size_t lds = persist_lds_bytes(p);
     const void *kfn = p.prec == PREC_FP32   ? (const void *)k_persist<PREC_FP32>
@@ -810,7 +796,8 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
         HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         persist_attr_bytes[p.prec] = lds;
     }
-    void *kargs[] = {(void *)&d};
+    // the arguments go by value: the runtime copies them into the launch
+    void *kargs[] = {(void *)&h};
     if (prof) prof_open(kstat_id("persistent"));
     HIP_TRY(hipLaunchCooperativeKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
                                        (unsigned)lds, stream));
