@@ -888,6 +888,20 @@ __device__ __forceinline__ void plasticity_tiles(const Params &p, const StepLds 
     }
 }
 
+// Rank of the input row of row item q (column-group half (q / 64) % 2): the
+// 64-row blocks of the step's input order (rows by decreasing sample-list
+// length) go to consecutive 128-item groups, in reverse order within every
+// other full set of four groups, so that the workgroup's waves (one group
+// per wave pair in a 512-thread workgroup) each get a mix of long and short
+// lists; a bijection on the items of nrow rows.
+__device__ __forceinline__ int item_rank(int q, int nrow)
+{
+    const int g = q >> 7, s4 = g >> 2;
+    const bool full = 4 * s4 + 3 < (nrow >> 6);
+    const int blk = (full && (s4 & 1)) ? 4 * s4 + 3 - (g & 3) : g;
+    return (blk << 6) | (q & 63);
+}
+
 // Phase C over all input rows of the block: split rows (Halves, blocks of
 // two or more column groups) or whole rows per thread; a thread loads its
 // next row's list head before working on the current row.  Rows are taken in
@@ -924,16 +938,16 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             pdone = colany;
             ucnt_items = 0;
         }
-        // item q: row ord[(q / 128) * 64 + q % 64], column groups 2 hf and
-        // 2 hf + 1 with hf = (q / 64) % 2, the same in every lane of a wave
-        // (nt is a multiple of 128)
+        // item q: row ord[item_rank(q)], column groups 2 hf and 2 hf + 1 with
+        // hf = (q / 64) % 2, the same in every lane of a wave (nt is a
+        // multiple of 128)
         const int nrow = (p.n_in + 63) & ~63;
         if (Pipe && ucnt_items == 0) {
             // the next item's row, list length and list head are loaded
             // before the current item's walk
             auto fetch = [&](int q, int &i, TileLoads<NH> &T) {
                 const int hf = (q >> 6) & 1;
-                const int r = ((q >> 7) << 6) | (q & 63);
+                const int r = item_rank(q, nrow);
                 const bool ok = q < 2 * nrow && r < p.n_in && min(2, ncg - 2 * hf) > 0;
                 i = ok ? (int)ord[r] : -1;
                 T.cnt = 0u;
@@ -964,7 +978,7 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
         }
         for (int q = tid; q < 2 * nrow; q += nt) {
             const int hf = (q >> 6) & 1;
-            const int r = ((q >> 7) << 6) | (q & 63);
+            const int r = item_rank(q, nrow);
             const int cg0 = 2 * hf;
             const int ng = min(2, ncg - cg0);
             if (r >= p.n_in || ng <= 0) continue;
