@@ -186,13 +186,16 @@ snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision);
 
 /* Replay repeated episodic runs from captured HIP graphs (on = 1) or launch
  * every kernel (on = 0, the default).  With graphs on, an snn_run /
- * snn_run_spikes with SNN_RUN_RESET (or a new batch size) on the PLAIN,
- * MFMA or FUSED path is captured the first time its arguments occur (batch,
- * T, buffers, reduction, precision) and replayed with a single launch
- * afterwards; results are those of the launched kernels.  Profiling
- * (snn_profile_enable) and the PERSISTENT path always launch directly.
- * Captured graphs are dropped when the batch capacity, path, precision or
- * reduction changes.  SNN_EINVAL for a NULL handle or on not in {0, 1}. */
+ * snn_run_spikes with SNN_RUN_RESET (or a new batch size) is captured the
+ * first time its arguments occur (path, batch, T, buffers, reduction,
+ * precision) and replayed with a single launch afterwards; results are those
+ * of the launched kernels.  On the PERSISTENT path the captured kernel is an
+ * ordinary (not cooperative) launch: its workgroups must all be resident at
+ * once, which holds when no other work occupies the GPU's CUs; otherwise its
+ * bounded grid barrier times out and snn_sync reports SNN_EDEVICE.
+ * Profiling (snn_profile_enable) always launches directly.  Captured graphs
+ * are dropped when the batch capacity, path, precision or reduction changes.
+ * SNN_EINVAL for a NULL handle or on not in {0, 1}. */
 snn_status snn_set_graphs(snn_net *net, int32_t on);
 
 /* The execution path the most recent snn_run / snn_run_spikes used (the

@@ -9,7 +9,10 @@
 // launch cost (a few microseconds per kernel, four or more kernels per step)
 // that dominates small batches.  The capture records nothing but kernel
 // launches (buffers are cleared by fill kernels, never by memset nodes).
-// The persistent path is one launch per chunk already and is not captured.
+// On the persistent path the captured episode is the fill kernels, the
+// encoder, the spike lists and orders, the first presynaptic traces and
+// one persistent launch per chunk (an ordinary kernel node, its arguments
+// by value).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -62,7 +65,9 @@ snn_status snn_net::run_graph(int path, const uint8_t *images, const uint64_t *i
             stream = user;
             return error(SNN_EDEVICE, "hipStreamBeginCapture failed");
         }
+        capturing = true;
         snn_status st = episode(path, images, ids, forced, batch, T, o);
+        capturing = false;
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(cap_stream, &g);
         stream = user;

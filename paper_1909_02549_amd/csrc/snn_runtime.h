@@ -90,6 +90,7 @@ struct snn_net {
     };
     static constexpr size_t kMaxGraphs = 16;
     bool use_graphs = false;
+    bool capturing = false;  // an episode is being captured (persistent: ordinary launch)
     hipStream_t cap_stream = nullptr;
     std::map<std::string, Graph> graphs;
     void graphs_invalidate();

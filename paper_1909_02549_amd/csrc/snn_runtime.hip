@@ -663,8 +663,7 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
     set_batch(batch);
     const int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T, images, ids, forced) : this->path;
     set_batch(batch);
-    if (reset && use_graphs && !prof && path != SNN_PATH_PERSISTENT)
-        return run_graph(path, images, ids, forced, batch, T, o);
+    if (reset && use_graphs && !prof) return run_graph(path, images, ids, forced, batch, T, o);
     if (reset) {
         st = reset_state(nullptr);
         if (st != SNN_OK) return st;
@@ -796,11 +795,19 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
         HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         persist_attr_bytes[p.prec] = lds;
     }
-    // the arguments go by value: the runtime copies them into the launch
+    // the arguments go by value: the runtime copies them into the launch.
+    // Launched directly, the kernel goes out as a cooperative launch (the
+    // runtime checks that every workgroup is resident at once); captured in
+    // a graph it is an ordinary kernel node: its nblk <= #CU workgroups each
+    // take a whole CU's LDS share, so an otherwise idle GPU holds them all,
+    // and the bounded grid barrier turns anything else into SNN_EDEVICE.
     void *kargs[] = {(void *)&h};
     if (prof) prof_open(kstat_id("persistent"));
-    HIP_TRY(hipLaunchCooperativeKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
-                                       (unsigned)lds, stream));
+    if (capturing)
+        HIP_TRY(hipLaunchKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs, (unsigned)lds, stream));
+    else
+        HIP_TRY(hipLaunchCooperativeKernel(kfn, dim3((unsigned)p.nblk), dim3(kPersistThreads), kargs,
+                                           (unsigned)lds, stream));
     if (prof) span.launches += 1;
     gstep += (uint64_t)steps;
     return SNN_OK;

@@ -26,7 +26,7 @@ def trial_outputs(torch, net, imgs_d, ids_d, T):
     return res
 
 
-@pytest.mark.parametrize("path", ["plain", "mfma", "fused"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "fused", "persistent"])
 def test_graph_replays_equal_launches(torch_cuda, path):
     torch = torch_cuda
     from paper_1909_02549_amd.snn import Net
@@ -80,5 +80,37 @@ def test_graph_with_changing_batch_and_frozen_weights(torch_cuda):
                 first = a
             else:
                 assert np.array_equal(first["counts"], a["counts"])
+    g_net.close()
+    e_net.close()
+
+
+def test_persistent_graph_full_size_trial(torch_cuda):
+    """The benchmark's workload (784 -> 6400/6400, B = 256, T = 350, STDP) on
+    the persistent path replayed from a captured graph: three trials in a
+    row, each bit-identical (spike counts, weights, thresholds) to the same
+    trial launched directly, with the device error flag clear."""
+    torch = torch_cuda
+    from paper_1909_02549_amd.snn import Net
+    wl = inputs.workload("dc6400")
+    cfg, B, T = wl["cfg"], wl["B"], wl["T"]
+    imgs_d = torch.from_numpy(stroke_images(B, 1234, wl["density"])).cuda()
+    ids_d = torch.from_numpy(sample_ids(B).astype(np.int64)).cuda()
+    W = uniform_weights(784, cfg["n_exc"], wl["wlo"], wl["whi"], 0)
+    g_net = Net(cfg, max_batch=B, path="persistent")
+    e_net = Net(cfg, max_batch=B, path="persistent")
+    g_net.snn_set_weights(W)
+    e_net.snn_set_weights(W)
+    g_net.snn_set_graphs(True)
+    for trial in range(3):
+        outs = []
+        for net in (g_net, e_net):
+            out = net.snn_run(imgs_d, ids_d, T, reset=True, record=("counts",))
+            net.snn_sync()
+            outs.append((out["counts"].cpu().numpy(), net.snn_get_weights(), net.snn_get_theta(),
+                         net.snn_last_path()))
+        (ca, wa, ta, pa), (cb, wb, tb, pb) = outs
+        assert pa == pb == "persistent"
+        assert np.array_equal(ca, cb) and np.array_equal(wa, wb) and np.array_equal(ta, tb), f"trial {trial}"
+        assert ca.sum() > 0
     g_net.close()
     e_net.close()
