@@ -1,17 +1,23 @@
-// snn_autotune.hip -- choice of the execution path for SNN_PATH_AUTO.
+// snn_autotune.hip -- choice of the execution path and the column block
+// width for SNN_PATH_AUTO.
 //
-// The candidates are the paths whose kernels fit the batch (persistent:
-// cooperative launch with every task's state in registers; fused: the
-// weight block and post traces fit in LDS; MFMA: matrix-core current and
-// STDP; plain: always).  The first AUTO run of
-// a given network shape, batch size and precision times each candidate on a
-// scratch copy of the network (same weights, thresholds and inputs, so the
-// spike activity is representative) for a short warm-up and one timed
-// episode, keeps the fastest in a process-wide table, and appends it to the
-// file named by SNN_AUTOTUNE_CACHE if set (lines "key path").
-// SNN_AUTOTUNE=0 skips the measurement and takes the first available path in
-// the order persistent, fused, MFMA, plain; SNN_AUTOTUNE_VERBOSE=1 reports
-// each candidate's time on stderr.
+// The candidate paths are those whose kernels fit the batch (persistent:
+// every workgroup resident at once with every task's state in registers;
+// fused: the weight block and post traces fit in LDS; MFMA: matrix-core
+// current and STDP; plain: always).  At an episode start the candidates
+// also cover the column block width JB (the handle's, and 8, 16 and 32
+// columns; the persistent path needs at most one block per CU), because it
+// sets how the work splits into workgroups.  The first AUTO run of a given
+// network shape, batch size and precision times each (path, JB) on scratch
+// copies of the network (same weights, thresholds and inputs, so the spike
+// activity is representative) for a short warm-up and one timed episode,
+// keeps the fastest in a process-wide table, and appends it to the file
+// named by SNN_AUTOTUNE_CACHE if set (lines "key choice", choice = path +
+// 64 JB).  The handle then re-lays out its weights and thresholds for the
+// chosen JB.  SNN_AUTOTUNE=0 skips the measurement and takes the first
+// available path in the order persistent, fused, MFMA, plain with the
+// handle's JB; SNN_JB fixes JB; SNN_AUTOTUNE_VERBOSE=1 reports each
+// candidate's time on stderr.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -40,105 +46,143 @@ void load_file_locked()
     if (!fn) return;
     std::ifstream f(fn);
     std::string key;
-    int path;
-    while (f >> key >> path)
-        if (path >= 0 && path <= 4 && path != SNN_PATH_AUTO) g_table[key] = path;
+    int choice;
+    while (f >> key >> choice)
+        if (choice % 64 >= 0 && choice % 64 <= 4 && choice % 64 != SNN_PATH_AUTO) g_table[key] = choice;
 }
 
-void append_file(const std::string &key, int path)
+void append_file(const std::string &key, int choice)
 {
     const char *fn = std::getenv("SNN_AUTOTUNE_CACHE");
     if (!fn) return;
     std::ofstream f(fn, std::ios::app);
-    f << key << ' ' << path << '\n';
+    f << key << ' ' << choice << '\n';
+}
+
+// Paths whose kernels fit the batch on handle n (the preferred order).
+std::vector<int> candidate_paths(snn_net *n)
+{
+    std::vector<int> cand;
+    if (n->persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
+    if (n->fused_ok()) cand.push_back(SNN_PATH_FUSED);
+    cand.push_back(SNN_PATH_MFMA);
+    cand.push_back(SNN_PATH_PLAIN);
+    return cand;
 }
 
 }  // namespace
 
 int snn_net::choose_path(uint32_t batch, uint32_t T, const uint8_t *images, const uint64_t *ids,
-                         const uint32_t *forced)
+                         const uint32_t *forced, int *jb_io)
 {
-    std::vector<int> cand;
-    if (persist_ok()) cand.push_back(SNN_PATH_PERSISTENT);
-    if (fused_ok()) cand.push_back(SNN_PATH_FUSED);
-    cand.push_back(SNN_PATH_MFMA);
-    cand.push_back(SNN_PATH_PLAIN);
+    const std::vector<int> cand = candidate_paths(this);
     const char *env = std::getenv("SNN_AUTOTUNE");
     const char *venv = std::getenv("SNN_AUTOTUNE_VERBOSE");
     const bool verbose = venv && venv[0] == '1';
-    if (cand.size() == 1 || (env && env[0] == '0')) return cand[0];
+    // column block widths to try: the handle's, and 8, 16 and 32 columns
+    // (only at an episode start, and not when SNN_JB fixes it)
+    std::vector<int> jbs{p.jb};
+    if (jb_io && !std::getenv("SNN_JB"))
+        for (int j : {8, 16, 32})
+            if (j != p.jb && (uint32_t)j <= ((cfg.n_exc + 7) & ~7u)) jbs.push_back(j);
+    if ((cand.size() == 1 && jbs.size() == 1) || (env && env[0] == '0')) return cand[0];
 
     std::ostringstream ks;
     ks << cfg.n_in << 'x' << cfg.n_exc << 'x' << cfg.n_inh << "_l" << cfg.learn << "_r" << cfg.reduce << "_p"
-       << precision << "_jb" << p.jb << "_B" << batch << "_T" << (T < 512u ? T : 512u) << "_g" << use_graphs
-       << "_cu" << cus;
+       << precision << "_jb" << (jb_io ? 0 : p.jb) << "_B" << batch << "_T" << (T < 512u ? T : 512u) << "_g"
+       << use_graphs << "_cu" << cus;
     const std::string key = ks.str();
     {
         std::lock_guard<std::mutex> lk(g_mu);
         load_file_locked();
         auto it = g_table.find(key);
-        if (it != g_table.end())
+        if (it != g_table.end()) {
+            const int path = it->second % 64, jb = it->second / 64;
+            if (jb_io && jb > 0) {
+                *jb_io = jb;
+                return path;
+            }
             for (int c : cand)
-                if (c == it->second) return c;
+                if (c == path) return c;
+        }
     }
 
-    // time each candidate on a scratch copy
+    // the caller's weights and thresholds in row-major form, copied into
+    // each scratch handle in its own block layout
+    std::vector<float> w((size_t)cfg.n_in * cfg.n_exc);
+    std::vector<double> th(cfg.n_exc);
+    int best = cand[0], best_jb = p.jb;
+    float best_ms = 1e30f;
+    if (snn_get_weights(this, w.data(), w.size()) != SNN_OK || snn_get_theta(this, th.data(), th.size()) != SNN_OK)
+        return best;
     snn_config c = cfg;
     c.max_batch = batch;
     c.hbm_budget_bytes = 0;
     c.path = SNN_PATH_PLAIN;
     c.precision = precision;
-    snn_net *tmp = nullptr;
-    int best = cand[0];
-    if (snn_create(&c, stream, &tmp) == SNN_OK && tmp->p.jb == p.jb) {
+    // a short warm-up (code loading, LDS limits), then one episode of the
+    // requested length (at most 512 steps) from a reset, so the bursty first
+    // steps weigh as much as they will in the real run
+    const uint32_t warm = T < 8u ? T : 8u;
+    const uint32_t steps = T < 512u ? T : 512u;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    for (int jb : jbs) {
+        if (!ok) break;
+        snn_net *tmp = nullptr;
+        if (create(&c, stream, jb, &tmp) != SNN_OK) continue;
         tmp->use_graphs = use_graphs;
-        const size_t nw = (size_t)p.n_in_pad * p.n_pad;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        bool ok = hipMemcpyAsync(tmp->W, W, nw * sizeof(float), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-                  hipMemcpyAsync(tmp->theta, theta, (size_t)p.n_pad * sizeof(double), hipMemcpyDeviceToDevice,
-                                 stream) == hipSuccess &&
-                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-        // a short warm-up (code loading, LDS limits), then one episode of
-        // the requested length (at most 512 steps) from a reset, so the
-        // bursty first steps weigh as much as they will in the real run
-        const uint32_t warm = T < 8u ? T : 8u;
-        const uint32_t steps = T < 512u ? T : 512u;
-        float best_ms = 1e30f;
-        for (int cnd : cand) {
-            if (!ok) break;
+        if (tmp->ensure_state(batch) != SNN_OK) {
+            snn_destroy(tmp);
+            continue;
+        }
+        tmp->set_batch(batch);
+        std::vector<int> tc = candidate_paths(tmp);
+        // the plain per-step path is tried at the handle's width only
+        if (jb != p.jb) tc.pop_back();
+        for (int cnd : tc) {
             // every candidate starts from the caller's weights and thresholds
-            ok = hipMemcpyAsync(tmp->W, W, nw * sizeof(float), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-                 hipMemcpyAsync(tmp->theta, theta, (size_t)p.n_pad * sizeof(double), hipMemcpyDeviceToDevice,
-                                stream) == hipSuccess;
-            if (!ok) break;
+            if (snn_set_weights(tmp, w.data(), w.size()) != SNN_OK || snn_set_theta(tmp, th.data(), th.size()) != SNN_OK)
+                break;
             tmp->path = cnd;
             if (tmp->run(images, ids, forced, batch, warm, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
             // with graph replay on, the timed episode replays a captured graph
             if (tmp->use_graphs && tmp->run(images, ids, forced, batch, steps, SNN_RUN_RESET, nullptr) != SNN_OK)
                 continue;
-            if (hipEventRecord(e0, stream) != hipSuccess) break;
+            if (hipEventRecord(e0, stream) != hipSuccess) {
+                ok = false;
+                break;
+            }
             if (tmp->run(images, ids, forced, batch, steps, SNN_RUN_RESET, nullptr) != SNN_OK) continue;
             float ms = 0.f;
             if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                ok = false;
                 break;
+            }
             if (tmp->check_device_error() != SNN_OK) continue;
             if (verbose)
-                std::fprintf(stderr, "snn autotune %s: path %d (ran %d) %.3f ms for %u steps\n", key.c_str(), cnd,
-                             tmp->last_path, ms, steps);
-            if (ms < best_ms) {
-                best_ms = ms;
+                std::fprintf(stderr, "snn autotune %s: path %d jb %d (ran %d) %.3f ms for %u steps\n", key.c_str(),
+                             cnd, jb, tmp->last_path, ms, steps);
+            // a different width must be at least 3 % faster (it costs a
+            // re-layout of the handle)
+            const float eff = jb == p.jb ? ms : 1.03f * ms;
+            if (eff < best_ms) {
+                best_ms = eff;
                 best = cnd;
+                best_jb = jb;
             }
         }
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        snn_destroy(tmp);
     }
-    snn_destroy(tmp);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (jb_io) *jb_io = best_jb;
+    const int choice = best + 64 * (jb_io ? best_jb : 0);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_table[key] = best;
+        g_table[key] = choice;
     }
-    append_file(key, best);
+    append_file(key, choice);
     return best;
 }

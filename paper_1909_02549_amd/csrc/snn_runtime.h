@@ -127,6 +127,11 @@ struct snn_net {
                            uint32_t *counts, const uint8_t *new_mask);
     friend struct snn_server;
     // AUTO: the fastest available execution path for this batch, measured
-    // once on a scratch copy of the network (snn_autotune.hip)
-    int choose_path(uint32_t batch, uint32_t T, const uint8_t *images, const uint64_t *ids, const uint32_t *forced);
+    // once on scratch copies of the network (snn_autotune.hip); with jb
+    // non-null also over column block widths (*jb receives the winner's)
+    int choose_path(uint32_t batch, uint32_t T, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
+                    int *jb = nullptr);
+    static int default_jb(uint32_t n_exc, int cus);
+    static snn_status create(const snn_config *cfg, void *stream, int jb, snn_net **out);
+    snn_status relayout(int jb);
 };

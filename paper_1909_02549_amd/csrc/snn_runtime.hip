@@ -291,7 +291,25 @@ void snn_net::free_state()
     cur_B = 0;
 }
 
+// The column block width a new handle starts with: one block per CU when the
+// layer is large (choose_jb), or the SNN_JB environment override.
+int snn_net::default_jb(uint32_t n_exc, int cus)
+{
+    int jb = choose_jb(n_exc, cus);
+    if (const char *e = std::getenv("SNN_JB")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 32) jb = v;
+    }
+    return jb;
+}
+
 extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **out)
+{
+    return snn_net::create(cfg, stream, 0, out);
+}
+
+// snn_create with the column block width jb (0: default_jb).
+snn_status snn_net::create(const snn_config *cfg, void *stream, int jb, snn_net **out)
 {
     if (!out) return fail(SNN_EINVAL, "out is NULL");
     *out = nullptr;
@@ -303,11 +321,7 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *stream, snn_net **
     n->stream = (hipStream_t)stream;
     HIP_TRY(hipGetDevice(&n->device));
     n->cus = device_cu_count();
-    int jb = choose_jb(cfg->n_exc, n->cus);
-    if (const char *e = std::getenv("SNN_JB")) {
-        const int v = std::atoi(e);
-        if (v >= 1 && v <= 32) jb = v;
-    }
+    if (jb <= 0) jb = default_jb(cfg->n_exc, n->cus);
     fill_dims(n->p, *cfg, jb);
     fill_params(n->p, *cfg);
     n->path = cfg->path;
@@ -408,6 +422,34 @@ extern "C" snn_status snn_get_theta(snn_net *net, double *th, size_t n)
     HIP_TRY(hipStreamSynchronize(net->stream));
     HIP_TRY(hipMemcpy(th, net->theta, n * sizeof(double), hipMemcpyDeviceToHost));
     return SNN_OK;
+}
+
+// Change the column block width to jb: the weights and thresholds keep their
+// values in the new block layout; the per-sample state and the captured
+// graphs are dropped (the next run starts an episode).
+snn_status snn_net::relayout(int jb)
+{
+    if (jb == p.jb) return SNN_OK;
+    std::vector<float> w((size_t)p.n_in * p.n_exc);
+    std::vector<double> th(p.n_exc);
+    snn_status st = snn_get_weights(this, w.data(), w.size());
+    if (st == SNN_OK) st = snn_get_theta(this, th.data(), th.size());
+    if (st != SNN_OK) return st;
+    graphs_invalidate();
+    free_state();
+    (void)hipFree(W);
+    (void)hipFree(theta);
+    W = nullptr;
+    theta = nullptr;
+    fill_dims(p, cfg, jb);
+    const size_t nw = (size_t)p.n_in_pad * p.n_pad;
+    HIP_TRY(hipMalloc(&W, nw * sizeof(float)));
+    HIP_TRY(hipMalloc(&theta, (size_t)p.n_pad * sizeof(double)));
+    HIP_TRY(hipMemset(W, 0, nw * sizeof(float)));
+    HIP_TRY(hipMemset(theta, 0, (size_t)p.n_pad * sizeof(double)));
+    st = snn_set_weights(this, w.data(), w.size());
+    if (st == SNN_OK) st = snn_set_theta(this, th.data(), th.size());
+    return st;
 }
 
 extern "C" snn_status snn_stdp_reduce(snn_net *net, int32_t mode)
@@ -659,9 +701,20 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
         o.v_exc = out->v_exc;
         o.v_inh = out->v_inh;
     }
-    const bool reset = batch != cur_B || (flags & SNN_RUN_RESET);
+    bool reset = batch != cur_B || (flags & SNN_RUN_RESET);
     set_batch(batch);
-    const int path = this->path == SNN_PATH_AUTO ? choose_path(batch, T, images, ids, forced) : this->path;
+    int path = this->path;
+    if (path == SNN_PATH_AUTO) {
+        // an episode start may also change the column block width
+        int jb = p.jb;
+        path = choose_path(batch, T, images, ids, forced, reset ? &jb : nullptr);
+        if (jb != p.jb) {
+            st = relayout(jb);
+            if (st == SNN_OK) st = ensure_state(batch);
+            if (st != SNN_OK) return st;
+            reset = true;
+        }
+    }
     set_batch(batch);
     if (reset && use_graphs && !prof) return run_graph(path, images, ids, forced, batch, T, o);
     if (reset) {

@@ -229,7 +229,7 @@ extern "C" snn_status snn_serve_create(snn_net *frozen, uint32_t max_slots, uint
         delete sv;
         return snn_net::error(SNN_EDEVICE, "serving stream");
     }
-    snn_status st = snn_create(&c, sv->stream, &sv->net);
+    snn_status st = snn_net::create(&c, sv->stream, frozen->p.jb, &sv->net);
     if (st != SNN_OK) {
         delete sv;
         return st;
