@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SNN_ABI_VERSION 1u
+#define SNN_ABI_VERSION 2u
 
 typedef struct snn_net snn_net;       /* opaque network + state handle */
 typedef struct snn_server snn_server; /* opaque serving loop handle    */
@@ -52,17 +52,29 @@ typedef enum {
 
 /* Batch reduction of per-sample parameter updates (Reduction methods
  * section: averaging by default, summation, per-synapse maximum per step as
- * in the unsupervised-learning experiment).  MAX keeps the largest
- * potentiation and, separately, the largest depression of each synapse;
- * MAX_SIGNED (a variant) adds the largest per-sample change
- * nu_post P_b - nu_pre D_b, which is 0 for a sample with no spike on the
- * synapse.  Theta uses the maximum for both.  MAX_SIGNED runs on the PLAIN
- * and MFMA paths (the FUSED and PERSISTENT paths fall back to PLAIN). */
+ * in the unsupervised-learning experiment; the section leaves the choice of
+ * reduction to the user).  Each reduces, per synapse, the B per-sample
+ * potentiation terms P_b = s_post[b] x_pre[b] and, separately, the B
+ * depression terms D_b = s_pre[b] x_post[b], then
+ * w <- clamp(w + nu_post R(P) - nu_pre R(D)).
+ *   SUM, MEAN   sum over b, and the sum / B;
+ *   MAX         the largest term;
+ *   SOFT_MAX    a family between MEAN and MAX: the log-mean-exp with
+ *               temperature tau, R(z) = tau log((1/B) sum_b exp(z_b / tau)),
+ *               which tends to the mean as tau grows and to the maximum as
+ *               tau tends to 0 (tau from snn_config.reduce_tau or
+ *               snn_stdp_reduce_soft);
+ *   MAX_SIGNED  (a variant) w <- clamp(w + max_b (nu_post P_b - nu_pre D_b)),
+ *               the largest per-sample change, 0 for a sample with no spike
+ *               on the synapse.
+ * Theta's increment is reduced the same way over the spike indicators
+ * (MAX_SIGNED: the maximum).  Every path computes every reduction. */
 typedef enum {
     SNN_REDUCE_SUM = 0,
     SNN_REDUCE_MEAN = 1,
     SNN_REDUCE_MAX = 2,
-    SNN_REDUCE_MAX_SIGNED = 3
+    SNN_REDUCE_MAX_SIGNED = 3,
+    SNN_REDUCE_SOFT_MAX = 4
 } snn_reduce;
 
 /* Operand form of the two contractions of a step (the synaptic current and
@@ -85,8 +97,9 @@ typedef enum { SNN_FP32 = 0, SNN_BF16 = 1, SNN_FP8_E4M3 = 2 } snn_precision;
  *   PERSISTENT one cooperative launch for all T steps, state kept on chip;
  *   AUTO       chosen by the library's autotuner for (batch, T, precision);
  *   MFMA       per-step launches with the synaptic current and the STDP
- *              outer products over the batch on the matrix cores (max
- *              reduction keeps the gather plasticity kernel). */
+ *              outer products over the batch on the matrix cores (sum and
+ *              mean; the other reductions keep the gather plasticity
+ *              kernel of PLAIN). */
 typedef enum {
     SNN_PATH_PLAIN = 0,
     SNN_PATH_FUSED = 1,
@@ -128,6 +141,12 @@ typedef struct {
                                       cheaper variant, on every path);
                                       0: after every learning step            */
     uint64_t hbm_budget_bytes;     /* 0: no limit                                   */
+    double reduce_tau;             /* temperature of SNN_REDUCE_SOFT_MAX: finite and
+                                      at least x_max / 64, x_max the largest trace
+                                      value (1 for nearest-spike traces,
+                                      1 / (1 - lambda) for additive ones, lambda the
+                                      slower of the two trace decays per step);
+                                      ignored by the other reductions          */
 } snn_config;
 
 /* Device outputs of snn_run; any NULL pointer is skipped.
@@ -177,8 +196,17 @@ snn_status snn_get_theta(snn_net *net, double *theta_host, size_t n);
 
 /* Select the batch reduction of weight and threshold updates (Reduction
  * methods section), a snn_reduce value.  Takes effect at the next step.
- * SNN_EINVAL for a NULL handle or a mode outside snn_reduce. */
+ * SNN_REDUCE_SOFT_MAX keeps the handle's temperature (snn_config.reduce_tau
+ * or the last snn_stdp_reduce_soft).  SNN_EINVAL for a NULL handle, a mode
+ * outside snn_reduce, or SOFT_MAX with a temperature out of range. */
 snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
+
+/* Select the soft-maximum reduction (SNN_REDUCE_SOFT_MAX) with temperature
+ * tau (Reduction methods section: a user-chosen reduction of the batch
+ * dimension; this family spans the mean and the maximum the section
+ * compares).  Takes effect at the next step.  SNN_EINVAL for a NULL handle
+ * or a tau that is not finite or below x_max / 64 (snn_config.reduce_tau). */
+snn_status snn_stdp_reduce_soft(snn_net *net, double tau);
 
 /* Select the execution path (snn_path) and the operand form of the
  * contractions (snn_precision).  SNN_EINVAL for values out of range. */

@@ -36,7 +36,8 @@ class _Config(C.Structure):
                 ("exc", _Lif), ("inh", _Lif), ("w_ei", C.c_double), ("w_ie", C.c_double),
                 ("nu_pre", C.c_double), ("nu_post", C.c_double), ("tau_pre_ms", C.c_double),
                 ("tau_post_ms", C.c_double), ("w_min", C.c_double), ("w_max", C.c_double),
-                ("norm", C.c_double), ("seed", C.c_uint64), ("norm_per_run", C.c_int32)]
+                ("norm", C.c_double), ("seed", C.c_uint64), ("norm_per_run", C.c_int32),
+                ("reduce_tau", C.c_double)]
 
 
 _lib = None
@@ -84,6 +85,7 @@ def make_config(cfg: dict, precision=0) -> _Config:
         setattr(c, k, float(cfg[k]))
     c.seed = int(cfg["seed"])
     c.norm_per_run = int(cfg.get("norm_per_run", 0))
+    c.reduce_tau = float(cfg.get("reduce_tau", 1.0))
     for layer in ("exc", "inh"):
         L = getattr(c, layer)
         p = cfg[layer]

@@ -20,7 +20,9 @@
  *     (Unsupervised Learning section);
  *   - online STDP from nearest-spike traces, reduced over the batch by sum,
  *     mean or per-synapse maximum (Reduction methods section; Fig. 3 text),
- *     or by the signed maximum of the per-sample changes (a variant),
+ *     by the signed maximum of the per-sample changes (a variant), or by the
+ *     soft maximum tau log((1/B) sum_b exp(z_b / tau)) (a user-chosen
+ *     reduction, which the section allows, between the mean and the max),
  *     clamp to [w_min, w_max] and per-column normalisation to a fixed sum
  *     (Unsupervised Learning section).
  * Readings of points the paper leaves open are listed in the design notes:
@@ -102,7 +104,7 @@ typedef struct {
 typedef struct {
     int32_t n_in, n_exc, n_inh;      /* n_inh = 0: no inhibitory layer      */
     int32_t uniform_rate, learn;     /* uniform_rate: every input max_rate  */
-    int32_t trace_additive, reduce;  /* reduce: 0 sum, 1 mean, 2 max, 3 signed max */
+    int32_t trace_additive, reduce;  /* reduce: 0 sum, 1 mean, 2 max, 3 signed max, 4 soft max */
     int32_t precision;               /* operand rounding, see orc_quantize  */
     double dt_ms, max_rate_hz;
     orc_lif exc, inh;
@@ -110,6 +112,7 @@ typedef struct {
     double nu_pre, nu_post, tau_pre_ms, tau_post_ms, w_min, w_max, norm;
     uint64_t seed;
     int32_t norm_per_run;            /* 1: normalise after a run's last step only */
+    double reduce_tau;               /* temperature of the soft maximum (reduce 4) */
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -164,9 +167,16 @@ uint32_t orc_threshold(const orc_config *c, int pixel)
     return (uint32_t)thr;
 }
 
-/* The batch reduction of one synapse's (or neuron's) B contributions. */
-static double reduce_terms(const double *terms, int B, int mode)
+/* The batch reduction of one synapse's (or neuron's) B contributions:
+ * sum, mean, maximum, or (mode 4) the soft maximum with temperature tau,
+ * tau log((1/B) sum_b exp(terms[b] / tau)) (the log-mean-exp). */
+static double reduce_terms(const double *terms, int B, int mode, double tau)
 {
+    if (mode == 4) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += exp(terms[b] / tau);
+        return tau * log(s / (double)B);
+    }
     if (mode == 2) {
         double m = terms[0];
         for (int b = 1; b < B; ++b)
@@ -329,7 +339,9 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
              * the post trace; each reduced over the batch on its own, visiting
              * the samples in order b = 0 .. B-1.  Signed max (mode 3) instead
              * takes, per synapse, the largest of the B per-sample changes
-             * nu_post tp - nu_pre td (0 for a sample with neither spike). */
+             * nu_post tp - nu_pre td (0 for a sample with neither spike).  The
+             * soft maximum (mode 4) sums exp(term / tau) over all B terms,
+             * zeros included, and takes tau log(sum / B). */
 #pragma omp parallel
             {
                 double *P = malloc(sizeof(double) * (size_t)n_exc);
@@ -349,6 +361,10 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                                 double dw = c->nu_post * tp - c->nu_pre * td;
                                 if (b == 0 || dw > M[j]) M[j] = dw;
                             }
+                            if (c->reduce == 4) {
+                                tp = exp(tp / c->reduce_tau);
+                                td = exp(td / c->reduce_tau);
+                            }
                             if (b == 0) {
                                 P[j] = tp;
                                 D[j] = td;
@@ -364,6 +380,10 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                     for (int j = 0; j < n_exc; ++j) {
                         double Pj = c->reduce == 1 ? P[j] / (double)B : P[j];
                         double Dj = c->reduce == 1 ? D[j] / (double)B : D[j];
+                        if (c->reduce == 4) {
+                            Pj = c->reduce_tau * log(P[j] / (double)B);
+                            Dj = c->reduce_tau * log(D[j] / (double)B);
+                        }
                         double w = c->reduce == 3 ? W[(size_t)i * n_exc + j] + M[j]
                                                   : W[(size_t)i * n_exc + j] + c->nu_post * Pj - c->nu_pre * Dj;
                         if (w < c->w_min) w = c->w_min;
@@ -396,7 +416,8 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
                 double *terms = malloc(sizeof(double) * (size_t)B);
                 for (int j = 0; j < n_exc; ++j) {
                     for (int b = 0; b < B; ++b) terms[b] = (double)s_exc[(size_t)b * n_exc + j];
-                    theta[j] += c->exc.theta_plus * reduce_terms(terms, B, c->reduce == 3 ? 2 : c->reduce);
+                    theta[j] += c->exc.theta_plus * reduce_terms(terms, B, c->reduce == 3 ? 2 : c->reduce,
+                                                                 c->reduce_tau);
                 }
                 free(terms);
             }

@@ -45,6 +45,7 @@ struct Params {
     float w_ei, w_ie;
     float lam_pre, lam_post, nu_pre, nu_post, w_min, w_max;
     float inv_B;
+    float itau2_r, tau_ln2_r; // soft-maximum reduction: log2(e) / temperature, temperature * ln(2)
     double norm, beta, theta_plus, inv_Bd;
     uint64_t seed;
 };
@@ -65,6 +66,17 @@ struct Outs {
     float *v_inh;          // T x B x n_exc
 };
 
-enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2, RED_MAX_SIGNED = 3 };
+enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2, RED_MAX_SIGNED = 3, RED_SOFT = 4 };
+
+// Reduction kind a plasticity kernel is compiled for: sum, mean and max
+// (chosen at run time from Params::reduce), the soft maximum (the traces
+// enter as expm1(x / tau), the reduced sums leave through tau log1p(S / B)),
+// or the signed maximum of the per-sample changes.
+enum RedKind { RK_STD = 0, RK_SOFT = 1, RK_SIGNED = 2 };
+
+__host__ __device__ constexpr int red_kind(int reduce)
+{
+    return reduce == RED_SOFT ? RK_SOFT : reduce == RED_MAX_SIGNED ? RK_SIGNED : RK_STD;
+}
 
 }  // namespace snn

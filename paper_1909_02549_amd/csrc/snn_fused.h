@@ -100,9 +100,9 @@ struct PersistArgs {
 
 size_t fused_lds_bytes(const Params &p);
 size_t persist_lds_bytes(const Params &p);
-template <int PREC>
+template <int PREC, int RK>
 __global__ void k_fused_step(Params p, FusedArgs a, StepPtrs s);
-template <int PREC>
+template <int PREC, int RK>
 __global__ void k_persist(const PersistArgs args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
@@ -225,8 +225,32 @@ __device__ __forceinline__ float4 round4(int prec, float4 v)
                        operand_value(prec, v.w));
 }
 
+// A trace value as a summand of the reduction of kind RK (the soft maximum's
+// exp(x / tau) - 1, else x), and the reduced sum S as the change it makes
+// (tau log1p(S / B) for the soft maximum, S / B for the mean, else S).
+template <int RK>
+__device__ __forceinline__ float red_in(float x, float k)
+{
+    return RK == RK_SOFT ? soft_term(x, k) : x;
+}
+
+template <int RK>
+__device__ __forceinline__ float4 red_in4(float4 v, float k)
+{
+    if (RK != RK_SOFT) return v;
+    return make_float4(soft_term(v.x, k), soft_term(v.y, k), soft_term(v.z, k), soft_term(v.w, k));
+}
+
+template <int RK>
+__device__ __forceinline__ float red_out(const Params &p, float S)
+{
+    if (RK == RK_SOFT) return soft_value(p, S);
+    return p.reduce == RED_MEAN ? S * p.inv_B : S;
+}
+
+template <int RK = RK_STD>
 __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const float *rows, int jbp, int c0, int zero_row,
-                                            int mode, float *acc, int prec)
+                                            int mode, float *acc, int prec, float ksoft = 0.f)
 {
     const int i0 = (int)(q.x & 0xFFFFu);
     const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
@@ -238,10 +262,10 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
     const float4 *r1 = reinterpret_cast<const float4 *>(rows + __mul24(i1, jbp) + c0);
     const float4 *r2 = reinterpret_cast<const float4 *>(rows + __mul24(i2, jbp) + c0);
     const float4 *r3 = reinterpret_cast<const float4 *>(rows + __mul24(i3, jbp) + c0);
-    const float4 a0 = round4(prec, r0[0]), b0 = round4(prec, r0[1]);
-    const float4 a1 = round4(prec, r1[0]), b1 = round4(prec, r1[1]);
-    const float4 a2 = round4(prec, r2[0]), b2 = round4(prec, r2[1]);
-    const float4 a3 = round4(prec, r3[0]), b3 = round4(prec, r3[1]);
+    const float4 a0 = red_in4<RK>(round4(prec, r0[0]), ksoft), b0 = red_in4<RK>(round4(prec, r0[1]), ksoft);
+    const float4 a1 = red_in4<RK>(round4(prec, r1[0]), ksoft), b1 = red_in4<RK>(round4(prec, r1[1]), ksoft);
+    const float4 a2 = red_in4<RK>(round4(prec, r2[0]), ksoft), b2 = red_in4<RK>(round4(prec, r2[1]), ksoft);
+    const float4 a3 = red_in4<RK>(round4(prec, r3[0]), ksoft), b3 = red_in4<RK>(round4(prec, r3[1]), ksoft);
     if (mode == RED_MAX) {
         red4(mode, acc, a0), red4(mode, acc + 4, b0);
         red4(mode, acc, a1), red4(mode, acc + 4, b1);
@@ -258,9 +282,9 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
 // The entries k0 .. cnt of a list (k0 a multiple of 4), 4 * NW at a time:
 // the NW 8-byte list words of a batch are loaded together, then gathered in
 // list order (the additions are those of a one-word-at-a-time walk).
-template <int NW = 4>
+template <int NW = 4, int RK = RK_STD>
 __device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0, int cnt, const float *rows, int jbp,
-                                            int c0, int zero_row, int mode, float *acc, int prec)
+                                            int c0, int zero_row, int mode, float *acc, int prec, float ksoft = 0.f)
 {
     for (; k0 < cnt; k0 += 4 * NW) {
         uint2 e[NW];
@@ -268,7 +292,8 @@ __device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0
         for (int q = 0; q < NW; ++q) e[q] = k0 + 4 * q < cnt ? l4[(k0 >> 2) + q] : make_uint2(0u, 0u);
 #pragma unroll
         for (int q = 0; q < NW; ++q)
-            if (k0 + 4 * q < cnt) gather4rows(e[q], k0 + 4 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+            if (k0 + 4 * q < cnt)
+                gather4rows<RK>(e[q], k0 + 4 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft);
     }
 }
 
@@ -277,17 +302,18 @@ __device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0
 // time, q the operand rounding of the precision `prec` (none for FP32);
 // slots past cnt read row `zero_row` (all zeros).  The first `nhead` (4 or
 // 8) entries are passed in registers (head0, head1), loaded ahead of time.
+template <int RK = RK_STD>
 __device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int cnt, uint2 head0, uint2 head1,
                                         int nhead, const float *rows, int jbp, int c0, int zero_row, int mode,
-                                        float *acc, int prec)
+                                        float *acc, int prec, float ksoft = 0.f)
 {
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
     if (cnt <= 0) return;
     const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
-    gather4rows(head0, 0, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
-    if (cnt > 4) gather4rows(nhead == 8 ? head1 : l4[1], 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
-    gather_tail(l4, 8, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    gather4rows<RK>(head0, 0, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft);
+    if (cnt > 4) gather4rows<RK>(nhead == 8 ? head1 : l4[1], 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft);
+    gather_tail<4, RK>(l4, 8, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft);
 }
 
 // The same with the first 8 * NH entries of the list in h[0 .. NH) (16-byte
@@ -418,7 +444,7 @@ __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, 
 // The x_pre values of the first XR spiking samples are loaded once into
 // registers (all in flight together) and reused by every column group; each
 // group walks the sample list for its depression sums.
-template <bool Coherent, int XR>
+template <bool Coherent, int XR, int RK = RK_STD>
 __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds &S, int i, int cnt, uint4 head,
                                                   const uint16_t *ltrow, const float *xpre, int ucnt, uint32_t colany,
                                                   int prec, int prec_d)
@@ -433,7 +459,7 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
         if (v < ucnt) {
             const int b = (int)S.ulist[v];
             cm[v] = S.colmask[b];
-            if (cm[v]) x[v] = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+            if (cm[v]) x[v] = red_in<RK>(operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i)), p.itau2_r);
         }
     }
     for (int cg = 0; cg < ncg; ++cg) {
@@ -458,23 +484,24 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
                 const int b = (int)S.ulist[u];
                 const uint32_t m = (S.colmask[b] >> c0) & 0xFFu;
                 if (!m) continue;
-                const float xv = operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i));
+                const float xv = red_in<RK>(operand_value(prec, ld_x<Coherent>(xpre + (size_t)b * p.n_in_pad + i)),
+                                            p.itau2_r);
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if ((m >> c) & 1u) P[c] = reduce2(p.reduce, P[c], xv);
             }
         }
         float D[8];
-        gather8(ltrow, cnt, make_uint2(head.x, head.y), make_uint2(head.z, head.w), 8, S.xpost, p.ls, c0, p.B,
-                p.reduce, D, prec_d);
+        gather8<RK>(ltrow, cnt, make_uint2(head.x, head.y), make_uint2(head.z, head.w), 8, S.xpost, p.ls, c0, p.B,
+                    p.reduce, D, prec_d, p.itau2_r);
         float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
         const float4 w0 = wr[0], w1 = wr[1];
         float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             float xw = w[c] * S.scalef[c0 + c];
-            if ((grp >> c) & 1u) xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[c] * p.inv_B : P[c]);
-            const float d = p.reduce == RED_MEAN ? D[c] * p.inv_B : D[c];
+            if ((grp >> c) & 1u) xw = xw + p.nu_post * red_out<RK>(p, P[c]);
+            const float d = red_out<RK>(p, D[c]);
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
         }
         wr[0] = make_float4(w[0], w[1], w[2], w[3]);
@@ -488,7 +515,7 @@ __device__ __forceinline__ void plasticity_row_cg(const Params &p, const StepLds
 // taken 8 listed spiking samples at a time: sample numbers and column masks
 // are the same in every lane (scalar branches); the 8 x_pre loads go out
 // together, the first 8 before the depression walk, which hides them.
-template <bool Coherent, int NH>
+template <bool Coherent, int NH, int RK = RK_STD>
 __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepLds &S, int i, int cg0, int ng,
                                                     int cnt, const uint4 *h, const uint16_t *ltrow, const float *xpre,
                                                     int ucnt, uint32_t pdone, int prec, int prec_d)
@@ -523,7 +550,7 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
         for (int v = 0; v < 8; ++v) {
             const uint32_t m = m8[v];
             if (m) {
-                const float xv = operand_value(prec, x8[v]);
+                const float xv = red_in<RK>(operand_value(prec, x8[v]), p.itau2_r);
 #pragma unroll
                 for (int c = 0; c < 16; ++c)
                     if ((m >> c) & 1u) P[c >> 3][c & 7] = reduce2(p.reduce, P[c >> 3][c & 7], xv);
@@ -537,7 +564,9 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
             const uint2 e = (q & 1) ? make_uint2(h[q >> 1].z, h[q >> 1].w) : make_uint2(h[q >> 1].x, h[q >> 1].y);
 #pragma unroll
             for (int g = 0; g < 2; ++g)
-                if (g < ng) gather4rows(e, 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
+                if (g < ng)
+                    gather4rows<RK>(e, 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d,
+                                    p.itau2_r);
         }
     }
     // list entries past the head, 8 at a time (two list words loaded
@@ -553,7 +582,8 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 #pragma unroll
             for (int g = 0; g < 2; ++g)
                 if (g < ng)
-                    gather4rows(e[q], k0 + 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g], prec_d);
+                    gather4rows<RK>(e[q], k0 + 4 * q, cnt, S.xpost, p.ls, 8 * (cg0 + g), p.B, p.reduce, D[g],
+                                    prec_d, p.itau2_r);
         }
     }
     if (ucnt > 0) {
@@ -573,8 +603,8 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             float xw = ((pdone >> (c0 + c)) & 1u) ? w[c] : w[c] * S.scalef[c0 + c];
-            xw = xw + p.nu_post * (p.reduce == RED_MEAN ? P[g][c] * p.inv_B : P[g][c]);
-            const float d = p.reduce == RED_MEAN ? D[g][c] * p.inv_B : D[g][c];
+            xw = xw + p.nu_post * red_out<RK>(p, P[g][c]);
+            const float d = red_out<RK>(p, D[g][c]);
             w[c] = fminf(fmaxf(xw - p.nu_pre * d, p.w_min), p.w_max);
         }
         wr[0] = make_float4(w[0], w[1], w[2], w[3]);
@@ -595,7 +625,7 @@ __device__ __forceinline__ void plasticity_row_half(const Params &p, const StepL
 // One 32-row tile rt of the potentiation product (one wave; lane = lane index).
 // With Pre, x0 holds this lane's x_pre operands of the first 32 listed
 // samples, loaded ahead of time (tile_loads); later chunks are loaded here.
-template <bool Coherent, bool Pre = false>
+template <bool Coherent, bool Pre = false, int RK = RK_STD>
 __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds &S, const float *xpre, int ucnt,
                                                   uint32_t colany, int prec, int rt, int lane,
                                                   const float (*x0)[8] = nullptr)
@@ -627,11 +657,14 @@ __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds
             if (k0 + 16 * h >= ucnt) break;
             const uint4 bop = ones_bf16(bits[h]);
             uint32_t c0[8], c1[8], c2[8];
+            // the soft maximum's summands are FP32 values off the forms' grids:
+            // three exact bfloat16 parts in every form
+            const bool three = prec == PREC_FP32 || RK == RK_SOFT;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                if (prec == PREC_FP32) {
+                if (three) {
                     uint32_t c[3];
-                    split<PREC_FP32>(x[h][e], c);
+                    split<PREC_FP32>(red_in<RK>(operand_value(prec, x[h][e]), p.itau2_r), c);
                     c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
                 } else {
                     c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
@@ -641,7 +674,7 @@ __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds
             const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
                                         c0[6] | (c0[7] << 16));
             acc = mfma<PREC_BF16>(a0, bop, acc);
-            if (prec == PREC_FP32) {
+            if (three) {
                 const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16),
                                             c1[4] | (c1[5] << 16), c1[6] | (c1[7] << 16));
                 const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16),
@@ -659,52 +692,15 @@ __device__ __forceinline__ void potentiation_tile(const Params &p, const StepLds
             const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
             if (i < p.n_in) {
                 float *w = S.W + i * p.ls + col;
-                *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
+                *w = *w * sc + p.nu_post * red_out<RK>(p, acc[r]);
             }
         }
     }
-}
-
-// One 16-sample K chunk pair of the potentiation product on the matrix cores:
-// x[h][e] are this lane's operands (sample 16 h + 8 (lane / 32) + e of the
-// chunk pair, at the lane's row), bits[h] the spike bits of those samples
-// at the lane's column; hn of the two halves hold listed samples.
-__device__ __forceinline__ f32x16_t potentiation_chunk(const float (&x)[2][8], const uint32_t (&bits)[2], int hn,
-                                                       int prec, f32x16_t acc)
-{
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h >= hn) break;
-        const uint4 bop = ones_bf16(bits[h]);
-        uint32_t c0[8], c1[8], c2[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (prec == PREC_FP32) {
-                uint32_t c[3];
-                split<PREC_FP32>(x[h][e], c);
-                c0[e] = c[0], c1[e] = c[1], c2[e] = c[2];
-            } else {
-                c0[e] = bf16_code(operand_value(prec, x[h][e]));  // exact: the form's grid fits bfloat16
-                c1[e] = c2[e] = 0u;
-            }
-        }
-        const uint4 a0 = make_uint4(c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c0[4] | (c0[5] << 16),
-                                    c0[6] | (c0[7] << 16));
-        acc = mfma<PREC_BF16>(a0, bop, acc);
-        if (prec == PREC_FP32) {
-            const uint4 a1 = make_uint4(c1[0] | (c1[1] << 16), c1[2] | (c1[3] << 16), c1[4] | (c1[5] << 16),
-                                        c1[6] | (c1[7] << 16));
-            const uint4 a2 = make_uint4(c2[0] | (c2[1] << 16), c2[2] | (c2[3] << 16), c2[4] | (c2[5] << 16),
-                                        c2[6] | (c2[7] << 16));
-            acc = mfma<PREC_BF16>(a1, bop, acc);
-            acc = mfma<PREC_BF16>(a2, bop, acc);
-        }
-    }
-    return acc;
 }
 
 // w <- w * scale + nu_post * P for the fired column of this lane in tile rt
 // (accumulator r: row 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile).
+template <int RK = RK_STD>
 __device__ __forceinline__ void potentiation_write(const Params &p, const StepLds &S, const f32x16_t &acc, int rt,
                                                    int lane, bool fired_col)
 {
@@ -716,7 +712,7 @@ __device__ __forceinline__ void potentiation_write(const Params &p, const StepLd
         const int i = rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
         if (i < p.n_in) {
             float *w = S.W + i * p.ls + col;
-            *w = *w * sc + p.nu_post * (p.reduce == RED_MEAN ? acc[r] * p.inv_B : acc[r]);
+            *w = *w * sc + p.nu_post * red_out<RK>(p, acc[r]);
         }
     }
 }
@@ -733,7 +729,7 @@ __device__ __forceinline__ void potentiation_write(const Params &p, const StepLd
 // overlaps the previous one's work.  Lane l takes the listed samples of
 // parity l / 32 of a chunk (8 per chunk); the samples of the first chunk
 // and their spike bits at the lane's column are read from LDS once.
-template <bool Coherent>
+template <bool Coherent, int RK = RK_STD>
 __device__ __forceinline__ void potentiation_pipe(const Params &p, const StepLds &S, const float *xpre, int ucnt,
                                                   uint32_t colany, int prec, int tid, int nt)
 {
@@ -798,11 +794,11 @@ __device__ __forceinline__ void potentiation_pipe(const Params &p, const StepLds
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (j >= npair) break;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(operand_value(prec, cur[j]), (bits >> j) & 1u ? 1.f : 0.f,
-                                                       acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(red_in<RK>(operand_value(prec, cur[j]), p.itau2_r),
+                                                       (bits >> j) & 1u ? 1.f : 0.f, acc, 0, 0, 0);
         }
         if (cn == 0 || !more) {
-            potentiation_write(p, S, acc, rt, lane, fired_col);
+            potentiation_write<RK>(p, S, acc, rt, lane, fired_col);
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = 0.f;
         }
@@ -815,12 +811,13 @@ __device__ __forceinline__ void potentiation_pipe(const Params &p, const StepLds
     }
 }
 
-template <bool Coherent>
+template <bool Coherent, int RK = RK_STD>
 __device__ __forceinline__ void potentiation_mfma(const Params &p, const StepLds &S, const float *xpre, int ucnt,
                                                   uint32_t colany, int prec, int tid, int nt)
 {
     const int nrt = (p.n_in + 31) >> 5;
-    for (int rt = tid >> 6; rt < nrt; rt += nt >> 6) potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, tid & 63);
+    for (int rt = tid >> 6; rt < nrt; rt += nt >> 6)
+        potentiation_tile<Coherent, false, RK>(p, S, xpre, ucnt, colany, prec, rt, tid & 63);
 }
 
 // The loads one 32-row tile's depression items start from (lane l: row
@@ -854,7 +851,7 @@ __device__ __forceinline__ void tile_loads(const Params &p, const uint16_t *lt, 
 // work (Pipe; otherwise after it), so their latency overlaps the current
 // tile's potentiation (whose own x_pre loads go out at its start) and
 // depression.
-template <bool Coherent, int NH, bool Pipe>
+template <bool Coherent, int NH, bool Pipe, int RK = RK_STD>
 __device__ __forceinline__ void plasticity_tiles(const Params &p, const StepLds &S, const uint16_t *lt,
                                                  const uint32_t *ct, const float *xpre, int ucnt, uint32_t colany,
                                                  int tid, int nt, int prec, int prec_d)
@@ -872,15 +869,15 @@ __device__ __forceinline__ void plasticity_tiles(const Params &p, const StepLds 
         const int rn = rt + nw;
         if (Pipe && rn < nrt) tile_loads<NH>(p, lt, ct, rn, lane, rn * 32 + (lane & 31) < p.n_in && ng > 0, nxt);
         if (ucnt > 0) {
-            potentiation_tile<Coherent>(p, S, xpre, ucnt, colany, prec, rt, lane);
+            potentiation_tile<Coherent, false, RK>(p, S, xpre, ucnt, colany, prec, rt, lane);
             // the tile's weights, written by other lanes of this wave
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (item)
-            plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cur.cnt, cur.h, lt + (size_t)i * p.lt_stride,
-                                              xpre, 0, colany, prec, prec_d);
+            plasticity_row_half<Coherent, NH, RK>(p, S, i, cg0, ng, (int)cur.cnt, cur.h,
+                                                  lt + (size_t)i * p.lt_stride, xpre, 0, colany, prec, prec_d);
         if (Pipe)
             cur = nxt;
         else if (rn < nrt)
@@ -902,23 +899,146 @@ __device__ __forceinline__ int item_rank(int q, int nrow)
     return (blk << 6) | (q & 63);
 }
 
+// Phase C for the signed maximum, row i, column groups [cg0, cg0 + ng):
+// per synapse the largest per-sample change
+//   M[i, c] = max over b of nu_post q(x_pre[b, i]) s_post[b, c]
+//                           - nu_pre q(x_post[b, c]) s_pre[b, i],
+// 0 for a sample with neither spike, then w <- clamp(w * scale[c] + M[i, c]).
+// The samples fall in three sets: those whose neuron c fired (among the
+// listed samples; their terms are taken one by one, with the pre spike bit
+// of (b, i)), those in which only input i fired (depression-only terms, never
+// positive when nu_pre >= 0), and the rest, which give the zero term unless
+// the first two sets cover the batch.  Input i's sample list is walked only
+// when they might (its length plus the listed samples reach B) or when a
+// depression-only term can be positive (nu_pre < 0); otherwise the zero term
+// stands for all of them.  The listed samples and their column masks are
+// the same in every lane (cg0 is uniform per wave): scalar branches.
+template <bool Coherent>
+__device__ __forceinline__ void plasticity_signed_row(const Params &p, const StepLds &S, int i, int cg0, int ng,
+                                                      int cnt, const uint16_t *ltrow, const uint32_t *bits_t,
+                                                      const float *xpre, int ucnt, int prec, int prec_d)
+{
+    float M[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) M[c] = -INFINITY;
+    const uint32_t *brow = bits_t + (i >> 5);
+    const uint32_t ib = 1u << (i & 31);
+    for (int u0 = 0; u0 < ucnt; u0 += 8) {
+        uint32_t b8[8], m8[8], w8[8];
+        float x8[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int u = u0 + v;
+            b8[v] = u < ucnt ? S.ulist[u] : 0u;
+            m8[v] = __builtin_amdgcn_readfirstlane(u < ucnt ? (S.colmask[b8[v]] >> (8 * cg0)) & 0xFFFFu : 0u);
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            x8[v] = 0.f;
+            w8[v] = 0u;
+            if (m8[v]) {
+                x8[v] = ld_x<Coherent>(xpre + (size_t)b8[v] * p.n_in_pad + i);
+                w8[v] = brow[(size_t)b8[v] * p.in_words];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const uint32_t m = m8[v];
+            if (!m) continue;
+            const float pot = p.nu_post * operand_value(prec, x8[v]);
+            const bool pre = (w8[v] & ib) != 0u;
+            const float *xq = S.xpost + b8[v] * p.ls + 8 * cg0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if ((m >> c) & 1u) M[c] = fmaxf(M[c], pre ? pot - p.nu_pre * operand_value(prec_d, xq[c]) : pot);
+        }
+    }
+    const bool walk = cnt + ucnt >= p.B || (p.nu_pre < 0.f && cnt > 0);
+    if (walk) {
+        // per column: the samples with a spike at input i or neuron col, and
+        // the depression-only terms, exactly (rare: a loop, not unrolled)
+        for (int c = 0; c < 8 * ng; ++c) {
+            const int col = 8 * cg0 + c;
+            const uint32_t *sp = S.spk + col * p.bwords;
+            int both = 0, qc = 0;
+            for (int w = 0; w < p.bwords; ++w) qc += __builtin_popcount(sp[w]);
+            float dn = -INFINITY;
+            for (int k = 0; k < cnt; ++k) {
+                const int b = ltrow[k];
+                if ((sp[b >> 5] >> (b & 31)) & 1u)
+                    ++both;
+                else
+                    dn = fmaxf(dn, -p.nu_pre * operand_value(prec_d, S.xpost[b * p.ls + col]));
+            }
+            const float z = cnt + qc - both < p.B ? fmaxf(dn, 0.f) : dn;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                if (cc == c) M[cc] = fmaxf(M[cc], z);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) M[c] = fmaxf(M[c], 0.f);
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if (g >= ng) break;
+        const int c0 = 8 * (cg0 + g);
+        float4 *wr = reinterpret_cast<float4 *>(S.W + i * p.ls + c0);
+        const float4 w0 = wr[0], w1 = wr[1];
+        float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) w[c] = fminf(fmaxf(w[c] * S.scalef[c0 + c] + M[8 * g + c], p.w_min), p.w_max);
+        wr[0] = make_float4(w[0], w[1], w[2], w[3]);
+        wr[1] = make_float4(w[4], w[5], w[6], w[7]);
+    }
+}
+
+// Phase C for the signed maximum over all input rows of the block.  Item q:
+// row 64 (q / 128) + q % 64 and column groups 2 ((q / 64) % 2) and the next,
+// for blocks of more than two groups (nt a multiple of 128, so the groups
+// are uniform per wave); row q and groups 0, 1 otherwise.  bits_t: the
+// step's input spikes per sample.
+template <bool Coherent>
+__device__ __forceinline__ void plasticity_signed(const Params &p, const StepLds &S, const uint16_t *lt,
+                                                  const uint32_t *ct, const uint32_t *bits_t, const float *xpre,
+                                                  int tid, int nt, int prec, int prec_d)
+{
+    const int ucnt = (int)S.ulist[p.B];
+    const int ncg = p.jbp >> 3;
+    const int npair = ncg > 2 ? 2 : 1;
+    const int nrow = (p.n_in + 63) & ~63;
+    for (int q = tid; q < npair * nrow; q += nt) {
+        const int hf = npair == 2 ? (q >> 6) & 1 : 0;
+        const int i = npair == 2 ? ((q >> 7) << 6) | (q & 63) : q;
+        if (i >= p.n_in) continue;
+        const int cg0 = 2 * hf;
+        plasticity_signed_row<Coherent>(p, S, i, cg0, min(2, ncg - cg0), (int)ct[i], lt + (size_t)i * p.lt_stride,
+                                        bits_t, xpre, ucnt, prec, prec_d);
+    }
+}
+
 // Phase C over all input rows of the block: split rows (Halves, blocks of
 // two or more column groups) or whole rows per thread; a thread loads its
 // next row's list head before working on the current row.  Rows are taken in
 // the order `ord` (inputs by decreasing sample-list length), so the lanes of
 // a wave walk lists of similar length.
-template <bool Coherent, int XR, bool Halves, int NH = kListHead, bool Interleave = true, bool Pipe = false>
+template <bool Coherent, int XR, bool Halves, int NH = kListHead, bool Interleave = true, bool Pipe = false,
+          int RK = RK_STD>
 __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S, const uint16_t *lt,
                                                const uint32_t *ct, const uint16_t *ord, const float *xpre, int tid,
-                                               int nt, int prec, int prec_d)
+                                               int nt, int prec, int prec_d, const uint32_t *bits_t)
 {
+    if constexpr (RK == RK_SIGNED) {
+        plasticity_signed<Coherent>(p, S, lt, ct, bits_t, xpre, tid, nt, prec, prec_d);
+        return;
+    }
     const int ucnt = (int)S.ulist[p.B];
     const int ncg = p.jbp >> 3;
     if (Interleave && Halves && ncg >= 2 && p.reduce != RED_MAX) {
         uint32_t colany = 0u;
         for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
         colany = __builtin_amdgcn_readfirstlane(colany);
-        plasticity_tiles<Coherent, NH, Pipe>(p, S, lt, ct, xpre, ucnt, colany, tid, nt, prec, prec_d);
+        plasticity_tiles<Coherent, NH, Pipe, RK>(p, S, lt, ct, xpre, ucnt, colany, tid, nt, prec, prec_d);
         return;
     }
     if (Halves && ncg >= 2) {
@@ -931,9 +1051,9 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             for (int u = 0; u < ucnt; ++u) colany |= S.colmask[S.ulist[u]];
             colany = __builtin_amdgcn_readfirstlane(colany);
             if (Pipe)
-                potentiation_pipe<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
+                potentiation_pipe<Coherent, RK>(p, S, xpre, ucnt, colany, prec, tid, nt);
             else
-                potentiation_mfma<Coherent>(p, S, xpre, ucnt, colany, prec, tid, nt);
+                potentiation_mfma<Coherent, RK>(p, S, xpre, ucnt, colany, prec, tid, nt);
             __syncthreads();
             pdone = colany;
             ucnt_items = 0;
@@ -966,7 +1086,7 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
                 if (more) fetch(q + nt, i_nxt, nxt);
                 if (i_cur >= 0) {
                     const int cg0 = 2 * ((q >> 6) & 1);
-                    plasticity_row_half<Coherent, NH>(p, S, i_cur, cg0, min(2, ncg - cg0), (int)cur.cnt, cur.h,
+                    plasticity_row_half<Coherent, NH, RK>(p, S, i_cur, cg0, min(2, ncg - cg0), (int)cur.cnt, cur.h,
                                                       lt + (size_t)i_cur * p.lt_stride, xpre, 0, pdone, prec,
                                                       prec_d);
                 }
@@ -986,7 +1106,7 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             const uint32_t cnt = ct[i];
             uint4 h[NH];
             load_heads<NH>(lt + (size_t)i * p.lt_stride, h);
-            plasticity_row_half<Coherent, NH>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
+            plasticity_row_half<Coherent, NH, RK>(p, S, i, cg0, ng, (int)cnt, h, lt + (size_t)i * p.lt_stride, xpre,
                                               ucnt_items, pdone, prec, prec_d);
         }
         return;
@@ -1012,7 +1132,7 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
             cnt_n = ct[i_n];
             head_n = *reinterpret_cast<const uint4 *>(lt + (size_t)i_n * p.lt_stride);
         }
-        plasticity_row_cg<Coherent, XR>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
+        plasticity_row_cg<Coherent, XR, RK>(p, S, i, (int)cnt, head, lt + (size_t)i * p.lt_stride, xpre, ucnt, colany,
                                         prec, prec_d);
         r = rn;
     }
@@ -1039,6 +1159,7 @@ __device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, i
 // their additions (a loop of one load and one dependent add per row would
 // pay the LDS latency on every row); the order of the additions is the
 // row order either way.
+template <int RK = RK_STD>
 __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S, double norm, int tid, int nt)
 {
     const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
@@ -1074,7 +1195,7 @@ __device__ __forceinline__ void colsums_theta(const Params &p, const StepLds &S,
         if (p.adaptive && tid < p.jb) {
             int cnt = 0;
             for (int bw = 0; bw < p.bwords; ++bw) cnt += __builtin_popcount(S.spk[tid * p.bwords + bw]);
-            S.th64[tid] = theta_step(p, S.th64[tid], cnt);
+            S.th64[tid] = theta_step<RK>(p, S.th64[tid], cnt);
         }
     }
     __syncthreads();

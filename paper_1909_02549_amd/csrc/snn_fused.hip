@@ -24,11 +24,11 @@ namespace snn {
 
 size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads, true).total; }
 
-// PREC: the operand form.  For BF16 / FP8 the block's weights are rounded
+// PREC: the operand form; RK: the reduction kind (RedKind) of the plasticity.  For BF16 / FP8 the block's weights are rounded
 // in LDS for the contraction and reloaded in FP32 for the plasticity, and
 // the post traces in LDS are rounded once after the neurons' state went back
 // to HBM in FP32; the presynaptic traces are rounded as they are read.
-template <int PREC>
+template <int PREC, int RK>
 __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -80,17 +80,25 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     }
     __syncthreads();
 
-    plasticity_all<false, 16, true, kListHead, PREC == PREC_FP32>(p, S, s.lt, s.ct, s.ord_in, s.xpre, tid, nt,
-                                                                 PREC, 0);
+    plasticity_all<false, 16, true, kListHead, PREC == PREC_FP32, false, RK>(p, S, s.lt, s.ct, s.ord_in, s.xpre,
+                                                                            tid, nt, PREC, 0, s.bits);
     __syncthreads();
-    colsums_theta(p, S, p.norm, tid, nt);
+    colsums_theta<RK>(p, S, p.norm, tid, nt);
     if (s.bits_next) xpre_next<false>(p, s.bits_next, s.xpre, s.xpre_next, g, gridDim.x, tid, nt);
     store_block(p, S, Wg, a.theta, g, tid, nt);
 }
 
-template __global__ void k_fused_step<PREC_FP32>(Params, FusedArgs, StepPtrs);
-template __global__ void k_fused_step<PREC_BF16>(Params, FusedArgs, StepPtrs);
-template __global__ void k_fused_step<PREC_FP8>(Params, FusedArgs, StepPtrs);
+#define SNN_FUSED_INST(PR, RK) template __global__ void k_fused_step<PR, RK>(Params, FusedArgs, StepPtrs);
+SNN_FUSED_INST(PREC_FP32, RK_STD)
+SNN_FUSED_INST(PREC_BF16, RK_STD)
+SNN_FUSED_INST(PREC_FP8, RK_STD)
+SNN_FUSED_INST(PREC_FP32, RK_SOFT)
+SNN_FUSED_INST(PREC_BF16, RK_SOFT)
+SNN_FUSED_INST(PREC_FP8, RK_SOFT)
+SNN_FUSED_INST(PREC_FP32, RK_SIGNED)
+SNN_FUSED_INST(PREC_BF16, RK_SIGNED)
+SNN_FUSED_INST(PREC_FP8, RK_SIGNED)
+#undef SNN_FUSED_INST
 
 // Sparse index lists of one chunk of encoded steps:
 //   lin[t][b][0 .. cin[t][b])  inputs that spiked in sample b (increasing)

@@ -53,12 +53,40 @@ __device__ __forceinline__ float reduce2(int mode, float acc, float x)
     return mode == RED_MAX ? fmaxf(acc, x) : acc + x;
 }
 
-// W <- clamp(W + nu_post P - nu_pre D); mean divides the sums by B.
+// The soft maximum with temperature tau, tau log((1 / B) sum_b exp(z_b / tau)),
+// over B terms of which only the spiking samples' are non-zero: a zero term
+// adds exp(0) = 1, so with S = sum over the spiking samples of
+// exp(z_b / tau) - 1 the reduction is tau log1p(S / B).  soft_term gives one
+// summand from k = log2(e) / tau with the hardware base-2 exponential (about
+// 1 ulp: an absolute error near 1e-7 per summand, which moves the reduced
+// change by about tau 1e-7, far below the weights' FP32 rounding; z = 0
+// gives exactly 0); soft_value the reduction of the sum, tau ln(2)
+// log2(1 + S / B) with the hardware base-2 logarithm (where S / B is far
+// below 1 the rounding of 1 + S / B costs an absolute error near
+// tau 6e-8, again far below the weights' rounding; S = 0 gives exactly 0).
+__device__ __forceinline__ float soft_term(float x, float k) { return __builtin_amdgcn_exp2f(x * k) - 1.f; }
+__device__ __forceinline__ float soft_value(const Params &p, float S)
+{
+    return p.tau_ln2_r * __builtin_amdgcn_logf(1.f + S * p.inv_B);
+}
+
+// One trace value as a summand of the batch reduction (the soft maximum's
+// transform, else the value itself).
+__device__ __forceinline__ float stdp_term(const Params &p, float x)
+{
+    return p.reduce == RED_SOFT ? soft_term(x, p.itau2_r) : x;
+}
+
+// W <- clamp(W + nu_post P - nu_pre D); mean divides the sums by B, the soft
+// maximum maps them through tau log1p(S / B).
 __device__ __forceinline__ float stdp_apply(const Params &p, float w, float P, float D)
 {
     if (p.reduce == RED_MEAN) {
         P *= p.inv_B;
         D *= p.inv_B;
+    } else if (p.reduce == RED_SOFT) {
+        P = soft_value(p, P);
+        D = soft_value(p, D);
     }
     w = w + p.nu_post * P - p.nu_pre * D;
     return fminf(fmaxf(w, p.w_min), p.w_max);
@@ -73,12 +101,20 @@ __device__ __forceinline__ float theta_offset(const Params &p, double theta)
 }
 
 // theta <- theta * beta + theta_plus * R_b(s_exc[b, j]) from the column's
-// spike count (sum: count, mean: count / B, max: any).
+// spike count (sum: count, mean: count / B, max and signed max: any, soft
+// maximum: the soft maximum of count ones and B - count zeros, in FP32 like
+// the weights' (its relative error near 1e-7 stays far inside the FP64
+// accumulation's needs), added to theta in FP64).  The soft branch is
+// compiled into the kernels of that reduction kind (RK) only; RK -1: every
+// branch, chosen from p.reduce at run time.
+template <int RK = -1>
 __device__ __forceinline__ double theta_step(const Params &p, double theta, int count)
 {
     double r = (double)count;
     if (p.reduce == RED_MEAN) r = (double)count / (double)p.B;
-    else if (p.reduce >= RED_MAX) r = count > 0 ? 1.0 : 0.0;
+    else if (p.reduce == RED_MAX || p.reduce == RED_MAX_SIGNED) r = count > 0 ? 1.0 : 0.0;
+    else if ((RK == -1 || RK == RK_SOFT) && p.reduce == RED_SOFT)
+        r = (double)soft_value(p, (float)count * soft_term(1.f, p.itau2_r));
     return theta * p.beta + p.theta_plus * r;
 }
 

@@ -208,8 +208,9 @@ __global__ void k_neuron(Params p, const float *__restrict__ I, const double *__
 //   D[i, j] = R_b s_in[b, i] x_post[b, j]   (depression on a pre spike)
 //   W <- clamp(W + nu_post P - nu_pre D), column sums in FP64, W[:, j] *=
 //   norm / c_j; theta <- theta * beta + theta_plus * R_b s_exc[b, j].
-// R is sum, mean (sum / B) or max, applied to P and D separately; the traces
-// enter in the operand form of the precision (unrounded for FP32).  The
+// R is sum, mean (sum / B), max or the soft maximum, applied to P and D
+// separately; the traces enter in the operand form of the precision
+// (unrounded for FP32).  The
 // signed max instead adds max_b (nu_post P_b - nu_pre D_b), the largest
 // per-sample change, 0 for a sample with neither spike on the synapse.
 __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W, double *__restrict__ theta,
@@ -281,7 +282,8 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
                 while (m) {
                     const int b = 32 * bw + __builtin_ctz(m);
                     m &= m - 1;
-                    D = reduce2(p.reduce, D, operand_value(p.prec, x_post[sbase + (size_t)b * p.jbp + jj]));
+                    D = reduce2(p.reduce, D,
+                                stdp_term(p, operand_value(p.prec, x_post[sbase + (size_t)b * p.jbp + jj])));
                 }
             }
             const uint32_t *sp = spk + jj * p.bwords;
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256) void k_plastic(Params p, float *__restrict__ W
                 while (m) {
                     const int b = 32 * bw + __builtin_ctz(m);
                     m &= m - 1;
-                    P = reduce2(p.reduce, P, operand_value(p.prec, x_pre[(size_t)b * p.n_in_pad + i]));
+                    P = reduce2(p.reduce, P, stdp_term(p, operand_value(p.prec, x_pre[(size_t)b * p.n_in_pad + i])));
                 }
             }
             const float w = stdp_apply(p, Wg[(size_t)i * JB + jj], P, D);

@@ -61,10 +61,11 @@ __device__ __forceinline__ bool grid_wait(const PersistSync &sy, uint32_t target
     return *abort_lds == 0;
 }
 
-template <int PREC>
+template <int PREC, int RK>
 __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs args)
 {
-    // PREC: the operand form (rounding in the gathers for BF16 / FP8)
+    // PREC: the operand form (rounding in the gathers for BF16 / FP8); RK:
+    // the reduction kind (RedKind) of the plasticity
 
     const Params &p = args.p;
     const FusedArgs &a = args.a;
@@ -152,11 +153,11 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
             xpre_next_own<XC>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, xc, g, gridDim.x, tid, nt);
         grid_arrive(sy);
         if (p.learn) {
-            plasticity_all<true, 16, true, 2, false, true>(p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride,
-                                              ch.ct + (size_t)k * p.n_in_pad, ch.ord_in + (size_t)k * p.n_in_pad,
-                                              xpre, tid, nt, PREC, PREC);
+            plasticity_all<true, 16, true, 2, false, true, RK>(
+                p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride, ch.ct + (size_t)k * p.n_in_pad,
+                ch.ord_in + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC, ch.bits + (size_t)k * p.bits_stride);
             __syncthreads();
-            colsums_theta(p, S, k >= ch.norm_from ? p.norm : 0.0, tid, nt);
+            colsums_theta<RK>(p, S, k >= ch.norm_from ? p.norm : 0.0, tid, nt);
             if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);
         }
         if (k + 1 < ch.steps) {
@@ -178,8 +179,16 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
     if (p.learn) store_block(p, S, Wg, a.theta, g, tid, nt);
 }
 
-template __global__ void k_persist<PREC_FP32>(const PersistArgs);
-template __global__ void k_persist<PREC_BF16>(const PersistArgs);
-template __global__ void k_persist<PREC_FP8>(const PersistArgs);
+#define SNN_PERSIST_INST(PR, RK) template __global__ void k_persist<PR, RK>(const PersistArgs);
+SNN_PERSIST_INST(PREC_FP32, RK_STD)
+SNN_PERSIST_INST(PREC_BF16, RK_STD)
+SNN_PERSIST_INST(PREC_FP8, RK_STD)
+SNN_PERSIST_INST(PREC_FP32, RK_SOFT)
+SNN_PERSIST_INST(PREC_BF16, RK_SOFT)
+SNN_PERSIST_INST(PREC_FP8, RK_SOFT)
+SNN_PERSIST_INST(PREC_FP32, RK_SIGNED)
+SNN_PERSIST_INST(PREC_BF16, RK_SIGNED)
+SNN_PERSIST_INST(PREC_FP8, RK_SIGNED)
+#undef SNN_PERSIST_INST
 
 }  // namespace snn

@@ -125,6 +125,26 @@ static size_t param_bytes(const Params &p)
     return (size_t)p.n_in_pad * p.n_pad * (4 + 2 + 1) + (size_t)p.n_pad * 8 + 1024;
 }
 
+// Smallest temperature of the soft-maximum reduction: every summand
+// expm1(x / tau) stays below e^64 (x at most 1 for nearest-spike traces, at
+// most 1 / (1 - lambda) for additive ones), so sums over any batch stay far
+// from the FP32 range limit.
+static double soft_tau_min(const snn_config &c)
+{
+    double xmax = 1.0;  // nearest-spike traces
+    if (c.trace_additive) {
+        // additive traces stay below 1 / (1 - lambda), lambda the slower decay
+        const double lam = std::max(std::exp(-c.dt_ms / c.tau_pre_ms), std::exp(-c.dt_ms / c.tau_post_ms));
+        xmax = lam < 1.0 ? 1.0 / (1.0 - lam) : HUGE_VAL;
+    }
+    return xmax / 64.0;
+}
+
+static bool soft_tau_ok(const snn_config &c, double tau)
+{
+    return std::isfinite(tau) && tau >= soft_tau_min(c);
+}
+
 static snn_status validate(const snn_config *c)
 {
     if (!c) return fail(SNN_EINVAL, "snn_config is NULL");
@@ -138,14 +158,16 @@ static snn_status validate(const snn_config *c)
     if (c->exc.refrac_steps < 0 || c->exc.refrac_steps > 127 || c->inh.refrac_steps < 0 ||
         c->inh.refrac_steps > 127)
         return fail(SNN_EINVAL, "refrac_steps must be in [0, 127]");
-    if (c->reduce < 0 || c->reduce > 3)
-        return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean), 2 (max) or 3 (signed max)");
+    if (c->reduce < 0 || c->reduce > 4)
+        return fail(SNN_EINVAL, "reduce must be 0 (sum), 1 (mean), 2 (max), 3 (signed max) or 4 (soft max)");
     if (c->precision < 0 || c->precision > 2) return fail(SNN_EINVAL, "precision must be 0, 1 or 2");
     if (c->path < 0 || c->path > 4) return fail(SNN_EINVAL, "path must be 0..4");
     if (c->learn && (!(c->tau_pre_ms > 0) || !(c->tau_post_ms > 0)))
         return fail(SNN_EINVAL, "trace time constants must be > 0");
     if (c->learn && c->exc.adaptive && !(c->exc.tau_theta_ms > 0))
         return fail(SNN_EINVAL, "tau_theta_ms must be > 0");
+    if (c->learn && c->reduce == SNN_REDUCE_SOFT_MAX && !soft_tau_ok(*c, c->reduce_tau))
+        return fail(SNN_EINVAL, "reduce_tau must be finite and at least the largest trace value / 64");
     if (c->w_min > c->w_max) return fail(SNN_EINVAL, "w_min > w_max");
     if (c->max_batch == 0) return fail(SNN_EINVAL, "max_batch must be > 0");
     if (c->norm_per_run > 1) return fail(SNN_EINVAL, "norm_per_run must be 0 or 1");
@@ -182,6 +204,9 @@ static void fill_params(Params &p, const snn_config &c)
     p.adaptive = c.exc.adaptive != 0;
     p.trace_add = c.trace_additive != 0;
     p.reduce = c.reduce;
+    const double tau = c.reduce == SNN_REDUCE_SOFT_MAX ? c.reduce_tau : 1.0;
+    p.itau2_r = (float)(M_LOG2E / tau);
+    p.tau_ln2_r = (float)(tau * M_LN2);
     p.prec = c.precision;
     p.uniform_rate = c.uniform_rate != 0;
     p.thr_uniform = rate_threshold(c, 0, true);
@@ -455,9 +480,24 @@ snn_status snn_net::relayout(int jb)
 extern "C" snn_status snn_stdp_reduce(snn_net *net, int32_t mode)
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
-    if (mode < 0 || mode > 3) return fail(SNN_EINVAL, "mode must be 0 (sum), 1 (mean), 2 (max) or 3 (signed max)");
+    if (mode < 0 || mode > 4)
+        return fail(SNN_EINVAL, "mode must be 0 (sum), 1 (mean), 2 (max), 3 (signed max) or 4 (soft max)");
+    if (mode == SNN_REDUCE_SOFT_MAX) return snn_stdp_reduce_soft(net, net->cfg.reduce_tau);
     net->cfg.reduce = mode;
     net->p.reduce = mode;
+    net->graphs_invalidate();
+    return SNN_OK;
+}
+
+extern "C" snn_status snn_stdp_reduce_soft(snn_net *net, double tau)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (!soft_tau_ok(net->cfg, tau)) return fail(SNN_EINVAL, "tau must be finite and at least the largest trace value / 64");
+    net->cfg.reduce = SNN_REDUCE_SOFT_MAX;
+    net->cfg.reduce_tau = tau;
+    net->p.reduce = RED_SOFT;
+    net->p.itau2_r = (float)(M_LOG2E / tau);
+    net->p.tau_ln2_r = (float)(tau * M_LN2);
     net->graphs_invalidate();
     return SNN_OK;
 }
@@ -761,6 +801,27 @@ snn_status snn_net::xpre_first(const uint32_t *bits_t)
     return SNN_OK;
 }
 
+// The fused per-step (Persist false) or persistent kernel for an operand
+// form and a reduction kind.
+template <int PREC, int RK, bool Persist>
+static const void *kernel_of()
+{
+    return Persist ? (const void *)k_persist<PREC, RK> : (const void *)k_fused_step<PREC, RK>;
+}
+
+template <bool Persist>
+static const void *step_kernel(int prec, int rk)
+{
+    static const void *const table[3][3] = {
+        {kernel_of<PREC_FP32, RK_STD, Persist>(), kernel_of<PREC_FP32, RK_SOFT, Persist>(),
+         kernel_of<PREC_FP32, RK_SIGNED, Persist>()},
+        {kernel_of<PREC_BF16, RK_STD, Persist>(), kernel_of<PREC_BF16, RK_SOFT, Persist>(),
+         kernel_of<PREC_BF16, RK_SIGNED, Persist>()},
+        {kernel_of<PREC_FP8, RK_STD, Persist>(), kernel_of<PREC_FP8, RK_SOFT, Persist>(),
+         kernel_of<PREC_FP8, RK_SIGNED, Persist>()}};
+    return table[prec][rk];
+}
+
 bool snn_net::fused_ok() const
 {
     return p.jb <= 32 && p.n_in_pad < 65535 && p.B < 65535 && fused_lds_bytes(p) <= kMaxLds;
@@ -788,21 +849,16 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     if (cfg.norm_per_run && (uint32_t)k + 1 != run_T) pp.norm = 0.0;
     FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
     const size_t lds = fused_lds_bytes(p);
-    const void *fn = p.prec == PREC_FP32   ? (const void *)k_fused_step<PREC_FP32>
-                     : p.prec == PREC_BF16 ? (const void *)k_fused_step<PREC_BF16>
-                                           : (const void *)k_fused_step<PREC_FP8>;
-    if (lds > fused_attr_bytes[p.prec]) {
+    const int rk = red_kind(p.reduce);
+    const void *fn = step_kernel<false>(p.prec, rk);
+    if (lds > fused_attr_bytes[p.prec][rk]) {
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        fused_attr_bytes[p.prec] = lds;
+        fused_attr_bytes[p.prec][rk] = lds;
     }
-    const dim3 grid((unsigned)p.nblk);
-    if (p.prec == PREC_FP32)
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP32>, grid, dim3(kFusedThreads), lds, pp, a, s);
-    else if (p.prec == PREC_BF16)
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_BF16>, grid, dim3(kFusedThreads), lds, pp, a, s);
-    else
-        SNN_LAUNCH("fused_step", k_fused_step<PREC_FP8>, grid, dim3(kFusedThreads), lds, pp, a, s);
-    HIP_TRY(hipGetLastError());
+    void *kargs[] = {(void *)&pp, (void *)&a, (void *)&s};
+    if (prof) prof_open(kstat_id("fused_step"));
+    HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)p.nblk), dim3(kFusedThreads), kargs, (unsigned)lds, stream));
+    if (prof) span.launches += 1;
     ++gstep;
     return SNN_OK;
 }
@@ -841,12 +897,11 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     h.sy = PersistSync{bar, err};
     SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
     const size_t lds = persist_lds_bytes(p);
-    const void *kfn = p.prec == PREC_FP32   ? (const void *)k_persist<PREC_FP32>
-                      : p.prec == PREC_BF16 ? (const void *)k_persist<PREC_BF16>
-                                            : (const void *)k_persist<PREC_FP8>;
-    if (lds > persist_attr_bytes[p.prec]) {
+    const int rk = red_kind(p.reduce);
+    const void *kfn = step_kernel<true>(p.prec, rk);
+    if (lds > persist_attr_bytes[p.prec][rk]) {
         HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        persist_attr_bytes[p.prec] = lds;
+        persist_attr_bytes[p.prec][rk] = lds;
     }
     // the arguments go by value: the runtime copies them into the launch.
     // Launched directly, the kernel goes out as a cooperative launch (the
@@ -903,10 +958,6 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
 snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                               uint32_t T, const Outs &o, const uint32_t *tl)
 {
-    // the signed max reduction is implemented by the plasticity kernels of
-    // the plain and MFMA routes only
-    if (p.learn && p.reduce == RED_MAX_SIGNED && (path == SNN_PATH_PERSISTENT || path == SNN_PATH_FUSED))
-        path = SNN_PATH_PLAIN;
     run_T = T;
     if (path == SNN_PATH_PERSISTENT && !persist_ok()) path = SNN_PATH_FUSED;
     if (path == SNN_PATH_FUSED && !fused_ok()) path = SNN_PATH_PLAIN;

@@ -169,7 +169,7 @@ DC_INH = dict(v_rest=-60.0, v_reset=-45.0, v_thresh=-40.0, tau_ms=10.0, refrac_s
 SCALING_LIF = dict(v_rest=-65.0, v_reset=-65.0, v_thresh=-52.0, tau_ms=100.0, refrac_steps=5,
                    adaptive=0, theta_plus=0.0, tau_theta_ms=1e7)
 
-REDUCE = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3}
+REDUCE = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3, "soft_max": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 

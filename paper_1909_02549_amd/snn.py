@@ -16,16 +16,16 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsnn.so")
 
-SNN_ABI_VERSION = 1
+SNN_ABI_VERSION = 2
 SNN_RUN_RESET = 1
 PATHS = {"plain": 0, "fused": 1, "persistent": 2, "auto": 3, "mfma": 4}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
-REDUCES = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3}
+REDUCES = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3, "soft_max": 4}
 STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4: "SNN_EAGAIN",
           -5: "SNN_ENOTFOUND", -6: "SNN_ESTATE"}
 
 EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "snn_set_stream",
-            "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce",
+            "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce", "snn_stdp_reduce_soft",
             "snn_set_path", "snn_last_path", "snn_set_graphs", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
@@ -54,7 +54,7 @@ class snn_config(C.Structure):
                 ("nu_pre", C.c_double), ("nu_post", C.c_double), ("tau_pre_ms", C.c_double),
                 ("tau_post_ms", C.c_double), ("w_min", C.c_double), ("w_max", C.c_double),
                 ("norm", C.c_double), ("seed", C.c_uint64), ("max_batch", C.c_uint32),
-                ("norm_per_run", C.c_uint32), ("hbm_budget_bytes", C.c_uint64)]
+                ("norm_per_run", C.c_uint32), ("hbm_budget_bytes", C.c_uint64), ("reduce_tau", C.c_double)]
 
 
 class snn_outputs(C.Structure):
@@ -98,6 +98,7 @@ def load_library():
         "snn_set_theta": ([VP, VP, SZ], I32),
         "snn_get_theta": ([VP, VP, SZ], I32),
         "snn_stdp_reduce": ([VP, I32], I32),
+        "snn_stdp_reduce_soft": ([VP, C.c_double], I32),
         "snn_set_path": ([VP, I32, I32], I32),
         "snn_last_path": ([VP, P(I32)], I32),
         "snn_set_graphs": ([VP, I32], I32),
@@ -158,6 +159,7 @@ def make_config(cfg: dict, max_batch: int, path="plain", precision="fp32", hbm_b
     c.max_batch = int(max_batch)
     c.norm_per_run = int(cfg.get("norm_per_run", 0))
     c.hbm_budget_bytes = int(hbm_budget)
+    c.reduce_tau = float(cfg.get("reduce_tau", 1.0))
     return c
 
 
@@ -221,6 +223,9 @@ class Net:
 
     def snn_stdp_reduce(self, mode):
         _check(self.lib.snn_stdp_reduce(self.h, REDUCES[mode] if isinstance(mode, str) else int(mode)))
+
+    def snn_stdp_reduce_soft(self, tau: float):
+        _check(self.lib.snn_stdp_reduce_soft(self.h, float(tau)))
 
     def snn_set_path(self, path="plain", precision="fp32"):
         _check(self.lib.snn_set_path(self.h, PATHS[path] if isinstance(path, str) else int(path),

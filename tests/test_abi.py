@@ -38,7 +38,7 @@ def test_binding_names_match_header():
 
 
 def test_abi_version(lib):
-    assert lib.snn_abi_version() == 1
+    assert lib.snn_abi_version() == 2
 
 
 def _cfg(**over):
@@ -61,6 +61,18 @@ def test_invalid_config_rejected_without_gpu(lib, field, value):
     assert lib.snn_last_error().decode()
 
 
+@pytest.mark.parametrize("tau,additive", [(1e-3, 0), (float("inf"), 0), (float("nan"), 0), (-1.0, 0),
+                                          (0.1, 1)])
+def test_soft_max_temperature_bound_rejected(lib, tau, additive):
+    """The soft maximum needs a finite temperature of at least x_max / 64
+    (x_max = 1 for nearest-spike traces, 1 / (1 - exp(-dt / tau_trace)),
+    about 20.5, for additive ones at 20 ms)."""
+    c = _cfg(reduce=4, reduce_tau=tau, trace_additive=additive)
+    h = C.c_void_p()
+    assert lib.snn_create(C.byref(c), None, C.byref(h)) == -1 and not h.value
+    assert "reduce_tau" in lib.snn_last_error().decode()
+
+
 def test_refractory_bound_rejected(lib):
     c = _cfg()
     c.exc.refrac_steps = 200
@@ -72,6 +84,7 @@ def test_null_handle_calls(lib):
     assert lib.snn_run(None, None, None, 1, 1, 0, None) == -1
     assert lib.snn_sync(None) == -1
     assert lib.snn_stdp_reduce(None, 0) == -1
+    assert lib.snn_stdp_reduce_soft(None, 1.0) == -1
     assert lib.snn_serve_poll(None, 1, None, None) == -1
 
 

@@ -313,14 +313,16 @@ def run_dc(oracle_mod, cfg, W, images, ids, T, **kw):
     return net, out
 
 
-@pytest.mark.parametrize("reduce", ["sum", "mean", "max", "max_signed"])
+@pytest.mark.parametrize("reduce", ["sum", "mean", "max", "max_signed", "soft_max"])
 def test_identical_samples_match_single_run(oracle_mod, reduce):
     """B = 2 copies of one sample (same image, same id): mean, max and signed
     max equal the single-sample run exactly; sum equals the single run with the learning
-    rates and theta increment doubled (x + x = 2x exactly)."""
+    rates and theta increment doubled (x + x = 2x exactly).  The soft maximum
+    of two equal terms is that term (tau log((e^(x/tau) + e^(x/tau)) / 2) = x),
+    up to the rounding of exp and log."""
     T = 60
     img = stroke_images(1, 11, 0.25)
-    cfg, W = dc_small(reduce=reduce)
+    cfg, W = dc_small(reduce=reduce, reduce_tau=0.2)
     net2, out2 = run_dc(oracle_mod, cfg, W, np.repeat(img, 2, 0), np.array([9, 9], np.uint64), T)
     cfg1 = dict(cfg)
     if reduce == "sum":
@@ -329,6 +331,10 @@ def test_identical_samples_match_single_run(oracle_mod, reduce):
     net1, out1 = run_dc(oracle_mod, cfg1, W, img, np.array([9], np.uint64), T)
     assert out1["exc"].sum() >= 5
     assert (out2["exc"][0] == out1["exc"][0]).all() and (out2["exc"][1] == out1["exc"][0]).all()
+    if reduce == "soft_max":
+        np.testing.assert_allclose(net2.W, net1.W, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(net2.theta, net1.theta, rtol=1e-12, atol=1e-15)
+        return
     assert np.array_equal(net2.W, net1.W)
     assert np.array_equal(net2.theta, net1.theta)
 
@@ -337,8 +343,8 @@ def test_single_sample_reductions_agree(oracle_mod):
     """With B = 1 every reduction is the identity."""
     img = stroke_images(1, 5, 0.2)
     Ws = []
-    for r in ("sum", "mean", "max", "max_signed"):
-        cfg, W = dc_small(reduce=r)
+    for r in ("sum", "mean", "max", "max_signed", "soft_max"):
+        cfg, W = dc_small(reduce=r, reduce_tau=0.1)
         net, _ = run_dc(oracle_mod, cfg, W, img, sample_ids(1), 50)
         Ws.append((net.W, net.theta))
     for W_, th in Ws[1:3]:
@@ -347,9 +353,12 @@ def test_single_sample_reductions_agree(oracle_mod):
     # of (W + a) - b, equal up to the last bit
     np.testing.assert_allclose(Ws[3][0], Ws[0][0], rtol=0, atol=1e-14)
     assert np.array_equal(Ws[3][1], Ws[0][1]) and np.abs(Ws[3][0] - Ws[0][0]).max() < 1e-15
+    # soft maximum of one term: tau log(exp(x / tau)) = x up to rounding
+    np.testing.assert_allclose(Ws[4][0], Ws[0][0], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(Ws[4][1], Ws[0][1], rtol=1e-12, atol=1e-15)
 
 
-def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post):
+def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post, tau=1.0, adaptive=0):
     """Two different samples with forced inputs.  Step 0 lays down pre traces
     without any post spike (weights 0.5 are subthreshold), so no weight
     changes there; on step 1 strong driver inputs make exc neurons fire in
@@ -358,8 +367,9 @@ def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post):
     Returns W0, the batch run's W and the two single-sample runs' W."""
     n_in, n_exc = 6, 4
     cfg = tiny_cfg(n_in, n_exc, learn=True, norm=0.0, w_min=-100.0, w_max=100.0,
-                   nu_pre=nu_pre, nu_post=nu_post, exc=dict(adaptive=0))
-    cfg["reduce"] = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3}[reduce]
+                   nu_pre=nu_pre, nu_post=nu_post, exc=dict(adaptive=adaptive, theta_plus=0.05),
+                   reduce_tau=tau)
+    cfg["reduce"] = {"sum": 0, "mean": 1, "max": 2, "max_signed": 3, "soft_max": 4}[reduce]
     W0 = np.full((n_in, n_exc), 0.5)
     W0[0, :] = [20.0, 0.0, 20.0, 0.0]
     W0[1, :] = [0.0, 20.0, 20.0, 0.0]
@@ -379,6 +389,8 @@ def _two_samples_one_learning_step(oracle_mod, reduce, nu_pre, nu_post):
         nb = oracle_mod.OracleNet(cfg, W0)
         nb.run(None, ids[b:b + 1], 2, forced_in=forced[b:b + 1], record=())
         singles.append(nb.W.copy())
+    if adaptive:
+        return W0, net.W.copy(), singles, net.theta.copy()
     return W0, net.W.copy(), singles
 
 
@@ -545,3 +557,79 @@ def test_paper_parameters_golden(oracle_mod):
     assert cfg["max_rate_hz"] == g["max_input_rate_hz"]["value"]
     assert cfg["exc"]["theta_plus"] == g["theta_plus_mv"]["value"]
     assert g["theta_decay_s"]["value"] * 1000.0 == 1e6  # paper; workload uses 1e7 ms
+
+
+# ---------------------------------------------------------------------------
+# soft maximum (log-mean-exp with temperature tau): pinned by its bounds,
+# limits and monotonicity against the single-sample runs (B = 1: every
+# reduction is the identity) and the mean and max reductions
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.02, 0.1, 1.0, 10.0])
+def test_soft_max_between_mean_and_max(oracle_mod, tau):
+    """For one learning step of two samples, per synapse: the mean of the
+    single-sample changes <= the soft-max change <= their maximum, and the
+    soft max is at least the maximum minus nu tau log 2 (the log-mean-exp of
+    two terms lies in [max - tau log 2, max]).  Potentiation alone
+    (nu_pre = 0) and depression alone (nu_post = 0, where the reduced term is
+    subtracted, so the bounds swap)."""
+    nu = 1e-2
+    W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "soft_max", 0.0, nu, tau)
+    d, d1, d2 = Wb - W0, W1 - W0, W2 - W0
+    eps = 1e-13
+    assert (d >= 0.5 * (d1 + d2) - eps).all() and (d <= np.maximum(d1, d2) + eps).all()
+    assert (d >= np.maximum(d1, d2) - nu * tau * math.log(2.0) - eps).all()
+    moved = np.abs(d1 - d2) > 1e-6
+    assert moved.any() and (d[moved] > 0.5 * (d1 + d2)[moved]).all()
+    W0, Wb, (W1, W2) = _two_samples_one_learning_step(oracle_mod, "soft_max", nu, 0.0, tau)
+    d, d1, d2 = Wb - W0, W1 - W0, W2 - W0
+    assert (d <= 0.5 * (d1 + d2) + eps).all() and (d >= np.minimum(d1, d2) - eps).all()
+    assert (d <= np.minimum(d1, d2) + nu * tau * math.log(2.0) + eps).all()
+    assert (np.abs(d1 - d2) > 1e-6).any()
+
+
+def test_soft_max_limits(oracle_mod):
+    """A large temperature gives the mean reduction (the log-mean-exp tends
+    to the mean, with an error below the terms' spread squared / (2 tau));
+    a small one the maximum (within nu tau log 2)."""
+    for nu_pre, nu_post in ((0.0, 1e-2), (1e-2, 0.0), (1e-4, 1e-2)):
+        _, Wm, _ = _two_samples_one_learning_step(oracle_mod, "mean", nu_pre, nu_post)
+        _, Ws, _ = _two_samples_one_learning_step(oracle_mod, "soft_max", nu_pre, nu_post, 1e6)
+        np.testing.assert_allclose(Ws, Wm, rtol=0, atol=1e-8)
+        assert np.abs(Ws - Wm).max() > 0 or nu_pre == 0
+    W0, Wx, _ = _two_samples_one_learning_step(oracle_mod, "max", 0.0, 1e-2)
+    _, Ws, _ = _two_samples_one_learning_step(oracle_mod, "soft_max", 0.0, 1e-2, 1.0 / 64)
+    # (the bound is met with equality up to rounding where one sample's term
+    # is 1 and the other's 0: the weights near 20 carry ulps of 3.6e-15)
+    assert (Ws <= Wx + 1e-13).all() and (Ws >= Wx - 1e-2 * math.log(2.0) / 64 - 1e-13).all()
+    assert (Ws < Wx).any()
+
+
+def test_soft_max_monotone_in_tau(oracle_mod):
+    """The log-mean-exp falls as the temperature rises (from the maximum
+    towards the mean): potentiation shrinks, depression grows."""
+    taus = [0.02, 0.05, 0.2, 1.0, 5.0]
+    pot = [_two_samples_one_learning_step(oracle_mod, "soft_max", 0.0, 1e-2, t)[1] for t in taus]
+    dep = [_two_samples_one_learning_step(oracle_mod, "soft_max", 1e-2, 0.0, t)[1] for t in taus]
+    for a, b in zip(pot, pot[1:]):
+        assert (b <= a + 1e-15).all() and (b < a).any()
+    for a, b in zip(dep, dep[1:]):
+        assert (b >= a - 1e-15).all() and (b > a).any()
+
+
+def test_soft_max_theta_increment(oracle_mod):
+    """Theta's increment is the soft maximum of the B spike indicators: a
+    neuron that fired in both samples gains theta_plus exactly as under the
+    mean and the max, one that fired in one sample gains between the mean's
+    theta_plus / 2 and the max's theta_plus (more with a lower temperature),
+    one that never fired nothing."""
+    args = (1e-4, 1e-2)
+    th = {}
+    for r, tau in (("mean", 1.0), ("max", 1.0), ("soft_max", 0.1), ("soft_max", 1.0)):
+        th[(r, tau)] = _two_samples_one_learning_step(oracle_mod, r, *args, tau=tau, adaptive=1)[3]
+    m, x, s1, s2 = th[("mean", 1.0)], th[("max", 1.0)], th[("soft_max", 0.1)], th[("soft_max", 1.0)]
+    np.testing.assert_allclose(s1[2], x[2], rtol=1e-12)
+    np.testing.assert_allclose(s2[2], m[2], rtol=1e-12)
+    for j in (0, 1):
+        assert m[j] < s2[j] < s1[j] < x[j]
+    assert s1[3] == 0.0 and s2[3] == 0.0

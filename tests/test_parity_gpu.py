@@ -163,16 +163,15 @@ def test_reductions_parity(torch_cuda, oracle_mod, reduce, path):
 @pytest.mark.parametrize("path", PATHS + ["auto"])
 def test_signed_max_reduction_parity(torch_cuda, oracle_mod, path):
     """Signed max (the largest per-sample change) through the first burst of
-    excitatory spikes: the gather plasticity kernel of the plain and MFMA
-    routes; the fused and persistent paths fall back to the plain path.  The
-    learned weights follow the signed max, not the per-term max, wherever
-    the two differ."""
+    excitatory spikes, on every path (the MFMA route's plasticity is the
+    plain gather kernel).  The learned weights follow the signed max, not the
+    per-term max, wherever the two differ."""
     cfg = dc_config(100, reduce="max_signed")
     imgs = stroke_images(16, 3, 0.19)
     W = uniform_weights(784, 100, 0.0, 0.3, 1)
     T = 14
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(16, 10), T, path=path)
-    assert g["path"] == (path if path in ("plain", "mfma") else "plain") or (path == "auto" and g["path"] == "mfma")
+    assert g["path"] == path or path == "auto"
     assert ref["exc"].sum() > 100
     t_div = check_parity(g, ref)
     assert t_div == T, f"rasters diverged at step {t_div}: weights not compared"
@@ -181,6 +180,49 @@ def test_signed_max_reduction_parity(torch_cuda, oracle_mod, path):
     diff = np.abs(orc.W - ref["W"]) > 1e-5
     assert diff.sum() > 100
     assert (np.abs(g["W"] - ref["W"])[diff] < 0.5 * np.abs(orc.W - ref["W"])[diff]).all()
+
+
+@pytest.mark.parametrize("path", PATHS + ["auto"])
+@pytest.mark.parametrize("tau", [0.03, 0.3, 3.0])
+def test_soft_max_reduction_parity(torch_cuda, oracle_mod, tau, path):
+    """The soft maximum (log-mean-exp with temperature tau, between the mean
+    and the max) on every path, 60 steps of B = 8 through the first bursts.
+    At tau = 0.03 it is close to the max reduction, at 3 close to the mean;
+    the weights differ from both wherever several samples fire."""
+    cfg = dc_config(100, reduce="soft_max", reduce_tau=tau)
+    imgs = stroke_images(8, 3, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 1)
+    ids = sample_ids(8, 10)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, ids, 60, path=path)
+    assert g["path"] == path or path == "auto"
+    assert ref["exc"].sum() > 50
+    check_parity(g, ref)
+    for other in ("mean", "max"):
+        orc = oracle_mod.OracleNet(dc_config(100, reduce=other), W.astype(np.float64))
+        orc.run(imgs, ids, 60, record=())
+        assert np.abs(orc.W - ref["W"]).max() > 1e-4
+
+
+def test_soft_max_selected_through_the_abi(torch_cuda, oracle_mod):
+    """snn_stdp_reduce_soft on a handle created with the mean reduction:
+    the next run uses the soft maximum at the new temperature; a temperature
+    below the bound is refused and leaves the handle as it was."""
+    from paper_1909_02549_amd.snn import SnnError
+    cfg = dc_config(100)
+    soft = dict(cfg, reduce=4, reduce_tau=0.2)
+    imgs = stroke_images(8, 5, 0.19)
+    W = uniform_weights(784, 100, 0.0, 0.3, 2)
+
+    def select(net):
+        with pytest.raises(SnnError):
+            net.snn_stdp_reduce_soft(1e-3)
+        net.snn_stdp_reduce_soft(0.2)
+    g, _ = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(8, 40), 40, path="persistent",
+                    before=select)
+    orc = oracle_mod.OracleNet(soft, W.astype(np.float64))
+    ref = orc.run(imgs, sample_ids(8, 40), 40, record=("in", "exc", "inh", "v_exc", "counts"))
+    ref["W"], ref["theta"] = orc.W, orc.theta
+    check_parity(g, ref)
 
 
 @pytest.mark.parametrize("path", PATHS + ["auto"])

@@ -73,17 +73,37 @@ def test_wide_block_reduced_forms(torch_cuda, oracle_mod, monkeypatch, precision
     assert np.isfinite(g["W"]).all()
 
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
-@pytest.mark.parametrize("variant", ["max_signed", "norm_per_run"])
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("variant", ["max_signed", "soft_max", "norm_per_run"])
 def test_wide_block_reduction_variants(torch_cuda, oracle_mod, monkeypatch, variant, path):
-    """The signed-max reduction and per-run normalisation at the 25-column
-    block of the 784 -> 6400 layout, through the first burst."""
+    """The signed-max and soft-max reductions and per-run normalisation at the
+    25-column block of the 784 -> 6400 layout, through the first burst."""
     monkeypatch.setenv("SNN_JB", "25")
-    cfg = dc_config(300, reduce="max_signed") if variant == "max_signed" else dc_config(300, norm_per_run=1)
+    cfg = (dc_config(300, reduce=variant, reduce_tau=0.1) if variant != "norm_per_run"
+           else dc_config(300, norm_per_run=1))
     T = 14
     imgs = stroke_images(32, 80, 0.19)
     W = uniform_weights(784, 300, 0.0, 0.3, 44)
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(32, 800), T, path=path)
+    assert g["path"] == path
+    assert ref["exc"].sum() > 100
+    t_div = check_parity(g, ref)
+    assert t_div == T, f"rasters diverged at step {t_div}: weights not compared"
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("reduce", ["max_signed", "soft_max"])
+def test_wide_block_reduced_forms_variant_reductions(torch_cuda, oracle_mod, monkeypatch, reduce, precision, path):
+    """The signed and soft maxima in the reduced operand forms, against the
+    oracle in the same form, through the first burst."""
+    monkeypatch.setenv("SNN_JB", "25")
+    cfg = dc_config(300, reduce=reduce, reduce_tau=0.1)
+    T = 14
+    imgs = stroke_images(32, 81, 0.19)
+    W = uniform_weights(784, 300, 0.0, 0.3, 45)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, imgs, sample_ids(32, 900), T, path=path,
+                      precision=precision)
     assert g["path"] == path
     assert ref["exc"].sum() > 100
     t_div = check_parity(g, ref)
