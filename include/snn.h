@@ -208,6 +208,26 @@ snn_status snn_stdp_reduce(snn_net *net, int32_t mode);
  * or a tau that is not finite or below x_max / 64 (snn_config.reduce_tau). */
 snn_status snn_stdp_reduce_soft(snn_net *net, double tau);
 
+/* Re-form the batch without a reset (an extension of the Dynamic minibatch
+ * size section, which re-initialises every sample's state when the batch
+ * size changes, for continuing simulation as in the Episodic vs. continuing
+ * simulation section).  New slot k < n_keep takes every per-sample variable
+ * of current slot keep_host[k]: voltages, refractory counts and previous
+ * spikes, traces, the last step's inhibitory count and its local step
+ * number (the Poisson encoder's step counter); slots n_keep .. batch - 1
+ * start from the initial state at local step 0.  Weights and theta are
+ * untouched.  The next snn_run / snn_run_spikes without SNN_RUN_RESET at
+ * this batch size continues every slot from there (its images and ids give
+ * slot b's inputs); a run with SNN_RUN_RESET or another batch size resets
+ * as usual.  keep_host: host memory, n_keep distinct entries below the
+ * current batch (0 before any run); may reorder.  Synchronises the handle's
+ * stream and allocates a staging copy of the kept samples' state for the
+ * call.  SNN_EINVAL for a NULL handle, batch 0, n_keep > batch, n_keep above
+ * the current batch, a NULL or invalid list; SNN_ENOMEM for batch above
+ * max_batch or the HBM budget, or a failed allocation (the per-sample state
+ * is then lost and the next run resets). */
+snn_status snn_rebatch(snn_net *net, const uint32_t *keep_host, uint32_t n_keep, uint32_t batch);
+
 /* Select the execution path (snn_path) and the operand form of the
  * contractions (snn_precision).  SNN_EINVAL for values out of range. */
 snn_status snn_set_path(snn_net *net, int32_t path, int32_t precision);

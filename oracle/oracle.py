@@ -138,7 +138,7 @@ class OracleNet:
         self.W = np.ascontiguousarray(W, dtype=np.float64).copy()
         self.theta = np.zeros(n_exc) if theta is None else np.ascontiguousarray(theta, np.float64).copy()
         self.B = 0
-        self.t = 0
+        self.tl = np.zeros(0, np.int64)
 
     # -- state ---------------------------------------------------------------
     def reset(self, B: int):
@@ -148,7 +148,7 @@ class OracleNet:
         n_in, n_exc, n_inh = cfg["n_in"], cfg["n_exc"], cfg["n_inh"]
         ni = max(n_inh, 1)
         self.B = B
-        self.t = 0
+        self.tl = np.zeros(B, np.int64)  # per-sample local step
         self.v_exc = np.full((B, n_exc), float(cfg["exc"]["v_rest"]))
         self.v_inh = np.full((B, ni), float(cfg["inh"]["v_rest"]))
         self.r_exc = np.zeros((B, n_exc), np.int32)
@@ -194,7 +194,7 @@ class OracleNet:
         cnt = rec("counts", (B, n_exc), np.uint32)
         r_th = rec("theta", (T, n_exc), np.float64)
         rc = lib().orc_run(
-            C.byref(self.c), C.c_int(B), C.c_int(T), C.c_int64(self.t),
+            C.byref(self.c), C.c_int(B), C.c_int(T), _ptr(self.tl, C.c_int64),
             _ptr(images, C.c_uint8), _ptr(ids, C.c_uint64), _ptr(forced_in, C.c_uint8),
             _ptr(self.W, C.c_double), _ptr(self.theta, C.c_double),
             _ptr(self.v_exc, C.c_double), _ptr(self.v_inh, C.c_double),
@@ -206,5 +206,22 @@ class OracleNet:
             _ptr(r_th, C.c_double))
         if rc != 0:
             raise RuntimeError(f"orc_run failed: {rc}")
-        self.t += T
+        self.tl += T
         return out
+
+    def rebatch(self, keep, B: int):
+        """Re-form the batch without a reset (an extension of the Dynamic
+        minibatch size section, whose re-initialisation on a size change
+        this avoids for the samples kept): new sample k < len(keep) takes
+        every per-sample variable of old sample keep[k], its local step
+        included; samples len(keep) .. B-1 start from the initial state at
+        local step 0.  Shared parameters are untouched."""
+        keep = np.asarray(keep, dtype=np.int64)
+        assert keep.ndim == 1 and len(keep) <= B and len(set(keep.tolist())) == len(keep)
+        assert (keep >= 0).all() and (keep < self.B).all()
+        old = {k: getattr(self, k) for k in ("v_exc", "v_inh", "r_exc", "r_inh", "x_pre", "x_post",
+                                             "s_exc", "s_inh", "tl")}
+        self.reset(B)
+        n = len(keep)
+        for k, a in old.items():
+            getattr(self, k)[:n] = a[keep]

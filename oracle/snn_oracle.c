@@ -216,7 +216,8 @@ static void lif_step(const orc_lif *p, int n, double alpha, double *v, int32_t *
 /*
  * Run T steps of a batch of B samples, starting from the state passed in
  * (episodic reset is the caller's job: fill v with v_rest and the rest with
- * zeros).  Local step numbers are t_start .. t_start+T-1.
+ * zeros).  Sample b's local step numbers are t_start[b] .. t_start[b]+T-1
+ * (all equal unless the batch was re-formed without a reset).
  *
  * Inputs:   images  B x n_in uint8 (ignored when uniform_rate or forced_in)
  *           ids     B sample ids
@@ -230,7 +231,7 @@ static void lif_step(const orc_lif *p, int n, double alpha, double *v, int32_t *
  *           rec_theta T x n_exc (theta after each step)
  * Returns 0, or -1 on an invalid configuration, -2 on allocation failure.
  */
-int orc_run(const orc_config *c, int B, int T, int64_t t_start,
+int orc_run(const orc_config *c, int B, int T, const int64_t *t_start,
             const uint8_t *images, const uint64_t *ids, const uint8_t *forced_in,
             double *W, double *theta,
             double *v_exc, double *v_inh, int32_t *r_exc, int32_t *r_inh,
@@ -265,11 +266,10 @@ int orc_run(const orc_config *c, int B, int T, int64_t t_start,
     }
 
     for (int k = 0; k < T; ++k) {
-        const uint64_t t = (uint64_t)(t_start + k);
-
-        /* 1. input spikes */
+        /* 1. input spikes (sample b at its own local step t_start[b] + k) */
 #pragma omp parallel for schedule(static)
         for (int b = 0; b < B; ++b) {
+            const uint64_t t = (uint64_t)(t_start[b] + k);
             for (int i = 0; i < n_in; ++i) {
                 uint8_t s;
                 if (forced_in) {

@@ -266,6 +266,19 @@ __global__ void k_reset(Params p, float *v_exc, float *v_inh, uint16_t *rf, floa
                         uint32_t *C, const uint8_t *mask);
 __global__ void k_fill_u32(uint32_t *dst, uint32_t value, size_t n);
 __global__ void k_slot_init(const uint8_t *mask, uint32_t *tl, uint32_t *counts, int n_exc, int B);
+// Staging copy of the kept samples' state while the batch is re-formed
+// (rows k < nk; block-major neuron arrays [g][k][jbp]).
+struct RebatchStage {
+    float *v_exc, *v_inh, *x_post;
+    uint16_t *rf;
+    float *x_pre;  // nk x n_in_pad
+    uint32_t *C, *tl;
+};
+__global__ void k_rebatch_save(Params p, const float *v_exc, const float *v_inh, const float *x_post, const uint16_t *rf,
+                               const float *xpre_last, const uint32_t *C_last, const uint32_t *tl, uint32_t t_uniform,
+                               const uint32_t *keep, int nk, RebatchStage s);
+__global__ void k_rebatch_load(Params p, float *v_exc, float *v_inh, float *x_post, uint16_t *rf, float *xpre_last,
+                               uint32_t *C_cur, uint32_t *C_last, uint32_t *tl, int nk, RebatchStage s);
 __global__ void k_add_u32(uint32_t *v, uint32_t add, int n);
 
 }  // namespace snn

@@ -371,6 +371,75 @@ __global__ void k_slot_init(const uint8_t *__restrict__ mask, uint32_t *__restri
     for (int j = threadIdx.x; j < n_exc; j += blockDim.x) counts[(size_t)b * n_exc + j] = 0u;
 }
 
+// Re-forming the batch without a reset.  k_rebatch_save gathers the
+// per-sample state of the kept samples (old slot keep[k] -> staging row k):
+// the neurons' v_exc, v_inh, x_post and flags, the presynaptic traces and
+// the inhibitory spike count of the last step, the local step (from tl, or
+// t_uniform when every slot shares one).  k_rebatch_load then writes slot
+// b < nk from staging row b and puts slots nk .. B-1 in the initial state at
+// local step 0; it also clears the current step's count slot.  Launched
+// over max(nblk * B * jbp, B * n_in_pad) threads of the layout in question.
+__global__ void k_rebatch_save(Params p, const float *__restrict__ v_exc, const float *__restrict__ v_inh,
+                               const float *__restrict__ x_post, const uint16_t *__restrict__ rf,
+                               const float *__restrict__ xpre_last, const uint32_t *__restrict__ C_last,
+                               const uint32_t *__restrict__ tl, uint32_t t_uniform, const uint32_t *__restrict__ keep,
+                               int nk, RebatchStage s)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)p.nblk * nk * p.jbp) {
+        const int jj = (int)(t % p.jbp);
+        const size_t gk = t / p.jbp;
+        const int k = (int)(gk % nk);
+        const int g = (int)(gk / nk);
+        const size_t src = ((size_t)g * p.Bs + keep[k]) * p.jbp + jj;
+        s.v_exc[t] = v_exc[src];
+        s.v_inh[t] = v_inh[src];
+        s.x_post[t] = x_post[src];
+        s.rf[t] = rf[src];
+    }
+    if (t < (size_t)nk * p.n_in_pad) {
+        const int k = (int)(t / p.n_in_pad);
+        s.x_pre[t] = xpre_last[(size_t)keep[k] * p.n_in_pad + t % p.n_in_pad];
+    }
+    if (t < (size_t)nk) {
+        s.C[t] = C_last[keep[t]];
+        s.tl[t] = tl ? tl[keep[t]] : t_uniform;
+    }
+}
+
+__global__ void k_rebatch_load(Params p, float *__restrict__ v_exc, float *__restrict__ v_inh,
+                               float *__restrict__ x_post, uint16_t *__restrict__ rf, float *__restrict__ xpre_last,
+                               uint32_t *__restrict__ C_cur, uint32_t *__restrict__ C_last, uint32_t *__restrict__ tl,
+                               int nk, RebatchStage s)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)p.nblk * p.B * p.jbp) {
+        const int jj = (int)(t % p.jbp);
+        const size_t gb = t / p.jbp;
+        const int b = (int)(gb % p.B);
+        const int g = (int)(gb / p.B);
+        const size_t n = ((size_t)g * p.Bs + b) * p.jbp + jj;
+        if (b < nk) {
+            const size_t q = ((size_t)g * nk + b) * p.jbp + jj;
+            v_exc[n] = s.v_exc[q];
+            v_inh[n] = s.v_inh[q];
+            x_post[n] = s.x_post[q];
+            rf[n] = s.rf[q];
+        } else {
+            v_exc[n] = p.exc.v_rest;
+            v_inh[n] = p.inh.v_rest;
+            x_post[n] = 0.f;
+            rf[n] = 0;
+        }
+    }
+    if (t < (size_t)p.B * p.n_in_pad) xpre_last[t] = t < (size_t)nk * p.n_in_pad ? s.x_pre[t] : 0.f;
+    if (t < (size_t)p.B) {
+        C_cur[t] = 0u;
+        C_last[t] = (int)t < nk ? s.C[t] : 0u;
+        tl[t] = (int)t < nk ? s.tl[t] : 0u;
+    }
+}
+
 // Serving: every slot's local step advances by the steps just run.
 __global__ void k_add_u32(uint32_t *__restrict__ v, uint32_t add, int n)
 {

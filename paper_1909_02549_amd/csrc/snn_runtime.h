@@ -49,6 +49,10 @@ struct snn_net {
     uint32_t run_T = 0;          // steps of the current snn_run call (per-run normalisation)
     uint32_t cap_chunk = kChunk; // steps the buffers hold at capacity
     uint8_t *flags_mask = nullptr;
+    // per-slot local steps of a batch re-formed by snn_rebatch (per_slot:
+    // continuing runs encode slot b at slot_t[b] + k; else every slot at tloc)
+    uint32_t *slot_t = nullptr;
+    bool per_slot = false;
 
     // optional per-kernel timing with HIP events on the handle's stream: one
     // event pair brackets each run of consecutive launches of one kernel (a
@@ -97,7 +101,8 @@ struct snn_net {
     snn_status episode(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch,
                        uint32_t T, const snn::Outs &o);
     snn_status episode_body(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
-                            uint32_t batch, uint32_t T, const snn::Outs &o);
+                            uint32_t batch, uint32_t T, const snn::Outs &o, const uint32_t *tl = nullptr);
+    snn_status rebatch(const uint32_t *keep_dev, uint32_t n_keep, uint32_t B);
     snn_status run_graph(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
                          uint32_t batch, uint32_t T, const snn::Outs &o);
     snn_status encode_chunk(const uint8_t *img, const uint64_t *ids, const uint32_t *tl, uint64_t tbase, int steps,

@@ -305,15 +305,16 @@ void snn_net::free_state()
 {
     for (void *q : {(void *)v_exc, (void *)v_inh, (void *)x_post, (void *)I, (void *)rf, (void *)x_pre, (void *)C,
                     (void *)bits, (void *)bitsT, (void *)flags_mask, (void *)lin, (void *)cin, (void *)lt, (void *)ct,
-                    (void *)ord_s, (void *)ord_in})
+                    (void *)ord_s, (void *)ord_in, (void *)slot_t})
         if (q) (void)hipFree(q);
     v_exc = v_inh = x_post = I = x_pre = nullptr;
     rf = nullptr;
     lin = lt = ord_s = ord_in = nullptr;
-    C = bits = bitsT = cin = ct = nullptr;
+    C = bits = bitsT = cin = ct = slot_t = nullptr;
     flags_mask = nullptr;
     cap_B = 0;
     cur_B = 0;
+    per_slot = false;
 }
 
 // The column block width a new handle starts with: one block per CU when the
@@ -590,6 +591,7 @@ snn_status snn_net::ensure_state(uint32_t B)
         A((void **)&ord_s, (size_t)(ch + 1) * B * 2);
         A((void **)&ord_in, (size_t)(ch + 1) * p.n_in_pad * 2);
         A((void **)&flags_mask, B);
+        A((void **)&slot_t, (size_t)B * 4);
         if (e != hipSuccess) {
             free_state();
             return fail(SNN_ENOMEM, std::string("state hipMalloc: ") + hipGetErrorString(e));
@@ -756,13 +758,87 @@ snn_status snn_net::run(const uint8_t *images, const uint64_t *ids, const uint32
         }
     }
     set_batch(batch);
+    if (reset) per_slot = false;
     if (reset && use_graphs && !prof) return run_graph(path, images, ids, forced, batch, T, o);
     if (reset) {
         st = reset_state(nullptr);
         if (st != SNN_OK) return st;
         cur_B = batch;
     }
-    return episode_body(path, images, ids, forced, batch, T, o);
+    if (!per_slot) return episode_body(path, images, ids, forced, batch, T, o);
+    // a batch re-formed by snn_rebatch: every slot at its own local step
+    st = episode_body(path, images, ids, forced, batch, T, o, slot_t);
+    if (st != SNN_OK) return st;
+    SNN_LAUNCH("slot_step", k_add_u32, dim3((batch + 255) / 256), dim3(256), 0, slot_t, T, (int)batch);
+    HIP_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
+// Re-form the batch without a reset: new slot k < n_keep takes the state of
+// old slot keep[k] (host list, checked by the caller), the other slots start
+// fresh; see snn_rebatch.
+snn_status snn_net::rebatch(const uint32_t *keep_host, uint32_t n_keep, uint32_t B)
+{
+    const int nk = (int)n_keep;
+    // staging rows of the kept samples and the list itself, in one allocation
+    const size_t ns = (size_t)p.nblk * p.jbp * n_keep;
+    const size_t nx = (size_t)n_keep * p.n_in_pad;
+    size_t off[8], total = 0;
+    const size_t sizes[8] = {ns * 4, ns * 4, ns * 4, ns * 2, nx * 4, (size_t)n_keep * 4, (size_t)n_keep * 4,
+                             (size_t)n_keep * 4};
+    for (int q = 0; q < 8; ++q) {
+        off[q] = total;
+        total += align16(std::max<size_t>(sizes[q], 16));
+    }
+    unsigned char *stage = nullptr;
+    const uint32_t *keep_dev = nullptr;
+    if (n_keep > 0) {
+        hipError_t e = hipMalloc((void **)&stage, total);
+        if (e != hipSuccess) return fail(SNN_ENOMEM, std::string("rebatch staging: ") + hipGetErrorString(e));
+        keep_dev = reinterpret_cast<const uint32_t *>(stage + off[7]);
+        e = hipMemcpyAsync(stage + off[7], keep_host, (size_t)n_keep * 4, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(SNN_EDEVICE, std::string("rebatch list copy: ") + hipGetErrorString(e));
+        }
+    }
+    RebatchStage rs{};  // (no staging when no sample is kept: k_rebatch_load reads none)
+    if (stage)
+        rs = RebatchStage{reinterpret_cast<float *>(stage + off[0]), reinterpret_cast<float *>(stage + off[1]),
+                          reinterpret_cast<float *>(stage + off[2]), reinterpret_cast<uint16_t *>(stage + off[3]),
+                          reinterpret_cast<float *>(stage + off[4]), reinterpret_cast<uint32_t *>(stage + off[5]),
+                          reinterpret_cast<uint32_t *>(stage + off[6])};
+    const int tpb = 256;
+    snn_status st = SNN_OK;
+    if (n_keep > 0) {
+        const size_t n = std::max(ns, nx);
+        SNN_LAUNCH("rebatch_save", k_rebatch_save, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, p,
+                   (const float *)v_exc, (const float *)v_inh, (const float *)x_post, (const uint16_t *)rf,
+                   (const float *)(x_pre + (size_t)((gstep + 2) % 3) * p.Bs * p.n_in_pad),
+                   (const uint32_t *)(C + (size_t)((gstep + 2) % 3) * p.Bs), per_slot ? (const uint32_t *)slot_t : nullptr,
+                   (uint32_t)tloc, keep_dev, nk, rs);
+        if (hipGetLastError() != hipSuccess) st = fail(SNN_EDEVICE, "k_rebatch_save launch failed");
+    }
+    // (a larger batch than the capacity reallocates the state; the staging
+    // copy is complete first: ensure_state waits for the stream)
+    if (st == SNN_OK) st = ensure_state(B);
+    if (st == SNN_OK) {
+        set_batch(B);
+        const size_t n = std::max((size_t)p.nblk * p.jbp * B, (size_t)B * p.n_in_pad);
+        SNN_LAUNCH("rebatch_load", k_rebatch_load, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, p, v_exc,
+                   v_inh, x_post, rf, x_pre + (size_t)((gstep + 2) % 3) * p.Bs * p.n_in_pad,
+                   C + (size_t)(gstep % 3) * p.Bs, C + (size_t)((gstep + 2) % 3) * p.Bs, slot_t, nk, rs);
+        if (hipGetLastError() != hipSuccess) st = fail(SNN_EDEVICE, "k_rebatch_load launch failed");
+    }
+    if (stage) {
+        if (hipStreamSynchronize(stream) != hipSuccess && st == SNN_OK) st = fail(SNN_EDEVICE, "rebatch: stream error");
+        (void)hipFree(stage);
+    }
+    if (st != SNN_OK) return st;
+    cur_B = B;
+    per_slot = true;
+    return SNN_OK;
 }
 
 // One episode from a reset state: reset, clear the outputs, run T steps.
@@ -777,7 +853,7 @@ snn_status snn_net::episode(int path, const uint8_t *images, const uint64_t *ids
 
 // Clear the outputs of a run, then T steps on `path`.
 snn_status snn_net::episode_body(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced,
-                                 uint32_t batch, uint32_t T, const Outs &o)
+                                 uint32_t batch, uint32_t T, const Outs &o, const uint32_t *tl)
 {
     const int words = (p.n_exc + 31) / 32;
     auto zero = [&](uint32_t *ptr, size_t n) {
@@ -789,7 +865,7 @@ snn_status snn_net::episode_body(int path, const uint8_t *images, const uint64_t
     zero(o.raster_exc, (size_t)T * batch * words);
     zero(o.raster_inh, (size_t)T * batch * words);
     HIP_TRY(hipGetLastError());
-    return run_steps(path, images, ids, forced, T, o);
+    return run_steps(path, images, ids, forced, T, o, tl);
 }
 
 snn_status snn_net::xpre_first(const uint32_t *bits_t)
@@ -1009,6 +1085,22 @@ extern "C" snn_status snn_run(snn_net *net, const uint8_t *images_dev, const uin
 {
     if (!net) return fail(SNN_EINVAL, "net is NULL");
     return net->run(images_dev, ids_dev, nullptr, batch, T, flags, out);
+}
+
+extern "C" snn_status snn_rebatch(snn_net *net, const uint32_t *keep_host, uint32_t n_keep, uint32_t batch)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (batch == 0) return fail(SNN_EINVAL, "batch must be > 0");
+    if (n_keep > batch) return fail(SNN_EINVAL, "n_keep exceeds the new batch");
+    if (n_keep > 0 && !keep_host) return fail(SNN_EINVAL, "keep_host is NULL");
+    if (n_keep > net->cur_B) return fail(SNN_EINVAL, "n_keep exceeds the current batch");
+    std::vector<uint8_t> seen(net->cur_B, 0);
+    for (uint32_t k = 0; k < n_keep; ++k) {
+        if (keep_host[k] >= net->cur_B) return fail(SNN_EINVAL, "keep entry beyond the current batch");
+        if (seen[keep_host[k]]++) return fail(SNN_EINVAL, "keep entries must be distinct");
+    }
+    if (batch > net->cfg.max_batch) return fail(SNN_ENOMEM, "batch exceeds max_batch");
+    return net->rebatch(keep_host, n_keep, batch);
 }
 
 extern "C" snn_status snn_run_spikes(snn_net *net, const uint32_t *in_bits_dev, uint32_t batch, uint32_t T,

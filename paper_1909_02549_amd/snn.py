@@ -26,7 +26,7 @@ STATUS = {0: "SNN_OK", -1: "SNN_EINVAL", -2: "SNN_ENOMEM", -3: "SNN_EDEVICE", -4
 
 EXPORTED = ["snn_abi_version", "snn_last_error", "snn_create", "snn_destroy", "snn_set_stream",
             "snn_set_weights", "snn_get_weights", "snn_set_theta", "snn_get_theta", "snn_stdp_reduce", "snn_stdp_reduce_soft",
-            "snn_set_path", "snn_last_path", "snn_set_graphs", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
+            "snn_set_path", "snn_rebatch", "snn_last_path", "snn_set_graphs", "snn_run", "snn_run_spikes", "snn_sync", "snn_state_bytes",
             "snn_profile_enable", "snn_profile_get",
             "snn_serve_create", "snn_serve_submit", "snn_serve_poll", "snn_serve_stats",
             "snn_serve_destroy", "snn_ifnet_create", "snn_ifnet_destroy", "snn_ifnet_set_layer", "snn_ifnet_run",
@@ -100,6 +100,7 @@ def load_library():
         "snn_stdp_reduce": ([VP, I32], I32),
         "snn_stdp_reduce_soft": ([VP, C.c_double], I32),
         "snn_set_path": ([VP, I32, I32], I32),
+        "snn_rebatch": ([VP, VP, U32, U32], I32),
         "snn_last_path": ([VP, P(I32)], I32),
         "snn_set_graphs": ([VP, I32], I32),
         "snn_run": ([VP, VP, VP, U32, U32, U32, P(snn_outputs)], I32),
@@ -230,6 +231,12 @@ class Net:
     def snn_set_path(self, path="plain", precision="fp32"):
         _check(self.lib.snn_set_path(self.h, PATHS[path] if isinstance(path, str) else int(path),
                                      PRECISIONS[precision] if isinstance(precision, str) else int(precision)))
+
+    def snn_rebatch(self, keep, batch: int):
+        """Re-form the batch without a reset: new slot k < len(keep) takes
+        the state of current slot keep[k]; the other slots start fresh."""
+        k = np.ascontiguousarray(np.asarray(keep, dtype=np.uint32))
+        _check(self.lib.snn_rebatch(self.h, k.ctypes.data if k.size else None, int(k.size), int(batch)))
 
     def snn_set_graphs(self, on: bool = True):
         _check(self.lib.snn_set_graphs(self.h, 1 if on else 0))

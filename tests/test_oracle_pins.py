@@ -633,3 +633,76 @@ def test_soft_max_theta_increment(oracle_mod):
     for j in (0, 1):
         assert m[j] < s2[j] < s1[j] < x[j]
     assert s1[3] == 0.0 and s2[3] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# re-forming the batch without a reset (rebatch)
+# ---------------------------------------------------------------------------
+
+def test_rebatch_identity_and_empty(oracle_mod):
+    """Keeping every sample in order changes nothing (the continuing run is
+    bit-identical to one without the call); keeping none equals an episodic
+    reset from the weights and thresholds of that moment."""
+    cfg, W = dc_small()
+    imgs, ids = stroke_images(4, 21, 0.2), sample_ids(4, 70)
+    a = oracle_mod.OracleNet(cfg, W)
+    a.run(imgs, ids, 30)
+    ra = a.run(imgs, ids, 20, reset=False)
+    b = oracle_mod.OracleNet(cfg, W)
+    b.run(imgs, ids, 30)
+    b.rebatch([0, 1, 2, 3], 4)
+    rb = b.run(imgs, ids, 20, reset=False)
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    assert np.array_equal(a.W, b.W) and np.array_equal(a.theta, b.theta)
+    c = oracle_mod.OracleNet(cfg, W)
+    c.run(imgs, ids, 30)
+    d = oracle_mod.OracleNet(cfg, c.W.copy(), c.theta.copy())
+    c.rebatch([], 4)
+    rc = c.run(imgs, ids, 20, reset=False)
+    rd = d.run(imgs, ids, 20)
+    for k in rc:
+        assert np.array_equal(rc[k], rd[k]), k
+    assert ra["exc"].sum() > 0
+
+
+def test_rebatch_samples_continue_independently(oracle_mod):
+    """Learning off, so the samples do not interact: after re-forming, each
+    kept sample continues exactly as in the original batch (its own local
+    step, traces, voltages and last spikes carried over) and each new sample
+    runs exactly as alone from a reset."""
+    cfg, W = dc_small(learn=False)
+    imgs, ids = stroke_images(4, 22, 0.25), sample_ids(4, 80)
+    new, nid = stroke_images(2, 23, 0.25), sample_ids(2, 90)
+    full = oracle_mod.OracleNet(cfg, W)
+    full.run(imgs, ids, 30)
+    cont = full.run(imgs, ids, 25, reset=False)
+    rb = oracle_mod.OracleNet(cfg, W)
+    rb.run(imgs, ids, 30)
+    rb.rebatch([3, 1], 4)
+    out = rb.run(np.concatenate([imgs[[3, 1]], new]), np.concatenate([ids[[3, 1]], nid]), 25, reset=False)
+    alone = oracle_mod.OracleNet(cfg, W).run(new, nid, 25)
+    for k in ("exc", "inh", "in", "v_exc"):
+        assert np.array_equal(out[k][0], cont[k][3]) and np.array_equal(out[k][1], cont[k][1]), k
+        assert np.array_equal(out[k][2:], alone[k]), k
+    assert cont["exc"][[1, 3]].sum() > 0 and alone["exc"].sum() > 0
+
+
+def test_rebatch_permutation_with_max_reduction(oracle_mod):
+    """With learning under the max reduction (independent of the order of
+    the samples), a permuted batch continues as the original one permuted,
+    weights and thresholds included, bit for bit."""
+    cfg, W = dc_small(reduce="max")
+    imgs, ids = stroke_images(4, 24, 0.25), sample_ids(4, 100)
+    perm = [2, 0, 3, 1]
+    a = oracle_mod.OracleNet(cfg, W)
+    a.run(imgs, ids, 30)
+    ra = a.run(imgs, ids, 25, reset=False)
+    b = oracle_mod.OracleNet(cfg, W)
+    b.run(imgs, ids, 30)
+    b.rebatch(perm, 4)
+    rb = b.run(imgs[perm], ids[perm], 25, reset=False)
+    for k in ("exc", "inh", "in", "v_exc", "counts"):
+        assert np.array_equal(rb[k], ra[k][perm]), k
+    assert np.array_equal(a.W, b.W) and np.array_equal(a.theta, b.theta)
+    assert ra["exc"].sum() > 0

@@ -278,6 +278,125 @@ def continuing_pair(torch, oracle_mod, cfg, W, imgs, ids, path, T1, T2, precisio
     return gs, rs
 
 
+def call_sequence(torch, oracle_mod, cfg, W, max_batch, path, ops, precision="fp32"):
+    """Calls on one handle and, in step, on one oracle: ("run", imgs, ids, T,
+    reset) or ("rebatch", keep, batch).  Returns ([gpu], [ref]) with each
+    run's records and the weights and thresholds after it."""
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    net = Net(cfg, max_batch=max_batch, path=path, precision=precision)
+    net.snn_set_weights(W)
+    orc = oracle_mod.OracleNet(cfg, W.astype(np.float64), precision=precision)
+    rec = ("in", "exc", "inh", "v_exc", "counts")
+    gs, rs = [], []
+    for op in ops:
+        if op[0] == "rebatch":
+            net.snn_rebatch(op[1], op[2])
+            orc.rebatch(op[1], op[2])
+            continue
+        _, imgs, ids, T, reset = op
+        out = net.snn_run(to_dev(torch, imgs), to_dev(torch, ids.astype(np.int64)), T, reset=reset, record=rec)
+        torch.cuda.synchronize()
+        g = {"in": unpack_bits(out["in"].cpu().numpy(), cfg["n_in"]).transpose(1, 0, 2),
+             "exc": unpack_bits(out["exc"].cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2),
+             "inh": unpack_bits(out["inh"].cpu().numpy(), cfg["n_exc"]).transpose(1, 0, 2),
+             "v_exc": out["v_exc"].cpu().numpy().transpose(1, 0, 2),
+             "counts": out["counts"].cpu().numpy().astype(np.int64),
+             "W": net.snn_get_weights(), "theta": net.snn_get_theta(), "path": net.snn_last_path()}
+        r = orc.run(imgs, ids, T, reset=reset, record=rec)
+        r["W"], r["theta"] = orc.W.copy(), orc.theta.copy()
+        gs.append(g)
+        rs.append(r)
+    net.close()
+    return gs, rs
+
+
+@pytest.mark.parametrize("path", PATHS + ["auto"])
+def test_rebatch_parity(torch_cuda, oracle_mod, path):
+    """Continuing across re-formed batches (snn_rebatch): 8 samples for 30
+    steps; samples 5, 2 and 7 kept as slots 0-2 with three new samples, 30
+    steps; then all six kept in a new order with six more (12 slots, above
+    the capacity the handle had allocated), 20 steps.  Kept samples continue
+    their input streams at their own local steps, new ones start at step 0.
+    Every call meets the parity bars against the oracle doing the same."""
+    cfg = dc_config(100)
+    W = uniform_weights(784, 100, 0.0, 0.3, 11)
+    imgs8, ids8 = stroke_images(8, 31, 0.19), sample_ids(8, 300)
+    new3, nid3 = stroke_images(3, 32, 0.19), sample_ids(3, 400)
+    imgs6 = np.concatenate([imgs8[[5, 2, 7]], new3])
+    ids6 = np.concatenate([ids8[[5, 2, 7]], nid3])
+    order = [4, 0, 5, 1, 3, 2]
+    new6, nid6 = stroke_images(6, 33, 0.19), sample_ids(6, 500)
+    imgs12 = np.concatenate([imgs6[order], new6])
+    ids12 = np.concatenate([ids6[order], nid6])
+    ops = [("run", imgs8, ids8, 30, True), ("rebatch", [5, 2, 7], 6), ("run", imgs6, ids6, 30, False),
+           ("rebatch", order, 12), ("run", imgs12, ids12, 20, False)]
+    gs, rs = call_sequence(torch_cuda, oracle_mod, cfg, W, 12, path, ops)
+    for g, r in zip(gs, rs):
+        assert g["path"] == path or path == "auto"
+        check_parity(g, r)
+    assert rs[1]["exc"].sum() > 20 and rs[2]["exc"].sum() > 20
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_rebatch_keeps_samples_independent(torch_cuda, path):
+    """Learning off, so samples do not interact: after snn_rebatch each kept
+    sample's spikes and voltages continue exactly as in the original batch,
+    bit for bit, and a new sample's equal its own episodic run."""
+    from paper_1909_02549_amd.snn import Net, unpack_bits
+    cfg = dc_config(100, learn=False)
+    W = uniform_weights(784, 100, 0.0, 0.3, 12)
+    imgs, ids = stroke_images(6, 34, 0.19), sample_ids(6, 600)
+    new, nid = stroke_images(1, 35, 0.19), sample_ids(1, 700)
+    rec = ("exc", "v_exc")
+
+    def run(net, im, i, T, reset):
+        out = net.snn_run(to_dev(torch_cuda, im), to_dev(torch_cuda, i.astype(np.int64)), T, reset=reset,
+                          record=rec)
+        torch_cuda.cuda.synchronize()
+        return (unpack_bits(out["exc"].cpu().numpy(), 100).transpose(1, 0, 2),
+                out["v_exc"].cpu().numpy().transpose(1, 0, 2))
+    a = Net(cfg, max_batch=8, path=path)
+    a.snn_set_weights(W)
+    run(a, imgs, ids, 25, True)
+    ea, va = run(a, imgs, ids, 25, False)
+    b = Net(cfg, max_batch=8, path=path)
+    b.snn_set_weights(W)
+    run(b, imgs, ids, 25, True)
+    b.snn_rebatch([4, 1], 3)
+    eb, vb = run(b, np.concatenate([imgs[[4, 1]], new]), np.concatenate([ids[[4, 1]], nid]), 25, False)
+    c = Net(cfg, max_batch=8, path=path)
+    c.snn_set_weights(W)
+    ec, vc = run(c, new, nid, 25, True)
+    assert np.array_equal(eb[0], ea[4]) and np.array_equal(eb[1], ea[1]) and np.array_equal(eb[2], ec[0])
+    assert np.array_equal(vb[0], va[4]) and np.array_equal(vb[1], va[1]) and np.array_equal(vb[2], vc[0])
+    assert ea[[1, 4]].sum() > 0
+    for n in (a, b, c):
+        n.close()
+
+
+def test_rebatch_errors(torch_cuda):
+    from paper_1909_02549_amd.snn import Net, SnnError
+    cfg = dc_config(100)
+    net = Net(cfg, max_batch=8)
+    net.snn_set_weights(uniform_weights(784, 100, 0.0, 0.3, 13))
+    with pytest.raises(SnnError):
+        net.snn_rebatch([0], 4)                  # no samples yet
+    net.snn_rebatch([], 4)                       # a fresh batch of 4
+    imgs, ids = stroke_images(4, 36, 0.19), sample_ids(4, 800)
+    net.snn_run(to_dev(torch_cuda, imgs), to_dev(torch_cuda, ids.astype(np.int64)), 5, reset=False)
+    for keep, B in (([4], 4), ([1, 1], 4), ([0, 1, 2], 2), ([0], 0)):
+        with pytest.raises(SnnError) as e:
+            net.snn_rebatch(keep, B)
+        assert e.value.status == -1
+    with pytest.raises(SnnError) as e:
+        net.snn_rebatch([0], 9)
+    assert e.value.status == -2
+    net.snn_rebatch([3, 0], 2)                   # still usable after the refusals
+    net.snn_run(to_dev(torch_cuda, imgs[[3, 0]]), to_dev(torch_cuda, ids[[3, 0]].astype(np.int64)), 5, reset=False)
+    net.snn_sync()
+    net.close()
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_continuing_run_parity(torch_cuda, oracle_mod, path):
     """Continuing simulation (Episodic vs. continuing simulation section): a
