@@ -221,8 +221,8 @@ __device__ __forceinline__ void red4(int mode, float *acc, const float4 v)
 __device__ __forceinline__ float4 round4(int prec, float4 v)
 {
     if (!prec) return v;
-    return make_float4(operand_value(prec, v.x), operand_value(prec, v.y), operand_value(prec, v.z),
-                       operand_value(prec, v.w));
+    const f32x2_t lo = operand_value2(prec, v.x, v.y), hi = operand_value2(prec, v.z, v.w);
+    return make_float4(lo.x, lo.y, hi.x, hi.y);
 }
 
 // A trace value as a summand of the reduction of kind RK (the soft maximum's
@@ -248,9 +248,15 @@ __device__ __forceinline__ float red_out(const Params &p, float S)
     return p.reduce == RED_MEAN ? S * p.inv_B : S;
 }
 
-template <int RK = RK_STD>
+__device__ __forceinline__ float4 mul4(float4 a, float4 b) { return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w); }
+
+// Scale: each row value is first multiplied by the column's pending
+// normalisation scale (slo: columns c0 .. c0 + 3, shi: c0 + 4 .. c0 + 7), so
+// that the operand rounding sees the normalised FP32 weight.
+template <int RK = RK_STD, bool Scale = false>
 __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const float *rows, int jbp, int c0, int zero_row,
-                                            int mode, float *acc, int prec, float ksoft = 0.f)
+                                            int mode, float *acc, int prec, float ksoft = 0.f,
+                                            float4 slo = float4{}, float4 shi = float4{})
 {
     const int i0 = (int)(q.x & 0xFFFFu);
     const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
@@ -262,10 +268,11 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
     const float4 *r1 = reinterpret_cast<const float4 *>(rows + __mul24(i1, jbp) + c0);
     const float4 *r2 = reinterpret_cast<const float4 *>(rows + __mul24(i2, jbp) + c0);
     const float4 *r3 = reinterpret_cast<const float4 *>(rows + __mul24(i3, jbp) + c0);
-    const float4 a0 = red_in4<RK>(round4(prec, r0[0]), ksoft), b0 = red_in4<RK>(round4(prec, r0[1]), ksoft);
-    const float4 a1 = red_in4<RK>(round4(prec, r1[0]), ksoft), b1 = red_in4<RK>(round4(prec, r1[1]), ksoft);
-    const float4 a2 = red_in4<RK>(round4(prec, r2[0]), ksoft), b2 = red_in4<RK>(round4(prec, r2[1]), ksoft);
-    const float4 a3 = red_in4<RK>(round4(prec, r3[0]), ksoft), b3 = red_in4<RK>(round4(prec, r3[1]), ksoft);
+    auto val = [&](float4 v, float4 sc) { return red_in4<RK>(round4(prec, Scale ? mul4(v, sc) : v), ksoft); };
+    const float4 a0 = val(r0[0], slo), b0 = val(r0[1], shi);
+    const float4 a1 = val(r1[0], slo), b1 = val(r1[1], shi);
+    const float4 a2 = val(r2[0], slo), b2 = val(r2[1], shi);
+    const float4 a3 = val(r3[0], slo), b3 = val(r3[1], shi);
     if (mode == RED_MAX) {
         red4(mode, acc, a0), red4(mode, acc + 4, b0);
         red4(mode, acc, a1), red4(mode, acc + 4, b1);
@@ -282,9 +289,10 @@ __device__ __forceinline__ void gather4rows(uint2 q, int k0, int cnt, const floa
 // The entries k0 .. cnt of a list (k0 a multiple of 4), 4 * NW at a time:
 // the NW 8-byte list words of a batch are loaded together, then gathered in
 // list order (the additions are those of a one-word-at-a-time walk).
-template <int NW = 4, int RK = RK_STD>
+template <int NW = 4, int RK = RK_STD, bool Scale = false>
 __device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0, int cnt, const float *rows, int jbp,
-                                            int c0, int zero_row, int mode, float *acc, int prec, float ksoft = 0.f)
+                                            int c0, int zero_row, int mode, float *acc, int prec, float ksoft = 0.f,
+                                            float4 slo = float4{}, float4 shi = float4{})
 {
     for (; k0 < cnt; k0 += 4 * NW) {
         uint2 e[NW];
@@ -293,7 +301,8 @@ __device__ __forceinline__ void gather_tail(const uint2 *__restrict__ l4, int k0
 #pragma unroll
         for (int q = 0; q < NW; ++q)
             if (k0 + 4 * q < cnt)
-                gather4rows<RK>(e[q], k0 + 4 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft);
+                gather4rows<RK, Scale>(e[q], k0 + 4 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec, ksoft, slo,
+                                       shi);
     }
 }
 
@@ -319,19 +328,24 @@ __device__ __forceinline__ void gather8(const uint16_t *__restrict__ list, int c
 // The same with the first 8 * NH entries of the list in h[0 .. NH) (16-byte
 // words loaded together ahead of time, so a list of up to 8 * NH entries costs
 // one memory round trip); entries past those are read from `list`.
-template <int NH>
+template <int NH, bool Scale = false>
 __device__ __forceinline__ void gather_pre(const uint16_t *__restrict__ list, int cnt, const uint4 *h, const float *rows,
-                                           int jbp, int c0, int zero_row, int mode, float *acc, int prec)
+                                           int jbp, int c0, int zero_row, int mode, float *acc, int prec,
+                                           float4 slo = float4{}, float4 shi = float4{})
 {
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
 #pragma unroll
     for (int q = 0; q < NH; ++q) {
-        if (8 * q < cnt) gather4rows(make_uint2(h[q].x, h[q].y), 8 * q, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+        if (8 * q < cnt)
+            gather4rows<RK_STD, Scale>(make_uint2(h[q].x, h[q].y), 8 * q, cnt, rows, jbp, c0, zero_row, mode, acc,
+                                       prec, 0.f, slo, shi);
         if (8 * q + 4 < cnt)
-            gather4rows(make_uint2(h[q].z, h[q].w), 8 * q + 4, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+            gather4rows<RK_STD, Scale>(make_uint2(h[q].z, h[q].w), 8 * q + 4, cnt, rows, jbp, c0, zero_row, mode, acc,
+                                       prec, 0.f, slo, shi);
     }
-    gather_tail<2>(reinterpret_cast<const uint2 *>(list), 8 * NH, cnt, rows, jbp, c0, zero_row, mode, acc, prec);
+    gather_tail<2, RK_STD, Scale>(reinterpret_cast<const uint2 *>(list), 8 * NH, cnt, rows, jbp, c0, zero_row, mode,
+                                  acc, prec, 0.f, slo, shi);
 }
 
 // Load the first 8 * NH entries of a list (NH 16-byte words, all in flight).
@@ -360,14 +374,15 @@ __device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, co
 
 // Step phase B for one task: 8 neurons j0+c of sample b (c < nv real).
 // acc: column sums of the sample's input spikes over the LDS block (raw,
-// before the pending scale); cp: the sample's inhibitory spike count of step
-// t - 1.  Updates the register state, the post traces in LDS, the spike
+// before the pending scale, unless scaled: then each weight was multiplied
+// by its column's scale before its operand rounding); cp: the sample's
+// inhibitory spike count of step t - 1.  Updates the register state, the post traces in LDS, the spike
 // masks and the inhibitory count; writes requested outputs.  Returns the
 // excitatory spikes as bits 0..7.
 template <class PP>
 __device__ __forceinline__ uint32_t neuron_task(const PP &p, const StepLds &S, const Outs &o, int k, int b, int c0,
                                                 int j0, int nv, const float *acc, uint32_t cp, float *ve, float *vi,
-                                                uint32_t *rw)
+                                                uint32_t *rw, bool scaled = false)
 {
     float xp[8];
     if (p.learn) {
@@ -385,7 +400,7 @@ __device__ __forceinline__ uint32_t neuron_task(const PP &p, const StepLds &S, c
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int jl = c0 + c;
-        const float I = acc[c] * S.scalef[jl];
+        const float I = scaled ? acc[c] : acc[c] * S.scalef[jl];
         NeuronState st{ve[c], vi[c], (rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu, xp[c]};
         bool se, si;
         neuron_update(p, I, cp, S.th[jl], st, se, si);
@@ -1136,20 +1151,6 @@ __device__ __forceinline__ void plasticity_all(const Params &p, const StepLds &S
                                         prec, prec_d);
         r = rn;
     }
-}
-
-// Apply the pending column scale to the LDS block (w <- float(w * scale))
-// and reset it: the reduced-precision forms round the normalised weight.
-__device__ __forceinline__ void apply_scale(const Params &p, const StepLds &S, int tid, int nt)
-{
-    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
-    if (jj < p.jb) {
-        const double sc = S.scale[jj];
-        for (int i = rg; i < p.n_in; i += nrg) S.W[i * p.ls + jj] = (float)((double)S.W[i * p.ls + jj] * sc);
-    }
-    __syncthreads();
-    if (tid < 32) S.scale[tid] = 1.0, S.scalef[tid] = 1.f;
-    __syncthreads();
 }
 
 // Phase C3: FP64 column sums of the updated block, the pending

@@ -11,59 +11,63 @@ namespace snn {
 
 enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
 
-// bfloat16 code of x, round to nearest even (finite x).
-__device__ __forceinline__ uint32_t bf16_code(float x)
+// The two reduced operand forms, on the conversion instructions of gfx950:
+//   bfloat16: round to nearest even (v_cvt_pk_bf16_f32);
+//   OCP FP8 E4M3: 4 significant bits, exponent bias 7, subnormal spacing 2^-9
+//     below 2^-6, round to nearest even, saturating at +-448 (a clamp, then
+//     v_cvt_pk_fp8_f32 / v_cvt_f32_fp8).
+// For every finite FP32 input these agree with the same roundings written
+// out in integer arithmetic on the FP32 bit pattern (an exhaustive
+// comparison over all finite FP32 values found no difference); each takes
+// one or two instructions per value.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// bfloat16 codes of a (low half) and b (high half).
+__device__ __forceinline__ uint32_t bf16_codes2(float a, float b)
 {
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
+__device__ __forceinline__ uint32_t bf16_code(float x) { return bf16_codes2(x, x) & 0xFFFFu; }
 __device__ __forceinline__ float bf16_value(uint32_t c) { return __uint_as_float(c << 16); }
 
-// OCP FP8 E4M3 code of x, round to nearest even: 4 significant bits,
-// exponent bias 7, subnormal spacing 2^-9 below 2^-6, saturating at 448.
-__device__ __forceinline__ uint32_t e4m3_code(float x)
+// E4M3 codes of a (byte 0) and b (byte 1).
+__device__ __forceinline__ uint32_t e4m3_codes2(float a, float b)
 {
-    const uint32_t u = __float_as_uint(x);
-    const uint32_t sign = (u >> 24) & 0x80u;
-    const uint32_t a = u & 0x7FFFFFFFu;
-    uint32_t c;
-    if (a >= 0x3C800000u) {  // |x| >= 2^-6: round the FP32 significand to 3 fraction bits
-        const uint32_t r = (a + 0x7FFFFu + ((a >> 20) & 1u)) >> 20;  // exponent(8) | fraction(3)
-        c = r - (120u << 3);                                         // rebias 127 -> 7
-        if (r < (120u << 3) || c > 0x7Eu) c = 0x7Eu;                 // saturate (largest finite)
-    } else {                 // multiples of 2^-9; 8 * 2^-9 = 2^-6 is code 0x08
-        c = (uint32_t)rintf(__uint_as_float(a) * 512.f);
-    }
-    return sign | c;
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(a, -448.f, 448.f),
+                                                     __builtin_amdgcn_fmed3f(b, -448.f, 448.f), 0, false);
 }
-__device__ __forceinline__ float e4m3_value(uint32_t c)
+__device__ __forceinline__ uint32_t e4m3_code(float x) { return e4m3_codes2(x, x) & 0xFFu; }
+
+// Values of two operands rounded to a form.
+__device__ __forceinline__ f32x2_t bf16_round2(float a, float b)
 {
-    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    const float v = e ? ldexpf(1.f + 0.125f * (float)m, (int)e - 7) : ldexpf((float)m, -9);
-    return (c & 0x80u) ? -v : v;
+    const f32x2_t v = {a, b};
+    return __builtin_convertvector(__builtin_convertvector(v, bf16x2_t), f32x2_t);
 }
 
-// x rounded to the E4M3 grid, as an FP32 value (the value of e4m3_code(x)):
-// 3 fraction bits at or above 2^-6, multiples of 2^-9 below, at most 448.
-__device__ __forceinline__ float e4m3_round(float x)
+__device__ __forceinline__ f32x2_t e4m3_round2(float a, float b)
 {
-    const uint32_t u = __float_as_uint(x);
-    const uint32_t a = u & 0x7FFFFFFFu;
-    float r;
-    if (a >= 0x3C800000u)
-        r = fminf(__uint_as_float((a + 0x7FFFFu + ((a >> 20) & 1u)) & 0xFFF00000u), 448.f);
-    else
-        r = rintf(__uint_as_float(a) * 512.f) * (1.f / 512.f);
-    return __uint_as_float(__float_as_uint(r) | (u & 0x80000000u));
+    const int q = (int)e4m3_codes2(a, b);
+    return f32x2_t{__builtin_amdgcn_cvt_f32_fp8(q, 0), __builtin_amdgcn_cvt_f32_fp8(q, 1)};
 }
 
 // Value of x as the contraction sees it in the form `prec` (the gather
 // kernels' view of the same operand rounding).
 __device__ __forceinline__ float operand_value(int prec, float x)
 {
-    if (prec == PREC_BF16) return bf16_value(bf16_code(x));
-    if (prec == PREC_FP8) return e4m3_round(x);
+    if (prec == PREC_BF16) return bf16_round2(x, x).x;
+    if (prec == PREC_FP8) return e4m3_round2(x, x).x;
     return x;
+}
+
+// Two values at a time (one conversion instruction for both).
+__device__ __forceinline__ f32x2_t operand_value2(int prec, float a, float b)
+{
+    if (prec == PREC_BF16) return bf16_round2(a, b);
+    if (prec == PREC_FP8) return e4m3_round2(a, b);
+    return f32x2_t{a, b};
 }
 
 typedef __bf16 bf16x8_t __attribute__((__vector_size__(8 * sizeof(__bf16))));

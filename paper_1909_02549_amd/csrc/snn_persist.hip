@@ -89,9 +89,9 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
     float ve[kPersistTasks][8], vi[kPersistTasks][8];
     uint32_t rw[kPersistTasks][4];
     uint32_t hin_cnt[kPersistTasks];
-    // list words read ahead (fewer for FP8, whose rounding in the gathers
-    // takes the registers)
-    constexpr int NHP = PREC == PREC_FP8 ? 1 : 2;
+    // list words read ahead (fewer for the reduced forms, whose rounding in
+    // the gathers takes the registers: two would spill)
+    constexpr int NHP = PREC == PREC_FP32 ? 2 : 1;
     uint4 hin[kPersistTasks][NHP];
 #pragma unroll
     for (int u = 0; u < kPersistTasks; ++u) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
     __syncthreads();
 
     // neuron parameters and output pointers in registers for the step loop
-    const NeuronK nk = PREC == PREC_FP8 ? neuron_consts(p) : neuron_consts_v(p);
+    const NeuronK nk = neuron_consts_v(p);
     const Outs outs = a.o;
     for (int k = 0; k < ch.steps; ++k) {
         const int mod = (ch.mod0 + k) % 3;
@@ -143,9 +143,17 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
             if (!has_task[u]) continue;
             float acc[8];
             const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
-            gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
+            if (PREC == PREC_FP32) {
+                gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
+            } else {
+                // the reduced forms round the normalised weight w * scale
+                const float4 slo = *reinterpret_cast<const float4 *>(S.scalef + tc0[u]);
+                const float4 shi = *reinterpret_cast<const float4 *>(S.scalef + tc0[u] + 4);
+                gather_pre<NHP, true>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc,
+                                      PREC, slo, shi);
+            }
             neuron_task(nk, S, outs, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, cp[u], ve[u], vi[u],
-                        rw[u]);
+                        rw[u], PREC != PREC_FP32);
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
@@ -158,7 +166,6 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
                 ch.ord_in + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC, ch.bits + (size_t)k * p.bits_stride);
             __syncthreads();
             colsums_theta<RK>(p, S, k >= ch.norm_from ? p.norm : 0.0, tid, nt);
-            if (PREC != PREC_FP32) apply_scale(p, S, tid, nt);
         }
         if (k + 1 < ch.steps) {
 #pragma unroll
