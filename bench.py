@@ -28,7 +28,8 @@ Also reported on the same JSON line:
                 sparse vector operations against the 157.3 TFLOP/s vector
                 peak) are kept beside it as context;
   serving       frozen 784 -> 1600 network, Poisson arrivals, T in
-                {100, 250, 500}: p50 / p99 latency and sample-steps/s;
+                {100, 250, 500}: p50 / p99 latency and sample-steps/s at
+                5000 requests/s, and (`sweep`) at 2000, 10000 and 20000;
   conversion    the converted 784-256-128-10 IF network (ANN to SNN
                 conversion section) at B = 1024 and B = 1, T = 10;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
@@ -649,6 +650,10 @@ def main():
     serving = None
     if not args.no_serve:
         serving = serving_run(args.serve_requests, args.serve_rate, max_slots=1024, chunk=25)
+        # the same server across arrival rates (3000 requests each)
+        serving["sweep"] = [{k: r[k] for k in ("rate_req_s", "p50_ms", "p99_ms", "value", "peak_active")}
+                            for r in (serving_run(3000, rate, max_slots=1024, chunk=25)
+                                      for rate in (2000.0, 10000.0, 20000.0))]
 
     conversion = None if args.no_conversion else conversion_run(oracle=not args.no_cpu)
     peaks = None if args.no_peaks else measured_peaks()
@@ -665,7 +670,7 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['n_in']}->{cfg['n_exc']}/{cfg['n_inh']} Diehl&Cook, "
                                f"B={B}, T={T}, STDP {'on' if cfg['learn'] else 'off'}, reduce="
-                               f"{['sum', 'mean', 'max', 'max_signed'][cfg['reduce']]}"
+                               f"{['sum', 'mean', 'max', 'max_signed', 'soft_max'][cfg['reduce']]}"
                                f"{', normalisation per trial' if cfg.get('norm_per_run') else ''}, synthetic stroke images",
                    "global_batch": B, "seq_len": T, "parallelism": "single-gpu", "path": used_path,
                    "precision": args.precision},

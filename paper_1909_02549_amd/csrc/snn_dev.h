@@ -64,6 +64,15 @@ struct Outs {
     uint32_t *raster_inh;  // T x B x exc_words
     float *v_exc;          // T x B x n_exc
     float *v_inh;          // T x B x n_exc
+    const uint32_t *until; // B: spikes of sample b are counted at call step k
+                           // only while k < until[b] (serving; nullptr: always)
+};
+
+// Serving: the per-slot arrays a slot move carries besides the network state.
+struct SlotArrays {
+    uint8_t *img;           // slots x n_in
+    uint64_t *ids;
+    uint32_t *tl, *counts;  // local step; slots x n_exc spike counts
 };
 
 enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2, RED_MAX_SIGNED = 3, RED_SOFT = 4 };

@@ -205,7 +205,7 @@ __device__ __forceinline__ void write_outputs(const Params &p, const Outs &o, in
                                               bool si, float ve, float vi)
 {
     const int words = (p.n_exc + 31) >> 5;
-    if (o.counts && se) o.counts[(size_t)b * p.n_exc + j] += 1u;
+    if (o.counts && se && (!o.until || (uint32_t)k < o.until[b])) o.counts[(size_t)b * p.n_exc + j] += 1u;
     if (o.raster_exc && se)
         atomicOr(&o.raster_exc[((size_t)k * p.B + b) * words + (j >> 5)], 1u << (j & 31));
     if (o.raster_inh && si)
@@ -223,7 +223,7 @@ __device__ __forceinline__ void write_outputs8(const PP &p, const Outs &o, int k
 {
     const int words = (p.n_exc + 31) >> 5;
     const size_t row = (size_t)k * p.B + b;
-    if (o.counts && se_m) {
+    if (o.counts && se_m && (!o.until || (uint32_t)k < o.until[b])) {
         // one owner per entry: a device atomic with its result unused, so the
         // step does not wait for a load of the old count
         uint32_t *cnt = o.counts + (size_t)b * p.n_exc + j0;
@@ -266,6 +266,8 @@ __global__ void k_reset(Params p, float *v_exc, float *v_inh, uint16_t *rf, floa
                         uint32_t *C, const uint8_t *mask);
 __global__ void k_fill_u32(uint32_t *dst, uint32_t value, size_t n);
 __global__ void k_slot_init(const uint8_t *mask, uint32_t *tl, uint32_t *counts, int n_exc, int B);
+__global__ void k_slot_move(Params p, float *v_exc, float *v_inh, float *x_post, uint16_t *rf, float *xpre_last,
+                            uint32_t *C_last, SlotArrays sa, int n_in, const uint32_t *pairs, int n);
 // Staging copy of the kept samples' state while the batch is re-formed
 // (rows k < nk; block-major neuron arrays [g][k][jbp]).
 struct RebatchStage {

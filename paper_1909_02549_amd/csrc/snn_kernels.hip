@@ -440,6 +440,40 @@ __global__ void k_rebatch_load(Params p, float *__restrict__ v_exc, float *__res
     }
 }
 
+// Serving: move slot pairs[2q] to slot pairs[2q + 1], q < n (grid y = q).
+// Every destination is a free slot below every source and no slot is both,
+// so the copies do not overlap.  Carries the network's per-sample state (the
+// neurons' v_exc, v_inh, x_post and flags, the last step's presynaptic
+// traces and inhibitory count) and the server's image, id, local step and
+// counts.  The destination's current-step count slot is zero already (it
+// was an idle slot below the active width).
+__global__ void k_slot_move(Params p, float *__restrict__ v_exc, float *__restrict__ v_inh,
+                            float *__restrict__ x_post, uint16_t *__restrict__ rf, float *__restrict__ xpre_last,
+                            uint32_t *__restrict__ C_last, SlotArrays sa, int n_in, const uint32_t *__restrict__ pairs,
+                            int n)
+{
+    const int q = blockIdx.y;
+    if (q >= n) return;
+    const uint32_t src = pairs[2 * q], dst = pairs[2 * q + 1];
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)p.nblk * p.jbp) {
+        const size_t g = t / p.jbp, jj = t % p.jbp;
+        const size_t s = (g * p.Bs + src) * p.jbp + jj, d = (g * p.Bs + dst) * p.jbp + jj;
+        v_exc[d] = v_exc[s];
+        v_inh[d] = v_inh[s];
+        x_post[d] = x_post[s];
+        rf[d] = rf[s];
+    }
+    if (t < (size_t)p.n_in_pad) xpre_last[(size_t)dst * p.n_in_pad + t] = xpre_last[(size_t)src * p.n_in_pad + t];
+    if (t < (size_t)p.n_exc) sa.counts[(size_t)dst * p.n_exc + t] = sa.counts[(size_t)src * p.n_exc + t];
+    if (t < (size_t)n_in) sa.img[(size_t)dst * n_in + t] = sa.img[(size_t)src * n_in + t];
+    if (t == 0) {
+        sa.ids[dst] = sa.ids[src];
+        sa.tl[dst] = sa.tl[src];
+        C_last[dst] = C_last[src];
+    }
+}
+
 // Serving: every slot's local step advances by the steps just run.
 __global__ void k_add_u32(uint32_t *__restrict__ v, uint32_t add, int n)
 {

@@ -127,9 +127,14 @@ struct snn_net {
     snn_status run_steps(int path, const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t T,
                          const snn::Outs &o, const uint32_t *tl = nullptr);
     // serving: `steps` more steps of the first B slots, encoder keyed by the
-    // per-slot local steps tl, exc spike counts added into counts
+    // per-slot local steps tl, exc spike counts added into counts while the
+    // call's step is below until[b]
     snn_status serve_steps(const uint8_t *images, const uint64_t *ids, const uint32_t *tl, uint32_t B, uint32_t steps,
-                           uint32_t *counts, const uint8_t *new_mask);
+                           uint32_t *counts, const uint8_t *new_mask, const uint32_t *until);
+    uint32_t serve_tune_T = 0;  // serving: the chunk length the path choice is tuned for
+    // serving: move slots (pairs_dev: n (from, to) pairs) with the server's
+    // per-slot arrays
+    snn_status move_slots(const uint32_t *pairs_dev, int n, const snn::SlotArrays &sa, int n_in);
     friend struct snn_server;
     // AUTO: the fastest available execution path for this batch, measured
     // once on scratch copies of the network (snn_autotune.hip); with jb

@@ -999,8 +999,19 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
 
 snn_status snn_net::error(snn_status st, const char *msg) { return fail(st, msg); }
 
+snn_status snn_net::move_slots(const uint32_t *pairs_dev, int n, const SlotArrays &sa, int n_in)
+{
+    if (n <= 0) return SNN_OK;
+    const size_t span = std::max({(size_t)p.nblk * p.jbp, (size_t)p.n_in_pad, (size_t)p.n_exc, (size_t)n_in});
+    SNN_LAUNCH("slot_move", k_slot_move, dim3((unsigned)((span + 255) / 256), (unsigned)n), dim3(256), 0, p, v_exc,
+               v_inh, x_post, rf, x_pre + (size_t)((gstep + 2) % 3) * p.Bs * p.n_in_pad,
+               C + (size_t)((gstep + 2) % 3) * p.Bs, sa, n_in, pairs_dev, n);
+    HIP_TRY(hipGetLastError());
+    return SNN_OK;
+}
+
 snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, const uint32_t *tl_dev, uint32_t B,
-                                uint32_t steps, uint32_t *counts, const uint8_t *new_mask)
+                                uint32_t steps, uint32_t *counts, const uint8_t *new_mask, const uint32_t *until)
 {
     if (B == 0 || B > cap_B || steps == 0) return fail(SNN_EINVAL, "serve_steps: bad batch or steps");
     set_batch(B);
@@ -1013,6 +1024,7 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
     }
     Outs o{};
     o.counts = counts;
+    o.until = until;
     // the active width changes with every admission: tune per power-of-two
     // width (at most log2(capacity) measurements, on the slot buffers, which
     // hold capacity entries)
@@ -1020,7 +1032,9 @@ snn_status snn_net::serve_steps(const uint8_t *images, const uint64_t *ids, cons
     if (path == SNN_PATH_AUTO) {
         uint32_t Bk = 1;
         while (Bk < B) Bk <<= 1;
-        path = choose_path(std::min(Bk, cap_B), steps, images, ids, nullptr);
+        Bk = std::min(Bk, cap_B);
+        set_batch(Bk);  // (the candidate paths depend on the width)
+        path = choose_path(Bk, serve_tune_T ? serve_tune_T : steps, images, ids, nullptr);
         set_batch(B);
     }
     snn_status st = run_steps(path, images, ids, nullptr, steps, o, tl_dev);

@@ -47,9 +47,14 @@ def wait_all(srv, rids, timeout=60.0):
     return out
 
 
-def test_alone_equals_mix_and_oracle(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("path", ["auto", "plain", "fused", "persistent", "mfma"])
+def test_alone_equals_mix_and_oracle(torch_cuda, oracle_mod, path):
+    """Ten requests of mixed lengths through six slots: chunks run in full
+    with per-slot count limits, finished slots' places are taken by moving
+    the highest active slots down, new requests join above them.  Every
+    request's counts equal its run alone, bit for bit, on every path."""
     from paper_1909_02549_amd.snn import Server
-    cfg, W, net = frozen_net()
+    cfg, W, net = frozen_net(path=path)
     imgs = inputs.stroke_images(10, 33, 0.19)
     Ts = [20, 50, 80, 20, 50, 80, 35, 64, 17, 90]
     ids = list(range(500, 510))
