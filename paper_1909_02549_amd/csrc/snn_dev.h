@@ -79,9 +79,11 @@ enum Reduce { RED_SUM = 0, RED_MEAN = 1, RED_MAX = 2, RED_MAX_SIGNED = 3, RED_SO
 
 // Reduction kind a plasticity kernel is compiled for: sum, mean and max
 // (chosen at run time from Params::reduce), the soft maximum (the traces
-// enter as expm1(x / tau), the reduced sums leave through tau log1p(S / B)),
-// or the signed maximum of the per-sample changes.
-enum RedKind { RK_STD = 0, RK_SOFT = 1, RK_SIGNED = 2 };
+// enter as exp(x / tau) - 1, the reduced sums leave through tau log1p(S / B)),
+// or the signed maximum of the per-sample changes.  RK_SERVE: a frozen
+// network with per-slot count limits (Outs::until), the serving loop's
+// launches; no plasticity is compiled in, and only this kind reads the limits.
+enum RedKind { RK_STD = 0, RK_SOFT = 1, RK_SIGNED = 2, RK_SERVE = 3 };
 
 __host__ __device__ constexpr int red_kind(int reduce)
 {

@@ -118,12 +118,14 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
     // x_pre(t) of this workgroup's own samples in registers (xpre_next_own)
     constexpr int XC = 2;
     float xc[XC];
-    if (p.learn) xpre_own_load<XC>(p, ch.xpre + (size_t)ch.mod0 * p.Bs * p.n_in_pad, xc, g, gridDim.x, tid, nt);
+    const bool learn = RK != RK_SERVE && p.learn;
+    if (learn) xpre_own_load<XC>(p, ch.xpre + (size_t)ch.mod0 * p.Bs * p.n_in_pad, xc, g, gridDim.x, tid, nt);
     __syncthreads();
 
     // neuron parameters and output pointers in registers for the step loop
     const NeuronK nk = neuron_consts_v(p);
-    const Outs outs = a.o;
+    Outs outs = a.o;
+    if (RK != RK_SERVE) outs.until = nullptr;  // (read by the serving kind only)
     for (int k = 0; k < ch.steps; ++k) {
         const int mod = (ch.mod0 + k) % 3;
         const float *xpre = ch.xpre + (size_t)mod * p.Bs * p.n_in_pad;
@@ -157,10 +159,10 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
         }
         __syncthreads();
         step_publish<true>(p, S, ch.C + (size_t)mod * p.Bs, ch.C + (size_t)((mod + 1) % 3) * p.Bs, g, tid, nt);
-        if (p.learn && (k + 1 < ch.steps || ch.has_next))
+        if (learn && (k + 1 < ch.steps || ch.has_next))
             xpre_next_own<XC>(p, ch.bits + (size_t)(k + 1) * p.bits_stride, xpre, xpre_nx, xc, g, gridDim.x, tid, nt);
         grid_arrive(sy);
-        if (p.learn) {
+        if (learn) {
             plasticity_all<true, 16, true, 2, false, true, RK>(
                 p, S, ch.lt + (size_t)k * p.n_in_pad * p.lt_stride, ch.ct + (size_t)k * p.n_in_pad,
                 ch.ord_in + (size_t)k * p.n_in_pad, xpre, tid, nt, PREC, PREC, ch.bits + (size_t)k * p.bits_stride);
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
         if (has_task[u])
             store_task_state(p, S, a, (size_t)g * p.Bs * JBP + (size_t)tb[u] * JBP + tc0[u], tb[u], tc0[u], ve[u],
                              vi[u], rw[u]);
-    if (p.learn) store_block(p, S, Wg, a.theta, g, tid, nt);
+    if (learn) store_block(p, S, Wg, a.theta, g, tid, nt);
 }
 
 #define SNN_PERSIST_INST(PR, RK) template __global__ void k_persist<PR, RK>(const PersistArgs);
@@ -196,6 +198,9 @@ SNN_PERSIST_INST(PREC_FP8, RK_SOFT)
 SNN_PERSIST_INST(PREC_FP32, RK_SIGNED)
 SNN_PERSIST_INST(PREC_BF16, RK_SIGNED)
 SNN_PERSIST_INST(PREC_FP8, RK_SIGNED)
+SNN_PERSIST_INST(PREC_FP32, RK_SERVE)
+SNN_PERSIST_INST(PREC_BF16, RK_SERVE)
+SNN_PERSIST_INST(PREC_FP8, RK_SERVE)
 #undef SNN_PERSIST_INST
 
 }  // namespace snn

@@ -112,12 +112,12 @@ struct snn_net {
     size_t mfma_c_attr_bytes[3] = {64 * 1024, 64 * 1024, 64 * 1024};  // current kernel, per precision
     snn_status xpre_first(const uint32_t *bits_t);
     bool fused_ok() const;
-    size_t fused_attr_bytes[3][3] = {};  // per operand form and reduction kind
+    size_t fused_attr_bytes[3][4] = {};  // per operand form and reduction kind
     snn_status fused_step(int kk, int k, bool has_next, const snn::Outs &o);
 
     // persistent path: grid barrier counter / error flag
     uint32_t *bar = nullptr, *err = nullptr;
-    size_t persist_attr_bytes[3][3] = {};
+    size_t persist_attr_bytes[3][4] = {};
     int coop_ok = -1;
     bool persist_ok();
     snn_status persist_chunk(int steps, bool has_next, int k0, const snn::Outs &o);

@@ -882,19 +882,24 @@ snn_status snn_net::xpre_first(const uint32_t *bits_t)
 template <int PREC, int RK, bool Persist>
 static const void *kernel_of()
 {
-    return Persist ? (const void *)k_persist<PREC, RK> : (const void *)k_fused_step<PREC, RK>;
+    if constexpr (Persist)
+        return (const void *)k_persist<PREC, RK>;
+    else
+        return (const void *)k_fused_step<PREC, RK>;
 }
 
 template <bool Persist>
 static const void *step_kernel(int prec, int rk)
 {
-    static const void *const table[3][3] = {
+    // (the fused kernel reads the serving count limits at run time: its
+    // serving launches use the RK_STD instantiation)
+    static const void *const table[3][4] = {
         {kernel_of<PREC_FP32, RK_STD, Persist>(), kernel_of<PREC_FP32, RK_SOFT, Persist>(),
-         kernel_of<PREC_FP32, RK_SIGNED, Persist>()},
+         kernel_of<PREC_FP32, RK_SIGNED, Persist>(), kernel_of<PREC_FP32, Persist ? RK_SERVE : RK_STD, Persist>()},
         {kernel_of<PREC_BF16, RK_STD, Persist>(), kernel_of<PREC_BF16, RK_SOFT, Persist>(),
-         kernel_of<PREC_BF16, RK_SIGNED, Persist>()},
+         kernel_of<PREC_BF16, RK_SIGNED, Persist>(), kernel_of<PREC_BF16, Persist ? RK_SERVE : RK_STD, Persist>()},
         {kernel_of<PREC_FP8, RK_STD, Persist>(), kernel_of<PREC_FP8, RK_SOFT, Persist>(),
-         kernel_of<PREC_FP8, RK_SIGNED, Persist>()}};
+         kernel_of<PREC_FP8, RK_SIGNED, Persist>(), kernel_of<PREC_FP8, Persist ? RK_SERVE : RK_STD, Persist>()}};
     return table[prec][rk];
 }
 
@@ -973,7 +978,8 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     h.sy = PersistSync{bar, err};
     SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
     const size_t lds = persist_lds_bytes(p);
-    const int rk = red_kind(p.reduce);
+    // serving launches (count limits, frozen network) have a kind of their own
+    const int rk = o.until ? RK_SERVE : red_kind(p.reduce);
     const void *kfn = step_kernel<true>(p.prec, rk);
     if (lds > persist_attr_bytes[p.prec][rk]) {
         HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
