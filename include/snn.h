@@ -22,7 +22,9 @@
  *  - Handles are not thread-safe, except that snn_serve_submit and
  *    snn_serve_poll may be called from any thread.
  *  - No call allocates device memory except snn_create, snn_run when the batch
- *    size grows beyond what was allocated, snn_serve_create and
+ *    size grows beyond what was allocated or when path AUTO measures its
+ *    candidates (scratch copies of the network, once per shape), snn_rebatch
+ *    (a staging copy of the kept samples), snn_serve_create and
  *    snn_ifnet_create.
  */
 #ifndef SNN_H
@@ -290,12 +292,17 @@ size_t snn_state_bytes(const snn_config *cfg, uint32_t batch);
 
 /* Continuous-batching inference server over a frozen network (learn must be
  * 0).  Single-sample requests (Dynamic minibatch size section: queries one at
- * a time) are admitted into free slots of a device-resident batch while
- * slots and the HBM budget allow, advanced chunk_steps steps per launch, and
- * retired when their own T is reached.  A request's result does not depend on
- * which other requests share the batch.
+ * a time) join a device-resident batch while slots and the HBM budget allow.
+ * The batch advances in chunks of chunk_steps steps; a slot counts spikes
+ * only up to its own request's T, so chunks always run in full.  Between
+ * chunks finished requests leave, the remaining slots are compacted to the
+ * lowest indices (state and all) and queued requests join above them; the
+ * worker keeps one chunk queued ahead of the one running.  A request's
+ * result does not depend on which other requests share the batch.  With
+ * path AUTO the execution path is tuned here for every power-of-two width.
  *   max_slots   largest device batch; hbm_budget 0 = no limit
- * snn_serve_create takes the network's weights at call time. */
+ * snn_serve_create takes the network's weights, path and operand form at
+ * call time. */
 snn_status snn_serve_create(snn_net *frozen, uint32_t max_slots, uint64_t hbm_budget,
                             uint32_t chunk_steps, snn_server **out);
 
