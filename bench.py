@@ -553,7 +553,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-rate", type=float, default=5000.0)
-    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-conversion", action="store_true", help="skip the converted IF network run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and GEMM peak measurements")
     ap.add_argument("--conversion-only", action="store_true",
@@ -650,9 +650,9 @@ def main():
     serving = None
     if not args.no_serve:
         serving = serving_run(args.serve_requests, args.serve_rate, max_slots=1024, chunk=25)
-        # the same server across arrival rates (3000 requests each)
-        serving["sweep"] = [{k: r[k] for k in ("rate_req_s", "p50_ms", "p99_ms", "value", "peak_active")}
-                            for r in (serving_run(3000, rate, max_slots=1024, chunk=25)
+        # the other arrival rates, the same number of requests each
+        serving["sweep"] = [{k: r[k] for k in ("rate_req_s", "requests", "p50_ms", "p99_ms", "value", "peak_active")}
+                            for r in (serving_run(args.serve_requests, rate, max_slots=1024, chunk=25)
                                       for rate in (2000.0, 10000.0, 20000.0))]
 
     conversion = None if args.no_conversion else conversion_run(oracle=not args.no_cpu)
