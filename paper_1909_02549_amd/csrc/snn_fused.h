@@ -1313,28 +1313,6 @@ __device__ __forceinline__ void load_block(const Params &p, const StepLds &S, co
     }
 }
 
-// The block's FP32 weights into LDS again (after a contraction on rounded
-// weights), the rows of load_block without the thresholds.
-__device__ __forceinline__ void reload_weights(const Params &p, const StepLds &S, const float *Wg, int tid, int nt)
-{
-    const int JB = p.jb, LS = p.ls;
-    const int jj = tid & 31, rg = tid >> 5, nrg = nt >> 5;
-    if (jj < JB) {
-        int i = rg;
-        for (; i + 3 * nrg < p.n_in_pad; i += 4 * nrg) {
-            const float v0 = Wg[(size_t)i * JB + jj];
-            const float v1 = Wg[(size_t)(i + nrg) * JB + jj];
-            const float v2 = Wg[(size_t)(i + 2 * nrg) * JB + jj];
-            const float v3 = Wg[(size_t)(i + 3 * nrg) * JB + jj];
-            S.W[i * LS + jj] = v0;
-            S.W[(i + nrg) * LS + jj] = v1;
-            S.W[(i + 2 * nrg) * LS + jj] = v2;
-            S.W[(i + 3 * nrg) * LS + jj] = v3;
-        }
-        for (; i < p.n_in_pad; i += nrg) S.W[i * LS + jj] = Wg[(size_t)i * JB + jj];
-    }
-}
-
 // Epilogue of a learning launch: the block, normalised, and the thresholds.
 __device__ __forceinline__ void store_block(const Params &p, const StepLds &S, float *Wg, double *theta, int g,
                                             int tid, int nt)

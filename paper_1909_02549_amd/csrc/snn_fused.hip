@@ -24,10 +24,12 @@ namespace snn {
 
 size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads, true).total; }
 
-// PREC: the operand form; RK: the reduction kind (RedKind) of the plasticity.  For BF16 / FP8 the block's weights are rounded
-// in LDS for the contraction and reloaded in FP32 for the plasticity, and
-// the post traces in LDS are rounded once after the neurons' state went back
-// to HBM in FP32; the presynaptic traces are rounded as they are read.
+// PREC: the operand form; RK: the reduction kind (RedKind) of the
+// plasticity.  For BF16 / FP8 the contraction rounds each weight as it is
+// gathered (the block in LDS stays FP32 for the plasticity; it was
+// normalised when it was stored, so no scale is pending at this point), the
+// post traces in LDS are rounded once after the neurons' state went back to
+// HBM in FP32, and the presynaptic traces are rounded as they are read.
 template <int PREC, int RK>
 __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
 {
@@ -42,8 +44,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
 
     load_block(p, S, Wg, a.theta, g, tid, nt);
     __syncthreads();
-    if (PREC != PREC_FP32)
-        for (int q = tid; q < p.n_in_pad * p.ls; q += nt) S.W[q] = operand_value(PREC, S.W[q]);
     step_begin<false>(p, S, s.Cprev, tid, nt);
     __syncthreads();
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
         uint4 h[kListHead];
         load_heads<kListHead>(row, h);
         load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
-        gather_pre<kListHead>(row, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, 0);
+        gather_pre<kListHead>(row, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, PREC);
         neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, S.cprev[b], ve, vi, rw);
         store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         if (PREC != PREC_FP32 && p.learn) {
@@ -74,10 +74,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     __syncthreads();
     step_publish<false>(p, S, s.Ccur, s.Cnext, g, tid, nt);
     if (!p.learn) return;
-    if (PREC != PREC_FP32) {
-        __syncthreads();
-        reload_weights(p, S, Wg, tid, nt);
-    }
     __syncthreads();
 
     plasticity_all<false, 16, true, kListHead, PREC == PREC_FP32, false, RK>(p, S, s.lt, s.ct, s.ord_in, s.xpre,
