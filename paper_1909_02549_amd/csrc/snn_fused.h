@@ -152,12 +152,24 @@ struct FusedLds {
         size_t o = 0;
         w = o;
         o += align16((size_t)(p.n_in_pad + 1) * p.ls * 4);
-        xpost = o;
-        o += p.learn ? align16((size_t)(p.B + 1) * p.ls * 4) : 0;
+        scale = o;
+        o += 32 * 8;
+        scalef = o;
+        o += 32 * 4;
+        theta = o;
+        o += 32 * 4;
+        theta64 = o;
+        o += 32 * 8;
+        // per-sample regions last: a network without inhibitory layer or
+        // without learning leaves the tail it does not use unallocated
+        const size_t fixed_end = o;
         cprev = o;
         o += align16((size_t)p.B * 4);
         cinh = o;
         o += align16((size_t)p.B * 4);
+        const size_t inh_end = o;
+        xpost = o;
+        o += p.learn ? align16((size_t)(p.B + 1) * p.ls * 4) : 0;
         spk = o;
         o += align16((size_t)p.jb * p.bwords * 4);
         colmask = o;
@@ -171,15 +183,9 @@ struct FusedLds {
             part = o;
             o += align16(part_bytes);
         }
-        scale = o;
-        o += 32 * 8;
-        scalef = o;
-        o += 32 * 4;
-        theta = o;
-        o += 32 * 4;
-        theta64 = o;
-        o += 32 * 8;
-        total = o;
+        // (without inhibitory layer the neuron tasks read cprev[0] and ignore
+        // it, so one entry stays allocated)
+        total = p.learn ? o : p.has_inh ? inh_end : fixed_end + 16;
     }
 };
 
@@ -363,12 +369,13 @@ __device__ __forceinline__ void load_heads(const uint16_t *list, uint4 *h)
 template <bool Coherent>
 __device__ __forceinline__ void step_begin(const Params &p, const StepLds &S, const uint32_t *Cprev, int tid, int nt)
 {
-    for (int q = tid; q < p.B; q += nt) {
-        if (Cprev) S.cprev[q] = p.has_inh ? ld_u<Coherent>(Cprev + q) : 0u;
+    const int nb_inh = p.has_inh ? p.B : 0, nb_learn = p.learn ? p.B : 0;
+    for (int q = tid; q < nb_inh; q += nt) {
+        if (Cprev) S.cprev[q] = ld_u<Coherent>(Cprev + q);
         S.cinh[q] = 0u;
-        S.colmask[q] = 0u;
     }
-    for (int q = tid; q < p.jb * p.bwords; q += nt) S.spk[q] = 0u;
+    for (int q = tid; q < nb_learn; q += nt) S.colmask[q] = 0u;
+    for (int q = tid; q < (p.learn ? p.jb * p.bwords : 0); q += nt) S.spk[q] = 0u;
     if (tid < 32) S.th[tid] = theta_offset(p, S.th64[tid]);
 }
 
@@ -434,7 +441,7 @@ template <bool Coherent>
 __device__ __forceinline__ void step_publish(const Params &p, const StepLds &S, uint32_t *Ccur, uint32_t *Cnext, int g,
                                              int tid, int nt)
 {
-    for (int q = tid; q < p.B; q += nt) {
+    for (int q = tid; q < (p.has_inh ? p.B : 0); q += nt) {
         const uint32_t c = S.cinh[q];
         if (c) atomicAdd(&Ccur[q], c);
         if (g == 0 && Cnext) st_x<Coherent>(Cnext + q, 0u);

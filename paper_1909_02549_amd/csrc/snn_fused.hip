@@ -33,6 +33,10 @@ size_t fused_lds_bytes(const Params &p) { return FusedLds(p, kFusedThreads, true
 template <int PREC, int RK>
 __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArgs a, StepPtrs s)
 {
+    // the frozen kind (RK_SERVE) runs networks that do not learn: with
+    // learn known to be 0 here, every plasticity branch compiles out and the
+    // kernel needs fewer registers
+    if constexpr (RK == RK_SERVE) p.learn = 0;
     extern __shared__ __align__(16) unsigned char smem[];
     const FusedLds L(p, blockDim.x, true);
     const StepLds S(smem, L);
@@ -47,10 +51,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
     step_begin<false>(p, S, s.Cprev, tid, nt);
     __syncthreads();
 
-    // B: one (sample, 8 columns) task at a time, state through registers
+    // B: one (sample, 8 columns) task at a time, state through registers.
+    // Without learning the samples are independent, and the grid's y
+    // dimension splits them between workgroups of the same column block
+    // (with learning gridDim.y is 1: the plasticity needs every sample)
     const size_t sbase = (size_t)g * p.Bs * JBP;
     const int nv_blk = min(JB, p.n_exc - g * JB);
-    for (int q = tid; q < p.B * ncg; q += nt) {
+    for (int q = tid + (int)blockIdx.y * nt; q < p.B * ncg; q += nt * (int)gridDim.y) {
         const int qb = q / ncg;
         const int b = s.ord_s[qb];
         const int c0 = 8 * (q - qb * ncg);
@@ -63,7 +70,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_step(Params p, FusedArg
         load_heads<kListHead>(row, h);
         load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         gather_pre<kListHead>(row, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad, RED_SUM, acc, PREC);
-        neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc, S.cprev[b], ve, vi, rw);
+        neuron_task(p, S, a.o, s.k, b, c0, g * JB + c0, max(0, min(8, nv_blk - c0)), acc,
+                    S.cprev[p.has_inh ? b : 0], ve, vi, rw);
         store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
         if (PREC != PREC_FP32 && p.learn) {
             float *xr = S.xpost + b * p.ls + c0;
@@ -94,6 +102,9 @@ SNN_FUSED_INST(PREC_FP8, RK_SOFT)
 SNN_FUSED_INST(PREC_FP32, RK_SIGNED)
 SNN_FUSED_INST(PREC_BF16, RK_SIGNED)
 SNN_FUSED_INST(PREC_FP8, RK_SIGNED)
+SNN_FUSED_INST(PREC_FP32, RK_SERVE)
+SNN_FUSED_INST(PREC_BF16, RK_SERVE)
+SNN_FUSED_INST(PREC_FP8, RK_SERVE)
 #undef SNN_FUSED_INST
 
 // Sparse index lists of one chunk of encoded steps:

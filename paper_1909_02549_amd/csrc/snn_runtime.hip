@@ -891,15 +891,14 @@ static const void *kernel_of()
 template <bool Persist>
 static const void *step_kernel(int prec, int rk)
 {
-    // (the fused kernel reads the serving count limits at run time: its
-    // serving launches use the RK_STD instantiation)
+    // (RK_SERVE: the frozen kind, for every run without learning)
     static const void *const table[3][4] = {
         {kernel_of<PREC_FP32, RK_STD, Persist>(), kernel_of<PREC_FP32, RK_SOFT, Persist>(),
-         kernel_of<PREC_FP32, RK_SIGNED, Persist>(), kernel_of<PREC_FP32, Persist ? RK_SERVE : RK_STD, Persist>()},
+         kernel_of<PREC_FP32, RK_SIGNED, Persist>(), kernel_of<PREC_FP32, RK_SERVE, Persist>()},
         {kernel_of<PREC_BF16, RK_STD, Persist>(), kernel_of<PREC_BF16, RK_SOFT, Persist>(),
-         kernel_of<PREC_BF16, RK_SIGNED, Persist>(), kernel_of<PREC_BF16, Persist ? RK_SERVE : RK_STD, Persist>()},
+         kernel_of<PREC_BF16, RK_SIGNED, Persist>(), kernel_of<PREC_BF16, RK_SERVE, Persist>()},
         {kernel_of<PREC_FP8, RK_STD, Persist>(), kernel_of<PREC_FP8, RK_SOFT, Persist>(),
-         kernel_of<PREC_FP8, RK_SIGNED, Persist>(), kernel_of<PREC_FP8, Persist ? RK_SERVE : RK_STD, Persist>()}};
+         kernel_of<PREC_FP8, RK_SIGNED, Persist>(), kernel_of<PREC_FP8, RK_SERVE, Persist>()}};
     return table[prec][rk];
 }
 
@@ -930,15 +929,24 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
     if (cfg.norm_per_run && (uint32_t)k + 1 != run_T) pp.norm = 0.0;
     FusedArgs a{W, theta, v_exc, v_inh, x_post, rf, o};
     const size_t lds = fused_lds_bytes(p);
-    const int rk = red_kind(p.reduce);
+    const int rk = p.learn ? red_kind(p.reduce) : RK_SERVE;
     const void *fn = step_kernel<false>(p.prec, rk);
     if (lds > fused_attr_bytes[p.prec][rk]) {
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         fused_attr_bytes[p.prec][rk] = lds;
     }
     void *kargs[] = {(void *)&pp, (void *)&a, (void *)&s};
+    // without learning: enough workgroups per column block to give every
+    // thread about one task and the grid a few workgroups per CU
+    unsigned split = 1;
+    if (!p.learn) {
+        const unsigned tasks = (unsigned)p.B * (unsigned)(p.jbp >> 3);
+        const unsigned by_tasks = (tasks + kFusedThreads - 1) / kFusedThreads;
+        const unsigned by_cus = std::max(1u, 4u * (unsigned)cus / (unsigned)p.nblk);
+        split = std::max(1u, std::min(by_tasks, by_cus));
+    }
     if (prof) prof_open(kstat_id("fused_step"));
-    HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)p.nblk), dim3(kFusedThreads), kargs, (unsigned)lds, stream));
+    HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)p.nblk, split), dim3(kFusedThreads), kargs, (unsigned)lds, stream));
     if (prof) span.launches += 1;
     ++gstep;
     return SNN_OK;
@@ -978,8 +986,9 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     h.sy = PersistSync{bar, err};
     SNN_LAUNCH("fill", k_fill_u32, dim3(1), dim3(64), 0, bar, 0u, (size_t)1);
     const size_t lds = persist_lds_bytes(p);
-    // serving launches (count limits, frozen network) have a kind of their own
-    const int rk = o.until ? RK_SERVE : red_kind(p.reduce);
+    // runs without learning (serving with its count limits among them) have
+    // a kind of their own
+    const int rk = o.until || !p.learn ? RK_SERVE : red_kind(p.reduce);
     const void *kfn = step_kernel<true>(p.prec, rk);
     if (lds > persist_attr_bytes[p.prec][rk]) {
         HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -2,6 +2,7 @@
 symbol include/snn.h declares, and rejects invalid configurations before
 touching the device.  No compute call is made here."""
 import ctypes as C
+import json
 import os
 import re
 
@@ -150,3 +151,28 @@ def test_handles_raise_without_gpu_or_library(monkeypatch):
     monkeypatch.setattr(snn, "LIB_PATH", os.path.join(ROOT, "no_such_libsnn.so"))
     with pytest.raises(RuntimeError, match="not built"):
         snn.load_library()
+
+
+def test_resource_report_parser():
+    from paper_1909_02549_amd import build
+    text = ("a.hip:3:1: remark: Function Name: k_a [-Rpass-analysis=kernel-resource-usage]\n"
+            "    3 | {\n      | ^\n"
+            "a.hip:3:1: remark:     VGPRs: 121 [-Rpass-analysis=kernel-resource-usage]\n"
+            "a.hip:3:1: remark:     ScratchSize [bytes/lane]: 448 [-Rpass-analysis=kernel-resource-usage]\n"
+            "a.hip:9:1: remark: Function Name: k_b [-Rpass-analysis=kernel-resource-usage]\n"
+            "a.hip:9:1: remark:     Occupancy [waves/SIMD]: 5 [-Rpass-analysis=kernel-resource-usage]\n")
+    assert build.parse_resources(text) == {"k_a": {"vgpr": 121, "scratch": 448}, "k_b": {"occupancy": 5}}
+
+
+def test_no_kernel_spills_to_scratch():
+    """Every kernel keeps its state in registers and LDS: a kernel that
+    starts spilling to scratch memory runs several times slower (the FP32
+    fused step at 448 bytes per lane took three times as long per step)."""
+    from paper_1909_02549_amd import build, snn
+    if not os.path.exists(build.RESOURCES) or not os.path.exists(snn.LIB_PATH):
+        pytest.skip("library not built")
+    res = json.load(open(build.RESOURCES))
+    assert os.path.getmtime(build.RESOURCES) >= os.path.getmtime(snn.LIB_PATH) - 5
+    assert any("k_fused_step" in k for k in res) and any("k_persist" in k for k in res)
+    spilling = {k: r["scratch"] for k, r in res.items() if r.get("scratch", 0)}
+    assert not spilling, spilling
