@@ -97,6 +97,10 @@ typedef enum { SNN_FP32 = 0, SNN_BF16 = 1, SNN_FP8_E4M3 = 2 } snn_precision;
  *   FUSED      one column-partitioned launch per step carrying contraction,
  *              neuron update and plasticity, encoder hoisted over all T;
  *   PERSISTENT one cooperative launch for all T steps, state kept on chip;
+ *              a network without learning and without inhibitory layer
+ *              (no neuron's input depends on another neuron) runs each
+ *              encoder chunk in one launch of independent tasks instead:
+ *              no grid barrier, any batch size;
  *   AUTO       chosen by the library's autotuner for (batch, T, precision);
  *   MFMA       per-step launches with the synaptic current and the STDP
  *              outer products over the batch on the matrix cores (sum and

@@ -33,6 +33,7 @@ constexpr int kFusedThreads = 1024;   // fused per-step kernel: 16 waves
 constexpr int kPersistThreads = 512;  // persistent kernel: 8 waves, with
 constexpr int kPersistTasks = 2;      //   two (sample, 8 columns) tasks each
 constexpr int kListHead = 4;          // 16-byte words of a spike list read ahead
+constexpr int kIndepThreads = 256;    // chunk kernel of independent tasks: 4 waves
 constexpr int kMfmaPotentiation = 0;  // spiking samples above which potentiation runs on the matrix cores
 static_assert(kFusedThreads % 128 == 0 && kPersistThreads % 128 == 0, "split-row plasticity needs nt % 128 == 0");
 
@@ -104,6 +105,10 @@ template <int PREC, int RK>
 __global__ void k_fused_step(Params p, FusedArgs a, StepPtrs s);
 template <int PREC, int RK>
 __global__ void k_persist(const PersistArgs args);
+// no learning and no inhibitory layer: every task on its own, no barrier
+size_t indep_lds_bytes(const Params &p);
+template <int PREC>
+__global__ void k_indep(const PersistArgs args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
 constexpr int kOrderThreads = 1024;

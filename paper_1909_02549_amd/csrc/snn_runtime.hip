@@ -954,6 +954,7 @@ snn_status snn_net::fused_step(int kk, int k, bool has_next, const Outs &o)
 
 bool snn_net::persist_ok()
 {
+    if (indep()) return p.jb <= 32 && p.n_in_pad < 65535 && p.B < 65535 && indep_lds_bytes(p) <= kMaxLds;
     if (coop_ok < 0) {
         int v = 0;
         coop_ok = (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess && v) ? 1 : 0;
@@ -968,6 +969,31 @@ snn_status snn_net::persist_chunk(int steps, bool has_next, int k0, const Outs &
     h.p = p;
     h.a = FusedArgs{W, theta, v_exc, v_inh, x_post, rf, o};
     ChunkPtrs &c = h.ch;
+    if (indep()) {
+        // independent tasks: one thread per task, any number of workgroups
+        c = ChunkPtrs{};
+        c.lin = lin;
+        c.cin = cin;
+        c.steps = steps;
+        c.k0 = k0;
+        h.sy = PersistSync{nullptr, nullptr};
+        const size_t lds = indep_lds_bytes(p);
+        const void *fn = p.prec == PREC_FP32   ? (const void *)k_indep<PREC_FP32>
+                         : p.prec == PREC_BF16 ? (const void *)k_indep<PREC_BF16>
+                                               : (const void *)k_indep<PREC_FP8>;
+        if (lds > indep_attr_bytes[p.prec]) {
+            HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            indep_attr_bytes[p.prec] = lds;
+        }
+        const unsigned tasks = (unsigned)p.B * (unsigned)(p.jbp >> 3);
+        const dim3 grid((unsigned)p.nblk, (tasks + kIndepThreads - 1) / kIndepThreads);
+        void *kargs[] = {(void *)&h};
+        if (prof) prof_open(kstat_id("indep"));
+        HIP_TRY(hipLaunchKernel(fn, grid, dim3(kIndepThreads), kargs, (unsigned)lds, stream));
+        if (prof) span.launches += 1;
+        gstep += (uint64_t)steps;
+        return SNN_OK;
+    }
     c.bits = bits;
     c.lin = lin;
     c.cin = cin;
@@ -1080,8 +1106,10 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
             const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
             SNN_LAUNCH("lists", k_lists, dim3((unsigned)((nq + 255) / 256), (unsigned)enc_steps), dim3(256), 0, p,
                        (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, p.learn);
-            SNN_LAUNCH("order", k_order, dim3((unsigned)enc_steps), dim3(kOrderThreads), 0, p, (const uint32_t *)cin,
-                       (const uint32_t *)ct, ord_s, ord_in, p.learn);
+            // (the independent-task chunk kernel takes no work order)
+            if (!(path == SNN_PATH_PERSISTENT && indep()))
+                SNN_LAUNCH("order", k_order, dim3((unsigned)enc_steps), dim3(kOrderThreads), 0, p,
+                           (const uint32_t *)cin, (const uint32_t *)ct, ord_s, ord_in, p.learn);
             HIP_TRY(hipGetLastError());
             if (k0 == 0 && p.learn) {
                 st = xpre_first(bits);
