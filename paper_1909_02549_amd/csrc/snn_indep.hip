@@ -30,6 +30,64 @@ size_t indep_lds_bytes(const Params &p)
     return FusedLds(q, kIndepThreads).total;
 }
 
+// The weight block in LDS as JBP / 4 planes of 4 columns: plane u holds
+// rows 0 .. n_in_pad (the last all zeros) of columns 4u .. 4u + 3, 16 bytes a
+// row.  A lane's two 16-byte reads of a row then fall on any of the 8 groups
+// of 4 banks, where the row-major 8-column layout left each read a choice of
+// 4, so the random rows of a wave's lanes collide less often.
+__device__ __forceinline__ void load_planes(const Params &p, float4 *planes, const float *Wg, int tid, int nt)
+{
+    const int JB = p.jb, rows = p.n_in_pad + 1, n = (p.jbp >> 2) * rows;
+    for (int e = tid; e < n; e += nt) {
+        const int u = e / rows, i = e - u * rows;
+        float v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = 4 * u + c;
+            v[c] = (i < p.n_in_pad && col < JB) ? Wg[(size_t)i * JB + col] : 0.f;
+        }
+        planes[e] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// acc[0..8) = sum over the first cnt entries of the list (in list order) of
+// the operand values of row i, columns c0 .. c0 + 7: the additions of
+// gather_pre, from the plane layout (pa: plane of columns c0 .. c0 + 3, pb:
+// the next).  The first 8 * NH entries come in h.
+template <int NH>
+__device__ __forceinline__ void gather_planes(const uint16_t *__restrict__ list, int cnt, const uint4 *h,
+                                              const float4 *pa, const float4 *pb, int zero_row, float *acc, int prec)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    auto four = [&](uint2 q, int k0) {
+        const int i0 = (int)(q.x & 0xFFFFu);
+        const int i1 = k0 + 1 < cnt ? (int)(q.x >> 16) : zero_row;
+        const int i2 = k0 + 2 < cnt ? (int)(q.y & 0xFFFFu) : zero_row;
+        const int i3 = k0 + 3 < cnt ? (int)(q.y >> 16) : zero_row;
+        const float4 a0 = round4(prec, pa[i0]), b0 = round4(prec, pb[i0]);
+        const float4 a1 = round4(prec, pa[i1]), b1 = round4(prec, pb[i1]);
+        const float4 a2 = round4(prec, pa[i2]), b2 = round4(prec, pb[i2]);
+        const float4 a3 = round4(prec, pa[i3]), b3 = round4(prec, pb[i3]);
+        add4(acc, a0), add4(acc + 4, b0);
+        add4(acc, a1), add4(acc + 4, b1);
+        add4(acc, a2), add4(acc + 4, b2);
+        add4(acc, a3), add4(acc + 4, b3);
+    };
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+        if (8 * q < cnt) four(make_uint2(h[q].x, h[q].y), 8 * q);
+        if (8 * q + 4 < cnt) four(make_uint2(h[q].z, h[q].w), 8 * q + 4);
+    }
+    const uint2 *l4 = reinterpret_cast<const uint2 *>(list);
+    for (int k0 = 8 * NH; k0 < cnt; k0 += 8) {
+        const uint2 e0 = l4[k0 >> 2];
+        const uint2 e1 = k0 + 4 < cnt ? l4[(k0 >> 2) + 1] : make_uint2(0u, 0u);
+        four(e0, k0);
+        if (k0 + 4 < cnt) four(e1, k0 + 4);
+    }
+}
+
 // grid (nblk, ceil(B * JBP / 8 / kIndepThreads)); task q = tid + nt * y is
 // (sample q / ncg, columns 8 * (q % ncg) ...) of column block g.
 template <int PREC>
@@ -50,9 +108,15 @@ __global__ __launch_bounds__(kIndepThreads) void k_indep(const PersistArgs args)
     const int nt = blockDim.x;
     const int JB = p.jb, JBP = p.jbp, ncg = p.jbp >> 3;
 
-    load_block(p, S, a.W + (size_t)g * p.n_in_pad * JB, a.theta, g, tid, nt);
-    __syncthreads();
-    if (tid < 32) S.th[tid] = theta_offset(p, S.th64[tid]);
+    // the block as planes (in the weight region, which holds at least
+    // (n_in_pad + 1) x JBP floats) and the thresholds (the weights of a
+    // network that does not learn carry no pending normalisation scale)
+    float4 *planes = reinterpret_cast<float4 *>(S.W);
+    load_planes(p, planes, a.W + (size_t)g * p.n_in_pad * JB, tid, nt);
+    if (tid < 32) {
+        const int jt = g * JB + tid;
+        S.th[tid] = theta_offset(p, (tid < JB && jt < p.n_exc) ? a.theta[jt] : 0.0);
+    }
     __syncthreads();
     // (no barrier follows: threads without a task may leave)
     const int q = tid + nt * (int)blockIdx.y;
@@ -64,6 +128,8 @@ __global__ __launch_bounds__(kIndepThreads) void k_indep(const PersistArgs args)
     float ve[8], vi[8];
     uint32_t rw[4];
     load_task_state(p, S, a, n0, b, c0, ve, vi, rw);
+    const float4 *pa = planes + (size_t)(c0 >> 2) * (p.n_in_pad + 1);
+    const float4 *pb = pa + (p.n_in_pad + 1);
 
     // the step's list length and first entries are fetched a step ahead
     uint32_t cnt = ch.steps > 0 ? ch.cin[b] : 0u;
@@ -81,9 +147,10 @@ __global__ __launch_bounds__(kIndepThreads) void k_indep(const PersistArgs args)
             for (int w = 0; w < kListHead; ++w) h_nx[w] = make_uint4(0u, 0u, 0u, 0u);
         }
         float acc[8];
-        gather_pre<kListHead>(ch.lin + ((size_t)k * p.B + b) * p.n_in_pad, (int)cnt, h, S.W, p.ls, c0, p.n_in_pad,
-                              RED_SUM, acc, PREC);
-        neuron_task(p, S, a.o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, 0u, ve, vi, rw);
+        gather_planes<kListHead>(ch.lin + ((size_t)k * p.B + b) * p.n_in_pad, (int)cnt, h, pa, pb, p.n_in_pad,
+                                 acc, PREC);
+        // (scale 1: the sums enter unscaled, as acc * 1 would)
+        neuron_task(p, S, a.o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, 0u, ve, vi, rw, true);
         cnt = cnt_nx;
 #pragma unroll
         for (int w = 0; w < kListHead; ++w) h[w] = h_nx[w];

@@ -256,6 +256,9 @@ __device__ __forceinline__ void write_outputs8(const PP &p, const Outs &o, int k
 __global__ void k_encode(Params p, const uint8_t *img, const uint64_t *ids, const uint32_t *thr_lut,
                          const uint32_t *tl, uint64_t tbase, const uint32_t *forced, uint32_t *bits,
                          uint32_t *bitsT, uint32_t *raster_in, int raster_k0);
+__global__ void k_encode_lists(Params p, const uint8_t *img, const uint64_t *ids, const uint32_t *thr_lut,
+                               const uint32_t *tl, uint64_t tbase, const uint32_t *forced, uint32_t *bits,
+                               uint16_t *lin, uint32_t *cin, uint32_t *raster_in, int raster_k0);
 __global__ void k_xpre(Params p, const uint32_t *bits_t, const float *xprev, float *xcur);
 __global__ void k_contract(Params p, const float *W, const uint32_t *bits_t, float *I);
 __global__ void k_neuron(Params p, const float *I, const double *theta, const uint32_t *Cprev, uint32_t *Ccur,

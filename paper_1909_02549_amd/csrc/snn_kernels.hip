@@ -22,8 +22,9 @@ namespace snn {
 // Counter (i / 8, t, id, 0), key (seed, 0); the four 64-bit outputs give eight
 // 32-bit uniforms, low half first; input i spikes when its uniform is below
 // the rate threshold thr[pixel] (thr / 2^32 = rate * dt).
-// One 64-lane wave encodes one 32-input word for 64 consecutive samples and
-// transposes the 32x64 bit tile with ballots for the per-input layout.
+// One 64-lane wave encodes one 32-input word for 64 consecutive samples and,
+// if bitsT is given (learning runs), transposes the 32x64 bit tile with
+// ballots for the per-input layout.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_encode(Params p, const uint8_t *__restrict__ img,
                                                const uint64_t *__restrict__ ids,
@@ -66,6 +67,8 @@ __global__ __launch_bounds__(64) void k_encode(Params p, const uint8_t *__restri
         bits[(size_t)k * p.bits_stride + (size_t)b * p.in_words + w] = word;
         if (raster_in) raster_in[((size_t)(raster_k0 + k) * p.B + b) * p.in_words + w] = word;
     }
+    // (the per-input layout feeds the plasticity only)
+    if (!bitsT) return;
     uint64_t mine = 0;
 #pragma unroll
     for (int e = 0; e < 32; ++e) {
@@ -77,6 +80,82 @@ __global__ __launch_bounds__(64) void k_encode(Params p, const uint8_t *__restri
         bitsT[base] = (uint32_t)mine;
         if (2 * (int)blockIdx.x + 1 < p.bwords) bitsT[base + 1] = (uint32_t)(mine >> 32);
     }
+}
+
+// Encoder of the runs that need no transposed input spikes (no learning):
+// the same draws as k_encode (input i: counter (i / 8, t, id, 0), uniform
+// i mod 8 of the block), and besides the per-sample words it writes each
+// sample's input spike list (increasing i) and its length, which the
+// column-block kernels walk.  One 64-lane wave per (sample, step); a lane
+// draws 16 consecutive inputs (two generator calls), so one pass covers
+// 1024 inputs; an exclusive scan of the lanes' spike counts places each
+// lane's entries in the list.  grid (ceil(B / 4), steps), 256 threads.
+__global__ __launch_bounds__(256) void k_encode_lists(Params p, const uint8_t *__restrict__ img,
+                                                      const uint64_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ thr_lut,
+                                                      const uint32_t *__restrict__ tl, uint64_t tbase,
+                                                      const uint32_t *__restrict__ forced,
+                                                      uint32_t *__restrict__ bits, uint16_t *__restrict__ lin,
+                                                      uint32_t *__restrict__ cin, uint32_t *__restrict__ raster_in,
+                                                      int raster_k0)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.y;
+    if (b >= p.B) return;  // (whole waves: no barrier below)
+    const uint64_t t = tbase + (uint64_t)k + (tl ? (uint64_t)tl[b] : 0ull);
+    const uint64_t id = forced ? 0ull : ids[b];
+    uint16_t *out = lin + ((size_t)k * p.B + b) * p.n_in_pad;
+    uint32_t base = 0;
+    for (int i_pass = 0; i_pass < p.n_in; i_pass += 1024) {
+        const int i0 = i_pass + 16 * lane;
+        uint32_t m = 0;
+        if (i0 < p.n_in) {
+            if (forced) {
+                m = forced[((size_t)k * p.B + b) * p.in_words + (i0 >> 5)] >> (i0 & 16);
+            } else {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int ib = i0 + 8 * h;
+                    if (ib >= p.n_in) break;
+                    uint64_t r[4];
+                    philox4x64_10((uint64_t)(ib >> 3), t, id, 0ull, p.seed, 0ull, r);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int i = ib + e;
+                        if (i < p.n_in) {
+                            const uint32_t u = (e & 1) ? (uint32_t)(r[e >> 1] >> 32) : (uint32_t)r[e >> 1];
+                            const uint32_t thr =
+                                p.uniform_rate ? p.thr_uniform : thr_lut[img[(size_t)b * p.n_in + i]];
+                            m |= (uint32_t)(u < thr) << (8 * h + e);
+                        }
+                    }
+                }
+            }
+            const int valid = p.n_in - i0;
+            m &= valid >= 16 ? 0xFFFFu : (1u << valid) - 1u;
+        }
+        // the 32-input words: lanes 2w and 2w + 1 hold its halves
+        const uint32_t hi = __shfl_down(m, 1, 64);
+        const int w = (i_pass >> 5) + (lane >> 1);
+        if (!(lane & 1) && w < p.in_words) {
+            const uint32_t word = m | (hi << 16);
+            bits[(size_t)k * p.bits_stride + (size_t)b * p.in_words + w] = word;
+            if (raster_in) raster_in[((size_t)(raster_k0 + k) * p.B + b) * p.in_words + w] = word;
+        }
+        // exclusive scan of the lanes' spike counts
+        const uint32_t c = (uint32_t)__builtin_popcount(m);
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        uint32_t pos = base + incl - c;
+        for (uint32_t mm = m; mm; mm &= mm - 1u) out[pos++] = (uint16_t)(i0 + __builtin_ctz(mm));
+        base += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) cin[(size_t)k * p.B + b] = base;
 }
 
 // Presynaptic traces of one step: x <- lam * x, then 1 (or x + 1) on a spike.

@@ -643,7 +643,7 @@ snn_status snn_net::encode_chunk(const uint8_t *img, const uint64_t *ids, const 
 {
     dim3 grid((unsigned)((p.B + 63) / 64), (unsigned)p.in_words, (unsigned)steps);
     SNN_LAUNCH("encode", k_encode, grid, dim3(64), 0, p, img, ids, (const uint32_t *)thr_lut, tl, tbase, forced,
-               bits, bitsT, raster_in, raster_k0);
+               bits, p.learn ? bitsT : nullptr, raster_in, raster_k0);
     HIP_TRY(hipGetLastError());
     return SNN_OK;
 }
@@ -1099,13 +1099,25 @@ snn_status snn_net::run_steps(int path, const uint8_t *images, const uint64_t *i
         const bool more = k0 + (uint32_t)steps < T;
         const int enc_steps = steps + (more ? 1 : 0);
         const uint32_t *fc = forced ? forced + (size_t)k0 * p.B * p.in_words : nullptr;
-        snn_status st = tl ? encode_chunk(images, ids, tl, k0, enc_steps, fc, o.raster_in, (int)k0)
-                           : encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
-        if (st != SNN_OK) return st;
-        if (path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT) {
-            const int nq = std::max(p.B, p.learn ? p.n_in_pad : 0);
-            SNN_LAUNCH("lists", k_lists, dim3((unsigned)((nq + 255) / 256), (unsigned)enc_steps), dim3(256), 0, p,
-                       (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, p.learn);
+        const bool col_block = path == SNN_PATH_FUSED || path == SNN_PATH_PERSISTENT;
+        snn_status st = SNN_OK;
+        if (col_block && !p.learn) {
+            // no plasticity: the encoder writes the per-sample spike lists
+            // itself (no transposed spikes, no list kernel)
+            SNN_LAUNCH("encode", k_encode_lists, dim3((unsigned)((p.B + 3) / 4), (unsigned)enc_steps), dim3(256), 0,
+                       p, images, ids, (const uint32_t *)thr_lut, tl, tl ? (uint64_t)k0 : tloc, fc, bits, lin, cin,
+                       o.raster_in, (int)k0);
+            HIP_TRY(hipGetLastError());
+        } else {
+            st = tl ? encode_chunk(images, ids, tl, k0, enc_steps, fc, o.raster_in, (int)k0)
+                    : encode_chunk(images, ids, nullptr, tloc, enc_steps, fc, o.raster_in, (int)k0);
+            if (st != SNN_OK) return st;
+        }
+        if (col_block) {
+            if (p.learn)
+                SNN_LAUNCH("lists", k_lists, dim3((unsigned)((std::max(p.B, p.n_in_pad) + 255) / 256),
+                                                  (unsigned)enc_steps),
+                           dim3(256), 0, p, (const uint32_t *)bits, (const uint32_t *)bitsT, lin, cin, lt, ct, 1);
             // (the independent-task chunk kernel takes no work order)
             if (!(path == SNN_PATH_PERSISTENT && indep()))
                 SNN_LAUNCH("order", k_order, dim3((unsigned)enc_steps), dim3(kOrderThreads), 0, p,
