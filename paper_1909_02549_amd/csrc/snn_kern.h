@@ -12,6 +12,19 @@ __host__ __device__ constexpr size_t align16(size_t n) { return (n + 15) & ~(siz
 // Philox4x64-10: ten rounds; per round two 64x64->128-bit products of the
 // counter words 0 and 2 with the round multipliers, mixed with words 1 and 3
 // and the key, the key advanced by the two Weyl increments between rounds.
+// Full 64 x 64 -> 128-bit product a * b as (hi, lo), from four 32 x 32 ->
+// 64-bit multiply-adds (schoolbook on 32-bit halves, each partial sum below
+// 2^64), where separate high and low halves would take six multiplies.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t t = (uint64_t)a0 * b0;
+    const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+    const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+    lo = (v << 32) | (uint32_t)t;
+    hi = (uint64_t)a1 * b1 + (u >> 32) + (v >> 32);
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                               uint64_t k0, uint64_t k1, uint64_t out[4])
 {
@@ -23,8 +36,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
             k0 += W0;
             k1 += W1;
         }
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, c0, hi0, lo0);
+        mulhilo64(M1, c2, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
