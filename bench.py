@@ -475,11 +475,15 @@ def conversion_run(runs: int = 200, warmup: int = 10, oracle: bool = True) -> di
     return res
 
 
-def sweep(name: str, trials: int) -> dict:
+SCALE_PATHS = ("plain", "plain+graph", "mfma", "mfma+graph", "fused", "fused+graph", "persistent")
+
+
+def sweep(name: str, trials: int, batches=None, paths=None) -> dict:
     """Throughput sweeps (not part of the default run):
     scale  1000 uniform 20 Hz inputs -> 1000 LIF, no learning, T=1000, over
            B = 1 .. 4096: per-step launches with and without graph replay,
-           the matrix-core route, the fused and the persistent kernel;
+           the matrix-core route, the fused and the persistent kernel
+           (`batches` and `paths`, entries of SCALE_PATHS, select a part);
     dc400  784 -> 400/400, T=250, STDP on, over B = 16 .. 1024, each batch
            reduction and operand precision on the autotuned path;
     serve  the serving workload at 2000, 5000, 10000 and 20000 requests/s
@@ -525,10 +529,10 @@ def sweep(name: str, trials: int) -> dict:
         return r
 
     if name == "scale":
-        for B in (1, 8, 64, 512, 4096):
-            for path, graphs in (("plain", False), ("plain", True), ("mfma", False), ("mfma", True),
-                                 ("fused", False), ("fused", True), ("persistent", False)):
-                rows.append(one(B, path, graphs))
+        for B in batches or (1, 8, 64, 512, 4096):
+            for entry in paths or SCALE_PATHS:
+                path, _, g = entry.partition("+")
+                rows.append(one(B, path, g == "graph"))
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     else:
         for B in (16, 64, 256, 1024):
@@ -558,6 +562,9 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and GEMM peak measurements")
     ap.add_argument("--conversion-only", action="store_true",
                     help="print only the converted IF network's measurement")
+    ap.add_argument("--batches", default=None, help="scale sweep: comma-separated batch sizes")
+    ap.add_argument("--sweep-paths", default=None,
+                    help="scale sweep: comma-separated entries of " + ",".join(SCALE_PATHS))
     ap.add_argument("--sweep", choices=["scale", "dc400", "serve"], default=None,
                     help="print a throughput sweep instead of the benchmark line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -569,7 +576,11 @@ def main():
         sys.exit(2)
 
     if args.sweep:
-        print(json.dumps({"sweep": sweep(args.sweep, args.steps)}), flush=True)
+        batches = [int(x) for x in args.batches.split(",")] if args.batches else None
+        paths = args.sweep_paths.split(",") if args.sweep_paths else None
+        if paths and any(x not in SCALE_PATHS for x in paths):
+            ap.error("--sweep-paths entries must be among " + ",".join(SCALE_PATHS))
+        print(json.dumps({"sweep": sweep(args.sweep, args.steps, batches, paths)}), flush=True)
         return
     if args.conversion_only:
         print(json.dumps({"conversion": conversion_run(oracle=not args.no_cpu)}), flush=True)

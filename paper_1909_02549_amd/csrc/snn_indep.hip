@@ -131,29 +131,55 @@ __global__ __launch_bounds__(kIndepThreads) void k_indep(const PersistArgs args)
     const float4 *pa = planes + (size_t)(c0 >> 2) * (p.n_in_pad + 1);
     const float4 *pb = pa + (p.n_in_pad + 1);
 
-    // the step's list length and first entries are fetched a step ahead
-    uint32_t cnt = ch.steps > 0 ? ch.cin[b] : 0u;
-    uint4 h[kListHead];
-    load_heads<kListHead>(ch.lin + (size_t)b * p.n_in_pad, h);
-    for (int k = 0; k < ch.steps; ++k) {
-        uint32_t cnt_nx = 0u;
-        uint4 h_nx[kListHead];
-        if (k + 1 < ch.steps) {
-            const size_t r = (size_t)(k + 1) * p.B + b;
-            cnt_nx = ch.cin[r];
-            load_heads<kListHead>(ch.lin + r * p.n_in_pad, h_nx);
-        } else {
-#pragma unroll
-            for (int w = 0; w < kListHead; ++w) h_nx[w] = make_uint4(0u, 0u, 0u, 0u);
-        }
+    // Spike counts accumulate in registers (16 bits per neuron, a chunk has
+    // at most 512 steps) and reach memory once per chunk: on gfx950 one
+    // in-order counter tracks a wave's loads, stores and atomics, so a count
+    // atomic issued in step t would hold up the wait for step t + 1's list
+    // data.  The other outputs (rasters, voltages) are written per step.
+    Outs o = a.o;
+    o.counts = nullptr;
+    const uint32_t until = a.o.until ? a.o.until[b] : 0xFFFFFFFFu;
+    uint32_t cnt16[4] = {0u, 0u, 0u, 0u};
+
+    // each step's list length and first entries are fetched a step ahead,
+    // into two slots that alternate between the two halves of the unrolled
+    // loop (no register copies, which would wait for the load just issued)
+    uint32_t c0s = 0u, c1s = 0u;
+    uint4 h0[kListHead], h1[kListHead];
+    // (past the chunk's last step the last step's list is read again: the
+    // loads stay unconditional, so the wait before a slot's first use counts
+    // exactly the loads issued after it)
+    auto fetch = [&](int k, uint32_t &c, uint4 *h) {
+        const size_t r = (size_t)min(k, max(ch.steps - 1, 0)) * p.B + b;
+        c = ch.cin[r];
+        load_heads<kListHead>(ch.lin + r * p.n_in_pad, h);
+    };
+    auto step = [&](int k, uint32_t c, const uint4 *h) {
         float acc[8];
-        gather_planes<kListHead>(ch.lin + ((size_t)k * p.B + b) * p.n_in_pad, (int)cnt, h, pa, pb, p.n_in_pad,
-                                 acc, PREC);
+        gather_planes<kListHead>(ch.lin + ((size_t)k * p.B + b) * p.n_in_pad, (int)c, h, pa, pb, p.n_in_pad, acc,
+                                 PREC);
         // (scale 1: the sums enter unscaled, as acc * 1 would)
-        neuron_task(p, S, a.o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, 0u, ve, vi, rw, true);
-        cnt = cnt_nx;
+        const uint32_t se = neuron_task(p, S, o, ch.k0 + k, b, c0, g * JB + c0, nv, acc, 0u, ve, vi, rw, true);
+        if ((uint32_t)(ch.k0 + k) < until) {
 #pragma unroll
-        for (int w = 0; w < kListHead; ++w) h[w] = h_nx[w];
+            for (int e = 0; e < 8; ++e) cnt16[e >> 1] += ((se >> e) & 1u) << (16 * (e & 1));
+        }
+    };
+    fetch(0, c0s, h0);
+    for (int k = 0; k < ch.steps; k += 2) {
+        fetch(k + 1, c1s, h1);
+        step(k, c0s, h0);
+        if (k + 1 >= ch.steps) break;
+        fetch(k + 2, c0s, h0);
+        step(k + 1, c1s, h1);
+    }
+    if (a.o.counts) {
+        uint32_t *cnt = a.o.counts + (size_t)b * p.n_exc + g * JB + c0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t v = (cnt16[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            if (v) (void)__hip_atomic_fetch_add(cnt + e, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     store_task_state(p, S, a, n0, b, c0, ve, vi, rw);
 }
