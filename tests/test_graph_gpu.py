@@ -56,23 +56,27 @@ def test_graph_replays_equal_launches(torch_cuda, path):
     e_net.close()
 
 
-def test_graph_with_changing_batch_and_frozen_weights(torch_cuda):
+@pytest.mark.parametrize("path,T", [("plain", 40), ("fused", 40), ("persistent", 40), ("persistent", 530)])
+def test_graph_with_changing_batch_and_frozen_weights(torch_cuda, path, T):
     """No learning: replays of the same trial repeat exactly; a different
-    batch size captures a new graph and still equals the launched kernels."""
+    batch size captures a new graph and still equals the launched kernels.
+    Without an inhibitory layer the persistent path runs the barrier-free
+    chunk kernel (530 steps: two encoder chunks inside one graph)."""
     torch = torch_cuda
     from paper_1909_02549_amd.snn import Net
     cfg = inputs.scaling_config(n_in=300, n_out=200)
     W = inputs.normal_weights(300, 200, 0.5, 0.2, 3)
-    g_net = Net(cfg, max_batch=64, path="plain")
-    e_net = Net(cfg, max_batch=64, path="plain")
+    g_net = Net(cfg, max_batch=64, path=path)
+    e_net = Net(cfg, max_batch=64, path=path)
     g_net.snn_set_weights(W)
     e_net.snn_set_weights(W)
     g_net.snn_set_graphs(True)
     first = None
     for B in (64, 16, 64, 16):
         ids_d = torch.from_numpy(sample_ids(B, 5).astype(np.int64)).cuda()
-        a = trial_outputs(torch, g_net, None, ids_d, 40)
-        b = trial_outputs(torch, e_net, None, ids_d, 40)
+        a = trial_outputs(torch, g_net, None, ids_d, T)
+        b = trial_outputs(torch, e_net, None, ids_d, T)
+        assert g_net.snn_last_path() == e_net.snn_last_path() == path
         for k in ("exc", "v_exc", "counts"):
             assert np.array_equal(a[k], b[k]), f"B={B}: {k} differs"
         if B == 64:
