@@ -145,3 +145,21 @@ def test_serving_alone_equals_mix(torch_cuda, oracle_mod):
         ref = oracle_mod.OracleNet(cfg, W.astype(np.float64)).run(imgs[k:k + 1], np.array([ids[k]], np.uint64),
                                                                   Ts[k], record=("counts",))
         assert (ref["counts"][0] == alone[k]).mean() >= 0.99
+
+
+@pytest.mark.parametrize("path", ["persistent", "fused"])
+def test_forced_input_spikes(torch_cuda, oracle_mod, path):
+    """Caller-given input spikes (snn_run_spikes) on a network without
+    learning: the encoder copies the words and builds the lists from them
+    (inputs 0 .. 69, so the last 16-input group of the lanes is ragged and
+    one 32-input word is half empty)."""
+    cfg = inputs.scaling_config(n_in=70, n_out=40)
+    W = inputs.normal_weights(70, 40, 0.8, 0.3, 4)
+    rng = np.random.default_rng(12)
+    B, T = 21, 90
+    forced = (rng.random((B, T, 70)) < 0.06).astype(np.uint8)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, sample_ids(B, 40), T, path=path, forced=forced,
+                      record=REC)
+    assert g["path"] == path
+    assert ref["exc"].sum() > 20
+    check_parity(g, ref, learn=False)
