@@ -109,6 +109,8 @@ __global__ void k_persist(const PersistArgs args);
 size_t indep_lds_bytes(const Params &p);
 template <int PREC>
 __global__ void k_indep(const PersistArgs args);
+template <int PREC, int NC>
+__global__ void k_indep_narrow(const PersistArgs args);
 __global__ void k_lists(Params p, const uint32_t *bits, const uint32_t *bitsT, uint16_t *lin, uint32_t *cin,
                         uint16_t *lt, uint32_t *ct, int with_t);
 constexpr int kOrderThreads = 1024;

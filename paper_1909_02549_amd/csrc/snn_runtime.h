@@ -123,7 +123,7 @@ struct snn_net {
     // no learning and no inhibitory layer: the persistent path's chunk
     // kernel needs no grid barrier (k_indep)
     bool indep() const { return !p.learn && !p.has_inh; }
-    size_t indep_attr_bytes[3] = {};
+    size_t indep_attr_bytes[3][4] = {};  // per form and columns per lane (1, 2, 4, 8)
     snn_status persist_chunk(int steps, bool has_next, int k0, const snn::Outs &o);
     snn_status check_device_error();
     snn_status run(const uint8_t *images, const uint64_t *ids, const uint32_t *forced, uint32_t batch, uint32_t T,

@@ -12,7 +12,9 @@ for bit; against the oracle it meets the usual parity bars.
 Shapes: ragged layers (150 columns: the last 8-column group holds 6), column
 blocks of 8, 13 and 32 columns, batches that leave the last workgroup of
 each column block partly empty, runs that cross an encoder chunk (512
-steps), continuing runs, the reduced operand forms, and serving.
+steps), continuing runs, the reduced operand forms, serving, and each
+number of columns per lane (small batches spread a task over several
+lanes).
 """
 import numpy as np
 import pytest
@@ -162,4 +164,26 @@ def test_forced_input_spikes(torch_cuda, oracle_mod, path):
                       record=REC)
     assert g["path"] == path
     assert ref["exc"].sum() > 20
+    check_parity(g, ref, learn=False)
+
+
+@pytest.mark.parametrize("cols", [1, 2, 4, 8])
+@pytest.mark.parametrize("jb", [8, 13])
+def test_columns_per_lane_bit_exact(torch_cuda, oracle_mod, monkeypatch, cols, jb):
+    """Small batches spread each 8-column task over 8 / cols lanes (the
+    library picks the width from the grid size; SNN_INDEP_COLS fixes it).
+    Every width gives the fused kernel's outputs bit for bit, in every operand
+    form, and meets the oracle's bars."""
+    monkeypatch.setenv("SNN_JB", str(jb))
+    monkeypatch.setenv("SNN_INDEP_COLS", str(cols))
+    cfg, W = scaling_net()
+    ids = sample_ids(37, 130)
+    for precision in ("fp32", "bf16", "fp8"):
+        gp, used_p = run_path(torch_cuda, cfg, W, ids, 70, "persistent", precision)
+        gf, used_f = run_path(torch_cuda, cfg, W, ids, 70, "fused", precision)
+        assert (used_p, used_f) == ("persistent", "fused")
+        for key in REC:
+            assert np.array_equal(gp[key], gf[key]), (precision, key)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, ids, 70, path="persistent", record=REC)
+    assert ref["exc"].sum() > 50
     check_parity(g, ref, learn=False)
