@@ -98,3 +98,19 @@ def test_single_gpu_guard():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_sweep_selection_flags():
+    """--sweep-paths must name entries of the scaling sweep; a bad entry is
+    refused before anything runs (no GPU needed)."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sweep", "scale", "--sweep-paths",
+                        "persistent,bogus"], capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "--sweep-paths entries must be among" in r.stderr
+
+
+def test_scale_sweep_entries(bench):
+    assert "persistent" in bench.SCALE_PATHS and "fused+graph" in bench.SCALE_PATHS
+    for e in bench.SCALE_PATHS:
+        path, _, g = e.partition("+")
+        assert path in ("plain", "mfma", "fused", "persistent") and g in ("", "graph")
