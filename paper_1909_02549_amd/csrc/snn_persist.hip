@@ -126,6 +126,33 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
     const NeuronK nk = neuron_consts_v(p);
     Outs outs = a.o;
     if (RK != RK_SERVE) outs.until = nullptr;  // (read by the serving kind only)
+
+    // the feed-forward sums of task u at step k (input list of step k, the
+    // block in LDS)
+    auto gather_task = [&](int k, int u, float *acc) {
+        const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
+        if (PREC == PREC_FP32) {
+            gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
+        } else {
+            // the reduced forms round the normalised weight w * scale
+            const float4 slo = *reinterpret_cast<const float4 *>(S.scalef + tc0[u]);
+            const float4 shi = *reinterpret_cast<const float4 *>(S.scalef + tc0[u] + 4);
+            gather_pre<NHP, true>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC,
+                                  slo, shi);
+        }
+    };
+    // The frozen kind gathers step t + 1's sums between its arrival and its
+    // wait: they need only the block, which does not change, and the input
+    // lists, so their time hides in the barrier's round trips (which set the
+    // step time of small batches).  The learning kinds' block changes in the
+    // plasticity that follows the arrival.
+    constexpr bool early = RK == RK_SERVE;
+    float acc_e[early ? kPersistTasks : 1][8];
+    if (early && ch.steps > 0) {
+#pragma unroll
+        for (int u = 0; u < kPersistTasks; ++u)
+            if (has_task[u]) gather_task(0, u, acc_e[u]);
+    }
     for (int k = 0; k < ch.steps; ++k) {
         const int mod = (ch.mod0 + k) % 3;
         const float *xpre = ch.xpre + (size_t)mod * p.Bs * p.n_in_pad;
@@ -144,15 +171,11 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
         for (int u = 0; u < kPersistTasks; ++u) {
             if (!has_task[u]) continue;
             float acc[8];
-            const uint16_t *row = ch.lin + ((size_t)k * p.B + tb[u]) * p.n_in_pad;
-            if (PREC == PREC_FP32) {
-                gather_pre<NHP>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc, PREC);
+            if (early) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] = acc_e[early ? u : 0][c];
             } else {
-                // the reduced forms round the normalised weight w * scale
-                const float4 slo = *reinterpret_cast<const float4 *>(S.scalef + tc0[u]);
-                const float4 shi = *reinterpret_cast<const float4 *>(S.scalef + tc0[u] + 4);
-                gather_pre<NHP, true>(row, (int)hin_cnt[u], hin[u], S.W, p.ls, tc0[u], p.n_in_pad, RED_SUM, acc,
-                                      PREC, slo, shi);
+                gather_task(k, u, acc);
             }
             neuron_task(nk, S, outs, ch.k0 + k, tb[u], tc0[u], g * JB + tc0[u], tnv[u], acc, cp[u], ve[u], vi[u],
                         rw[u], PREC != PREC_FP32);
@@ -175,6 +198,11 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PersistArgs a
                 if (!has_task[u]) continue;
                 hin_cnt[u] = ch.cin[(size_t)(k + 1) * p.B + tb[u]];
                 load_heads<NHP>(ch.lin + ((size_t)(k + 1) * p.B + tb[u]) * p.n_in_pad, hin[u]);
+            }
+            if (early) {
+#pragma unroll
+                for (int u = 0; u < kPersistTasks; ++u)
+                    if (has_task[u]) gather_task(k + 1, u, acc_e[early ? u : 0]);
             }
         }
     }
