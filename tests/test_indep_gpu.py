@@ -187,3 +187,22 @@ def test_columns_per_lane_bit_exact(torch_cuda, oracle_mod, monkeypatch, cols, j
     g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, ids, 70, path="persistent", record=REC)
     assert ref["exc"].sum() > 50
     check_parity(g, ref, learn=False)
+
+
+@pytest.mark.parametrize("cols", [1, 2, 4, 8])
+def test_tiny_network(torch_cuda, oracle_mod, monkeypatch, cols):
+    """10 inputs (one 32-input word, mostly padding) -> 3 neurons (one
+    4-column plane, partly padding), B = 5: every width against the oracle
+    and bit for bit against the fused kernel."""
+    monkeypatch.setenv("SNN_INDEP_COLS", str(cols))
+    cfg = inputs.scaling_config(n_in=10, n_out=3, rate_hz=150.0)
+    W = inputs.normal_weights(10, 3, 4.0, 1.0, 8)
+    ids = sample_ids(5, 300)
+    g, ref = run_both(torch_cuda, oracle_mod, cfg, W, None, ids, 80, path="persistent", record=REC)
+    assert g["path"] == "persistent"
+    assert ref["exc"].sum() > 10
+    check_parity(g, ref, learn=False)
+    gf, _ = run_path(torch_cuda, cfg, W, ids, 80, "fused")
+    gp, _ = run_path(torch_cuda, cfg, W, ids, 80, "persistent")
+    for key in REC:
+        assert np.array_equal(gp[key], gf[key]), key
