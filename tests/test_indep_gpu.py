@@ -206,3 +206,24 @@ def test_tiny_network(torch_cuda, oracle_mod, monkeypatch, cols):
     gp, _ = run_path(torch_cuda, cfg, W, ids, 80, "persistent")
     for key in REC:
         assert np.array_equal(gp[key], gf[key]), key
+
+
+def test_very_large_batch(torch_cuda, oracle_mod):
+    """B = 20 000 on the 1000 -> 1000 scaling network (twice the largest
+    batch of the scaling sweep; the grid has 125 x 313 workgroups): sampled
+    samples against the oracle, every row against the fused kernel."""
+    wl = inputs.workload("scale")
+    cfg = wl["cfg"]
+    W = inputs.normal_weights(1000, 1000, wl["wmean"], wl["wstd"], 0)
+    B, T = 20000, 24
+    ids = sample_ids(B, 9)
+    rec = ("exc", "counts")
+    gp, used = run_path(torch_cuda, cfg, W, ids, T, "persistent", record=rec)
+    gf, _ = run_path(torch_cuda, cfg, W, ids, T, "fused", record=rec)
+    assert used == "persistent"
+    for key in rec:
+        assert np.array_equal(gp[key], gf[key]), key
+    sel = np.array([0, 1, 9999, 19998, 19999])
+    ref = oracle_mod.OracleNet(cfg, W.astype(np.float64)).run(None, ids[sel], T, record=("counts",))
+    assert ref["counts"].sum() > 0
+    assert (gp["counts"][sel] == ref["counts"]).mean() >= 0.999
